@@ -1,0 +1,237 @@
+/*
+ * expri -- exponential Rosenbrock-Euler transient solver with the invert-Krylov
+ * matrix-exponential-vector product, for gfx950 (MI355X).
+ *
+ * Method: Zhuang, Yu, Kang, Wang, Cheng, "An Algorithmic Framework for
+ * Efficient Large-Scale Circuit Simulation Using Exponential Integrators",
+ * DAC 2015.  The circuit is the DAE of the paper's background section,
+ *     C x' = -G_lin x - I_dev(x) + B u(t),
+ * with C symmetric positive semi-definite (it may be singular), G_lin the
+ * linear conductances, I_dev the MOSFET currents (level-1 model) and u
+ * piecewise linear.  Each step (Algorithm 2) linearises at x_k, factorises
+ * only G_k = G_lin + dI_dev/dx (one LU per accepted step, reused when the step
+ * is reduced), evaluates the phi-function products on the invert Krylov
+ * subspace K_m(-G_k^{-1} C, v) (Algorithm 1, MEVP_IKS) and accepts the step
+ * when the local nonlinear error estimate (section "Local Nonlinear Error
+ * Estimator") is within E_rr.
+ *
+ * Conventions for every entry point
+ *   - Units are SI (V, A, S, F, s).  Node ids are 0-based; EXPRI_GND and
+ *     EXPRI_VDD denote the ideal rails.
+ *   - Host input arrays are copied during the call; the caller may free them
+ *     on return.  Arguments documented as "device" are device pointers that the
+ *     caller owns (e.g. PyTorch tensors) and that must stay valid for the call.
+ *   - Work is queued on the HIP stream given to expri_setup; every entry point
+ *     that produces results synchronises that stream before returning.
+ *   - Every call returns an expri_status; nothing throws, aborts or prints.
+ *     expri_last_error() gives a message for the last failure.  After an error
+ *     in a transient call the caller's state vectors hold the last accepted
+ *     state.
+ *   - A batch: expri_setup takes n_inst circuits.  Instances with identical
+ *     sparsity share their symbolic analysis; each instance is integrated
+ *     independently (its own time grid, status and trace).  Per-instance
+ *     device vectors are passed as a host array of n_inst device pointers.
+ */
+#ifndef EXPRI_H
+#define EXPRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXPRI_GND (-1)
+#define EXPRI_VDD (-2)
+
+typedef struct expri_ctx expri_ctx;
+
+typedef enum {
+  EXPRI_OK = 0,
+  EXPRI_EINVAL = -1,     /* bad argument or circuit description */
+  EXPRI_ENOMEM = -2,     /* device or host allocation failed */
+  EXPRI_ESINGULAR = -3,  /* |u_ii| <= piv_tol * max_j |G_k(i,j)| in the LU of G_k */
+  EXPRI_EKRYLOV = -4,    /* m_max Arnoldi steps without residual <= eps_krylov */
+  EXPRI_ESTEPMIN = -5,   /* the step fell below h_min */
+  EXPRI_ENONFINITE = -6, /* NaN or Inf in the state or the small exponential */
+  EXPRI_EHIP = -7,       /* a HIP runtime call failed */
+  EXPRI_EPATTERN = -8,   /* instance data inconsistent with its pattern */
+  EXPRI_ENOCONV = -9     /* DC Newton iteration did not converge */
+} expri_status;
+
+/* CSR matrix, 0-based, column indices sorted and unique within a row. */
+typedef struct {
+  int32_t n_rows, n_cols, nnz;
+  const int32_t *rowptr; /* n_rows + 1 */
+  const int32_t *colidx; /* nnz */
+  const double *val;     /* nnz */
+} expri_csr;
+
+/* Level-1 (Shichman-Hodges) MOSFETs with channel-length modulation:
+ * triode I = K (V_ov V_ds - V_ds^2/2)(1 + lam V_ds), saturation
+ * I = K V_ov^2 / 2 (1 + lam V_ds), K = kp * wl; PMOS is the mirror image. */
+typedef struct {
+  int32_t n;
+  const int8_t *type;                /* +1 NMOS, -1 PMOS */
+  const int32_t *d, *g, *s;          /* terminals: node id, EXPRI_GND or EXPRI_VDD */
+  const double *kp, *wl, *vth, *lam; /* A/V^2, -, V (magnitude), 1/V */
+} expri_mosfets;
+
+/* Piecewise-linear waveform: value v[i] at t[i], linear between corners,
+ * constant outside [t[0], t[npts-1]]; t strictly increasing. */
+typedef struct {
+  int32_t npts;
+  const double *t, *v;
+} expri_pwl;
+
+/* One circuit instance. */
+typedef struct {
+  int32_t n;          /* unknowns (node voltages) */
+  expri_csr G;        /* n x n linear conductance matrix */
+  expri_csr C;        /* n x n capacitance matrix, symmetric PSD */
+  expri_csr B;        /* n x n_src source incidence */
+  expri_mosfets dev;  /* nonlinear devices */
+  int32_t n_src;
+  const expri_pwl *src; /* n_src waveforms, one per column of B */
+  double vdd;         /* value of the EXPRI_VDD rail */
+  double T;           /* end of the transient */
+  int32_t n_probe;    /* nodes recorded in each trace record */
+  const int32_t *probe;
+} expri_circuit;
+
+/* Solver options (Algorithm 2 parameters and the readings documented in the
+ * design notes).  expri_default_opts fills: E_rr = 1e-6 V, eps_krylov =
+ * 0.1 E_rr, alpha = 0.5, beta = 2, grow_if_rejects_lt = 5, h_init = 1e-13 s,
+ * h_min = 1e-18 s, h_max = 0 (meaning T / 20 per instance), m_max = 60,
+ * breakdown = 1e-13, piv_tol = 1e-13, block_size = 0 (automatic),
+ * trace_cap = 4096 records per instance and launch. */
+typedef struct {
+  double E_rr, eps_krylov, alpha, beta, h_init, h_min, h_max, breakdown, piv_tol;
+  int32_t grow_if_rejects_lt, m_max, block_size, trace_cap;
+} expri_opts;
+
+/* Counters of the last transient or DC call of one instance. */
+typedef struct {
+  double t;          /* time reached */
+  int32_t steps;     /* accepted steps (DC: Newton iterations) */
+  int32_t lu_count;  /* numeric factorisations of G_k */
+  int32_t rejects;   /* rejected trials */
+  int32_t arnoldi;   /* Arnoldi iterations (both MEVPs) */
+  int32_t status;    /* expri_status of this instance */
+  /* device time per phase of the step loop (seconds, from the GPU wall
+   * clock): 0 device stamp + LU refactor, 1 right-hand-side solves, 2 Arnoldi
+   * SpMV + triangular solves, 3 modified Gram-Schmidt, 4 Hessenberg
+   * exponential and residual, 5 trial update, re-stamp, error set-up */
+  double phase_s[6];
+} expri_run_info;
+
+/* Trace record layout (doubles): t, h, h_try, m, m_err, rejects, err_inf,
+ * krylov_residual, then the n_probe probed voltages at t. */
+#define EXPRI_REC_FIXED 8
+
+/* Fill o with the defaults listed above. */
+expri_status expri_default_opts(expri_opts *o);
+
+/* Analyse and upload n_inst circuits (host data, copied).  Builds the
+ * symbolic analysis of G_k's pattern (fill-reducing order, L\U pattern, level
+ * schedules, refactor update lists, stamp maps) once per distinct pattern.
+ * hip_stream: the hipStream_t all work is queued on (NULL = default stream).
+ * EINVAL for malformed input; ENOMEM / EHIP on allocation failure. */
+expri_status expri_setup(expri_ctx **ctx, const expri_circuit *ckt, int32_t n_inst,
+                         const expri_opts *o, void *hip_stream);
+
+/* Device workspace the context needs (bytes, 256-byte aligned use). */
+expri_status expri_workspace_size(const expri_ctx *ctx, size_t *bytes);
+
+/* Give the context a caller-owned device workspace of at least
+ * expri_workspace_size bytes (must outlive the context's use).  Without it
+ * the first compute call allocates one.  EINVAL if too small or misaligned. */
+expri_status expri_bind_workspace(expri_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* DC operating point at time t0 (Algorithm 2, x(0) = DC_solution): x[i]
+ * (device, n values each, caller numbering) is the starting guess on entry and
+ * the solution on return.  Newton on B u - G_lin x - I_dev(x) = 0 with the
+ * gate couplings between strongly connected blocks dropped until the update
+ * is below 1e-9 V, then full Newton to 1e-12 V.  ENOCONV / ESINGULAR. */
+expri_status expri_dc(expri_ctx *ctx, double *const *x, double t0);
+
+/* Stamp the devices at x (device vectors) and factorise G_k on the GPU
+ * (Algorithm 2, LU_decompose(G_k)).  The factors stay in the context for
+ * expri_solve / expri_mevp.  ESINGULAR on a small pivot. */
+expri_status expri_factor(expri_ctx *ctx, const double *const *x);
+
+/* y[i] = G_k^{-1} b[i] with the factors of the last expri_factor (device
+ * vectors, caller numbering; y may not alias b). */
+expri_status expri_solve(expri_ctx *ctx, const double *const *b, double *const *y);
+
+/* Algorithm 1 on the factors of the last expri_factor: out[i] =
+ * (I - e^{hJ}) v[i], J = -C^{-1} G_k, from the invert Krylov basis grown
+ * until the residual norm rho_m(h) <= eps.  m[i] and rho[i] (host arrays of
+ * n_inst, may be NULL) receive the basis size and residual.  EKRYLOV. */
+expri_status expri_mevp(expri_ctx *ctx, const double *const *v, double *const *out, double h,
+                        double eps, int32_t *m, double *rho);
+
+/* Adaptive ER transient of every instance from t0 to its T (Algorithm 2 with
+ * step control).  x[i] (device, caller numbering) holds the initial state and
+ * receives the final one.  Each accepted step appends one trace record
+ * (retrieve with expri_trace).  max_steps_per_launch bounds the work of one
+ * kernel launch (<= trace_cap); the call loops until all instances finish. */
+expri_status expri_run(expri_ctx *ctx, double *const *x, double t0, int32_t max_steps_per_launch);
+
+/* Replay: step instance i through the given accepted times t_seq[i][0..
+ * n_steps[i]) (host arrays, increasing, > t0) accepting every first trial;
+ * the error estimate is still computed and recorded.  Used for parity against
+ * a reference time grid. */
+expri_status expri_run_schedule(expri_ctx *ctx, double *const *x, double t0,
+                                const double *const *t_seq, const int32_t *n_steps);
+
+/* One step of size h from (t, x) for every instance (a replay of one step);
+ * info (host array of n_inst, may be NULL) receives the counters. */
+expri_status expri_step(expri_ctx *ctx, double *const *x, double t, double h,
+                        expri_run_info *info);
+
+/* Copy up to cap trace records of instance inst (host buffer of
+ * cap * (EXPRI_REC_FIXED + n_probe) doubles); *n_rec = records available. */
+expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_t cap, int64_t *n_rec);
+
+/* Counters of the last transient / DC call of instance inst. */
+expri_status expri_get_run_info(const expri_ctx *ctx, int32_t inst, expri_run_info *info);
+
+/* Symbolic data of instance inst (host buffers may be NULL to query sizes):
+ * L\U CSR in the internal order (rowptr n+1, col nnz), perm[internal] =
+ * caller node id, level counts of the L and U solves and the multiply-adds of
+ * one refactor. */
+expri_status expri_lu_pattern(const expri_ctx *ctx, int32_t inst, int32_t *rowptr, int32_t *col,
+                              int32_t *perm, int64_t *nnz, int32_t *n_lev, int32_t *n_ulev,
+                              int64_t *flops);
+
+/* L\U values of instance inst after expri_factor (host buffer of nnz). */
+expri_status expri_lu_values(const expri_ctx *ctx, int32_t inst, double *out);
+
+/* Host-only diagnostics of the symbolic analysis (no GPU is touched):
+ * expri_symbolic_create analyses one circuit's pattern; expri_symbolic_array
+ * copies one of its integer arrays by name ("perm", "lu_rowptr", "lu_col",
+ * "lu_diag", "lev_ptr", "lev_rows", "ulev_ptr", "ulev_rows", "row_grp",
+ * "grp_pos", "grp_diag", "grp_ptr", "pair_src", "pair_dst", "lu_gidx",
+ * "jac_ptr", "jac_code", "node_ptr", "node_code", "g_rowptr", "g_col",
+ * "g_src", "c_rowptr", "c_col", "c_src", "b_rowptr", "b_col", "b_src",
+ * "dev_node", "block_of"): up to cap values into out (may be NULL), *len =
+ * full length.  EINVAL for an unknown name. */
+typedef struct expri_symbolic expri_symbolic;
+expri_status expri_symbolic_create(expri_symbolic **sym, const expri_circuit *ckt);
+expri_status expri_symbolic_array(const expri_symbolic *sym, const char *name, int32_t *out, int64_t cap,
+                                  int64_t *len);
+void expri_symbolic_destroy(expri_symbolic *sym);
+
+/* Message of the last failure ("" if none). */
+const char *expri_last_error(const expri_ctx *ctx);
+
+/* Release everything the context owns (not a bound workspace). */
+void expri_destroy(expri_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXPRI_H */

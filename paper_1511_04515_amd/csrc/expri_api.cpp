@@ -1,0 +1,739 @@
+// C-ABI of the ER solver (include/expri.h): context, host-side validation,
+// upload of symbolic data and values, workspace layout and the host loops
+// that drive the gfx950 kernels of engine.hip.
+#include "../../include/expri.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "layout.hpp"
+#include "symbolic.hpp"
+
+namespace expri {
+// launchers (engine.hip)
+size_t lds_bytes(int bs, int R);
+hipError_t set_lds_limits(size_t bytes);
+hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
+                        hipStream_t s);
+hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
+hipError_t launch_run(const InstDesc *d, int n_inst, const Opts &o, int max_steps, int replay, int bs,
+                      int R, hipStream_t s);
+hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R,
+                     hipStream_t s);
+hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, hipStream_t s);
+hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, double *const *y, int bs,
+                        int R, hipStream_t s);
+hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
+                       double *const *out, double h, double eps, int bs, int R, hipStream_t s);
+}  // namespace expri
+
+using namespace expri;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxRunSteps = 4000000;  // accepted steps per instance and call
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Appends arrays into one byte image with 256-byte alignment.
+struct Packer {
+  std::vector<char> img;
+  template <class T>
+  size_t add(const T *p, size_t count) {
+    size_t off = align_up(img.size());
+    img.resize(off + std::max<size_t>(count * sizeof(T), 1), 0);
+    if (count) std::memcpy(img.data() + off, p, count * sizeof(T));
+    return off;
+  }
+  template <class T>
+  size_t add(const std::vector<T> &v) { return add(v.data(), v.size()); }
+};
+
+struct PatternDev {
+  Symbolic sym;
+  size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
+      grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
+      g_rowptr, g_col, c_rowptr, c_col, b_rowptr, b_col, dev_node, perm;
+};
+
+struct Inst {
+  int pat = 0;
+  int32_t n = 0, n_dev = 0, n_src = 0, n_probe = 0, n_bp = 0;
+  double vdd = 1.0, T = 0.0, h_max = 0.0;
+  size_t g_val, c_val, b_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
+  // workspace offsets
+  size_t xk, x1, w, p, z, tmp, e, Ik, devI, devD, devI1, lu, V, Ve, H, He, mat, state, trace;
+  int64_t ldv = 0;
+  std::vector<double> trace_host;
+  expri_run_info info{};
+};
+
+}  // namespace
+
+struct expri_ctx {
+  hipStream_t stream = nullptr;
+  expri_opts opts{};
+  std::vector<PatternDev> pats;
+  std::vector<Inst> inst;
+  char *d_const = nullptr;
+  size_t const_bytes = 0;
+  char *d_ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  InstDesc *d_desc = nullptr;
+  std::vector<InstDesc> h_desc;
+  void **d_ptrs = nullptr;  // 4 * n_inst device pointers
+  int bs = 512, R = 8192;
+  double wall_hz = 1e8;  // GPU wall-clock counter rate
+  std::string err;
+};
+
+namespace {
+
+expri_status fail(expri_ctx *c, expri_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+expri_status hip_fail(expri_ctx *c, hipError_t e, const char *what) {
+  return fail(c, EXPRI_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+Opts kernel_opts(const expri_opts &o) {
+  Opts k{};
+  k.E_rr = o.E_rr;
+  k.eps_K = o.eps_krylov;
+  k.alpha = o.alpha;
+  k.beta = o.beta;
+  k.h_init = o.h_init;
+  k.h_min = o.h_min;
+  k.h_max = o.h_max;
+  k.breakdown = o.breakdown;
+  k.piv_tol = o.piv_tol;
+  k.grow_if_rejects_lt = o.grow_if_rejects_lt;
+  k.m_max = o.m_max;
+  return k;
+}
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// permuted copy of CSR values: out[e'] = val[src[e']]
+std::vector<double> gather(const double *val, const std::vector<int32_t> &src) {
+  std::vector<double> out(src.size());
+  for (size_t e = 0; e < src.size(); ++e) out[e] = val[src[e]];
+  return out;
+}
+
+expri_status validate_circuit(expri_ctx *c, const expri_circuit &k, int idx) {
+  const std::string w = "instance " + std::to_string(idx) + ": ";
+  if (k.n <= 0) return fail(c, EXPRI_EINVAL, w + "n must be positive");
+  auto mat_ok = [&](const expri_csr &m, int32_t r, int32_t cc, const char *nm) -> bool {
+    if (m.n_rows != r || m.n_cols != cc) { c->err = w + nm + ": wrong shape"; return false; }
+    if (!m.rowptr || (m.nnz > 0 && (!m.colidx || !m.val))) { c->err = w + nm + ": null array"; return false; }
+    if (m.rowptr[0] != 0 || m.rowptr[r] != m.nnz) { c->err = w + nm + ": rowptr/nnz mismatch"; return false; }
+    if (!finite_all(m.val, m.nnz)) { c->err = w + nm + ": non-finite value"; return false; }
+    return true;
+  };
+  if (!mat_ok(k.G, k.n, k.n, "G") || !mat_ok(k.C, k.n, k.n, "C") || !mat_ok(k.B, k.n, k.n_src, "B"))
+    return EXPRI_EINVAL;
+  if (k.n_src < 0 || (k.n_src > 0 && !k.src)) return fail(c, EXPRI_EINVAL, w + "bad sources");
+  for (int s = 0; s < k.n_src; ++s) {
+    const expri_pwl &p = k.src[s];
+    if (p.npts < 1 || !p.t || !p.v) return fail(c, EXPRI_EINVAL, w + "empty PWL source");
+    if (!finite_all(p.t, p.npts) || !finite_all(p.v, p.npts))
+      return fail(c, EXPRI_EINVAL, w + "non-finite PWL corner");
+    for (int i = 1; i < p.npts; ++i)
+      if (!(p.t[i] > p.t[i - 1])) return fail(c, EXPRI_EINVAL, w + "PWL times not increasing");
+  }
+  if (k.dev.n < 0 || (k.dev.n > 0 && (!k.dev.type || !k.dev.d || !k.dev.g || !k.dev.s || !k.dev.kp ||
+                                      !k.dev.wl || !k.dev.vth || !k.dev.lam)))
+    return fail(c, EXPRI_EINVAL, w + "bad device table");
+  for (int i = 0; i < k.dev.n; ++i) {
+    if (k.dev.type[i] != 1 && k.dev.type[i] != -1) return fail(c, EXPRI_EINVAL, w + "device type must be +-1");
+    const double v[4] = {k.dev.kp[i], k.dev.wl[i], k.dev.vth[i], k.dev.lam[i]};
+    if (!finite_all(v, 4)) return fail(c, EXPRI_EINVAL, w + "non-finite device parameter");
+  }
+  if (!(k.T > 0) || !std::isfinite(k.T) || !std::isfinite(k.vdd)) return fail(c, EXPRI_EINVAL, w + "bad T / vdd");
+  if (k.n_probe < 0 || (k.n_probe > 0 && !k.probe)) return fail(c, EXPRI_EINVAL, w + "bad probes");
+  for (int i = 0; i < k.n_probe; ++i)
+    if (k.probe[i] < 0 || k.probe[i] >= k.n) return fail(c, EXPRI_EINVAL, w + "probe out of range");
+  return EXPRI_OK;
+}
+
+// workspace layout; returns total bytes
+size_t layout_workspace(expri_ctx *c) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  const int mm = c->opts.m_max;
+  for (auto &I : c->inst) {
+    const auto &S = c->pats[I.pat].sym;
+    const size_t n = I.n, nd = std::max(I.n_dev, 1);
+    I.ldv = (int64_t)((n + 31) / 32 * 32);
+    I.xk = take(8 * n); I.x1 = take(8 * n); I.w = take(8 * n); I.p = take(8 * n);
+    I.z = take(8 * n); I.tmp = take(8 * n); I.e = take(8 * n); I.Ik = take(8 * n);
+    I.devI = take(8 * nd); I.devD = take(24 * nd); I.devI1 = take(8 * nd);
+    I.lu = take(8 * (size_t)S.lu_rowptr[n]);
+    I.V = take(8 * (size_t)I.ldv * (mm + 1));
+    I.Ve = take(8 * (size_t)I.ldv * (mm + 1));
+    I.H = take(8 * (size_t)kHLd * kMaxKrylov);
+    I.He = take(8 * (size_t)kHLd * kMaxKrylov);
+    I.mat = take(8 * (size_t)7 * kHLd * kHLd);
+    I.state = take(sizeof(InstState));
+    I.trace = take(8 * (size_t)c->opts.trace_cap * (kRecFixed + I.n_probe));
+  }
+  return off;
+}
+
+void fill_descs(expri_ctx *c) {
+  c->h_desc.resize(c->inst.size());
+  for (size_t k = 0; k < c->inst.size(); ++k) {
+    const Inst &I = c->inst[k];
+    const PatternDev &P = c->pats[I.pat];
+    const Symbolic &S = P.sym;
+    InstDesc d{};
+    auto ci = [&](size_t off) { return reinterpret_cast<const int32_t *>(c->d_const + off); };
+    auto cd = [&](size_t off) { return reinterpret_cast<const double *>(c->d_const + off); };
+    auto wd = [&](size_t off) { return reinterpret_cast<double *>(c->d_ws + off); };
+    d.n = I.n;
+    d.n_dev = I.n_dev;
+    d.n_src = I.n_src;
+    d.n_bp = I.n_bp;
+    d.nnz_lu = S.lu_rowptr[I.n];
+    d.n_lev = (int32_t)S.lev_ptr.size() - 1;
+    d.n_ulev = (int32_t)S.ulev_ptr.size() - 1;
+    d.n_probe = I.n_probe;
+    d.has_dev = I.n_dev > 0;
+    d.vdd = I.vdd;
+    d.T = I.T;
+    d.h_max = I.h_max;
+    d.lu_rowptr = ci(P.lu_rowptr); d.lu_col = ci(P.lu_col); d.lu_diag = ci(P.lu_diag);
+    d.lev_ptr = ci(P.lev_ptr); d.lev_rows = ci(P.lev_rows);
+    d.ulev_ptr = ci(P.ulev_ptr); d.ulev_rows = ci(P.ulev_rows);
+    d.row_grp = ci(P.row_grp); d.grp_pos = ci(P.grp_pos); d.grp_diag = ci(P.grp_diag);
+    d.grp_ptr = ci(P.grp_ptr); d.pair_src = ci(P.pair_src); d.pair_dst = ci(P.pair_dst);
+    d.lu_gidx = ci(P.lu_gidx); d.jac_ptr = ci(P.jac_ptr); d.jac_code = ci(P.jac_code);
+    d.node_ptr = ci(P.node_ptr); d.node_code = ci(P.node_code);
+    d.g_rowptr = ci(P.g_rowptr); d.g_col = ci(P.g_col);
+    d.c_rowptr = ci(P.c_rowptr); d.c_col = ci(P.c_col);
+    d.b_rowptr = ci(P.b_rowptr); d.b_col = ci(P.b_col);
+    d.dev_node = ci(P.dev_node); d.perm = ci(P.perm);
+    d.probe = ci(I.probe);
+    d.g_val = cd(I.g_val); d.c_val = cd(I.c_val); d.b_val = cd(I.b_val);
+    d.dev_par = cd(I.dev_par); d.src_ptr = ci(I.src_ptr); d.src_t = cd(I.src_t);
+    d.src_v = cd(I.src_v); d.bp = cd(I.bp);
+    d.xk = wd(I.xk); d.x1 = wd(I.x1); d.w = wd(I.w); d.p = wd(I.p); d.z = wd(I.z);
+    d.tmp = wd(I.tmp); d.e = wd(I.e); d.devI = wd(I.devI); d.devD = wd(I.devD);
+    d.devI1 = wd(I.devI1); d.Ik = wd(I.Ik); d.lu = wd(I.lu); d.V = wd(I.V); d.Ve = wd(I.Ve);
+    d.H = wd(I.H); d.He = wd(I.He); d.mat = wd(I.mat);
+    d.ldv = I.ldv;
+    d.state = reinterpret_cast<InstState *>(c->d_ws + I.state);
+    d.trace = wd(I.trace);
+    d.trace_cap = c->opts.trace_cap;
+    c->h_desc[k] = d;
+  }
+}
+
+expri_status ensure_ws(expri_ctx *c) {
+  if (c->d_ws) return EXPRI_OK;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, c->ws_bytes);
+  if (e != hipSuccess) return fail(c, EXPRI_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
+  c->d_ws = static_cast<char *>(p);
+  c->ws_owned = true;
+  fill_descs(c);
+  HIPCHK(c, hipMemcpyAsync(c->d_desc, c->h_desc.data(), sizeof(InstDesc) * c->h_desc.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  return EXPRI_OK;
+}
+
+expri_status upload_descs(expri_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->d_desc, c->h_desc.data(), sizeof(InstDesc) * c->h_desc.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  return EXPRI_OK;
+}
+
+// copy a host array of n_inst device pointers into d_ptrs[slot * n_inst ...]
+expri_status put_ptrs(expri_ctx *c, int slot, const void *const *ptrs) {
+  const size_t n = c->inst.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!ptrs[i]) return fail(c, EXPRI_EINVAL, "null device vector");
+  HIPCHK(c, hipMemcpyAsync(c->d_ptrs + slot * n, ptrs, sizeof(void *) * n, hipMemcpyHostToDevice, c->stream));
+  return EXPRI_OK;
+}
+
+expri_status read_states(expri_ctx *c, std::vector<InstState> &st) {
+  st.resize(c->inst.size());
+  for (size_t k = 0; k < c->inst.size(); ++k)
+    HIPCHK(c, hipMemcpyAsync(&st[k], c->d_ws + c->inst[k].state, sizeof(InstState), hipMemcpyDeviceToHost,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EXPRI_OK;
+}
+
+expri_status first_error(expri_ctx *c, const std::vector<InstState> &st, const char *what) {
+  for (size_t k = 0; k < st.size(); ++k)
+    if (st[k].status != kOK) {
+      static const char *names[] = {"ok", "invalid argument", "out of memory", "singular pivot in LU(G_k)",
+                                    "Krylov residual not reached at m_max", "step below h_min",
+                                    "non-finite value", "HIP error", "pattern mismatch",
+                                    "Newton iteration did not converge"};
+      const int s = -st[k].status;
+      return fail(c, (expri_status)st[k].status,
+                  std::string(what) + ": instance " + std::to_string(k) + ": " +
+                      ((s >= 0 && s <= 9) ? names[s] : "error"));
+    }
+  return EXPRI_OK;
+}
+
+// drive k_run until every instance is done (adaptive or replay)
+expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int replay) {
+  const int n = (int)c->inst.size();
+  if (max_steps < 1 || max_steps > c->opts.trace_cap)
+    return fail(c, EXPRI_EINVAL, "max_steps_per_launch must be in [1, trace_cap]");
+  expri_status s;
+  if ((s = upload_descs(c)) != EXPRI_OK) return s;
+  if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
+  const Opts ko = kernel_opts(c->opts);
+  HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t0, c->opts.h_init,
+                         c->stream));
+  for (auto &I : c->inst) I.trace_host.clear();
+  std::vector<int32_t> prev(n, 0);
+  std::vector<InstState> st;
+  const int64_t max_launches = kMaxRunSteps / max_steps + 1;
+  for (int64_t launches = 0;; ++launches) {
+    if (launches >= max_launches)
+      return fail(c, EXPRI_ESTEPMIN, "step budget of " + std::to_string(kMaxRunSteps) + " accepted steps exhausted");
+    HIPCHK(c, launch_run(c->d_desc, n, ko, max_steps, replay, c->bs, c->R, c->stream));
+    if ((s = read_states(c, st)) != EXPRI_OK) return s;
+    bool all = true;
+    for (int k = 0; k < n; ++k) {
+      Inst &I = c->inst[k];
+      const int32_t add = st[k].steps - prev[k];
+      if (add > 0) {
+        const size_t rec = kRecFixed + I.n_probe;
+        const size_t old = I.trace_host.size();
+        I.trace_host.resize(old + (size_t)add * rec);
+        HIPCHK(c, hipMemcpyAsync(I.trace_host.data() + old, c->d_ws + I.trace, sizeof(double) * add * rec,
+                                 hipMemcpyDeviceToHost, c->stream));
+      }
+      prev[k] = st[k].steps;
+      if (!st[k].done) all = false;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (all) break;
+  }
+  HIPCHK(c, launch_end(c->d_desc, n, reinterpret_cast<double *const *>(c->d_ptrs), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) {
+    expri_run_info &in = c->inst[k].info;
+    in.t = st[k].t;
+    in.steps = st[k].steps;
+    in.lu_count = st[k].lu_count;
+    in.rejects = st[k].rejects;
+    in.arnoldi = st[k].arnoldi;
+    in.status = st[k].status;
+    for (int p = 0; p < 6; ++p) in.phase_s[p] = st[k].ph[p] / c->wall_hz;
+  }
+  return first_error(c, st, "transient");
+}
+
+}  // namespace
+
+extern "C" {
+
+expri_status expri_default_opts(expri_opts *o) {
+  if (!o) return EXPRI_EINVAL;
+  o->E_rr = 1e-6;
+  o->eps_krylov = 1e-7;
+  o->alpha = 0.5;
+  o->beta = 2.0;
+  o->h_init = 1e-13;
+  o->h_min = 1e-18;
+  o->h_max = 0.0;
+  o->breakdown = 1e-13;
+  o->piv_tol = 1e-13;
+  o->grow_if_rejects_lt = 5;
+  o->m_max = 60;
+  o->block_size = 0;
+  o->trace_cap = 4096;
+  return EXPRI_OK;
+}
+
+expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_inst, const expri_opts *o,
+                         void *hip_stream) {
+  if (!out) return EXPRI_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<expri_ctx> c(new (std::nothrow) expri_ctx());
+  if (!c) return EXPRI_ENOMEM;
+  if (!ckt || n_inst <= 0) return EXPRI_EINVAL;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (o) c->opts = *o; else expri_default_opts(&c->opts);
+  const expri_opts &op = c->opts;
+  if (!(op.E_rr > 0) || !(op.eps_krylov > 0) || !(op.alpha > 0 && op.alpha < 1) || !(op.beta >= 1) ||
+      !(op.h_init > 0) || !(op.h_min > 0) || !(op.h_max >= 0) || !(op.breakdown >= 0) ||
+      !(op.piv_tol >= 0) || op.m_max < 1 || op.m_max > kMaxKrylov || op.trace_cap < 1 ||
+      (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
+    *out = c.release();
+    (*out)->err = "invalid options";
+    return EXPRI_EINVAL;
+  }
+  expri_status s;
+  std::map<uint64_t, int> by_hash;
+  int n_max = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    if ((s = validate_circuit(c.get(), ckt[k], k)) != EXPRI_OK) {
+      *out = c.release();
+      return s;
+    }
+    const expri_circuit &K = ckt[k];
+    PatternInput pin;
+    pin.n = K.n;
+    pin.g_rowptr = K.G.rowptr; pin.g_col = K.G.colidx;
+    pin.c_rowptr = K.C.rowptr; pin.c_col = K.C.colidx;
+    pin.b_rowptr = K.B.rowptr; pin.b_col = K.B.colidx;
+    pin.n_src = K.n_src;
+    pin.n_dev = K.dev.n;
+    pin.dev_d = K.dev.d; pin.dev_g = K.dev.g; pin.dev_s = K.dev.s;
+    const uint64_t h = pattern_hash(pin);
+    int pid;
+    auto it = by_hash.find(h);
+    if (it != by_hash.end()) {
+      pid = it->second;
+      const Symbolic &S = c->pats[pid].sym;
+      // guard against a hash collision: compare the sizes and the G pattern
+      bool same = S.n == K.n && S.n_dev == K.dev.n && S.n_src == K.n_src &&
+                  (int32_t)S.g_col.size() == K.G.nnz && (int32_t)S.c_col.size() == K.C.nnz;
+      if (!same) { *out = c.release(); (*out)->err = "pattern hash collision"; return EXPRI_EPATTERN; }
+    } else {
+      PatternDev P;
+      if (!analyse(pin, P.sym)) {
+        *out = c.release();
+        (*out)->err = "instance " + std::to_string(k) + ": " + P.sym.error;
+        return EXPRI_EINVAL;
+      }
+      pid = (int)c->pats.size();
+      c->pats.push_back(std::move(P));
+      by_hash[h] = pid;
+    }
+    Inst I;
+    I.pat = pid;
+    I.n = K.n;
+    I.n_dev = K.dev.n;
+    I.n_src = K.n_src;
+    I.n_probe = K.n_probe;
+    I.vdd = K.vdd;
+    I.T = K.T;
+    I.h_max = op.h_max > 0 ? op.h_max : K.T / 20;
+    c->inst.push_back(std::move(I));
+    n_max = std::max(n_max, K.n);
+  }
+
+  // ---- pack constant data ----
+  Packer pk;
+  for (auto &P : c->pats) {
+    const Symbolic &S = P.sym;
+    P.lu_rowptr = pk.add(S.lu_rowptr); P.lu_col = pk.add(S.lu_col); P.lu_diag = pk.add(S.lu_diag);
+    P.lev_ptr = pk.add(S.lev_ptr); P.lev_rows = pk.add(S.lev_rows);
+    P.ulev_ptr = pk.add(S.ulev_ptr); P.ulev_rows = pk.add(S.ulev_rows);
+    P.row_grp = pk.add(S.row_grp); P.grp_pos = pk.add(S.grp_pos); P.grp_diag = pk.add(S.grp_diag);
+    P.grp_ptr = pk.add(S.grp_ptr); P.pair_src = pk.add(S.pair_src); P.pair_dst = pk.add(S.pair_dst);
+    P.lu_gidx = pk.add(S.lu_gidx); P.jac_ptr = pk.add(S.jac_ptr); P.jac_code = pk.add(S.jac_code);
+    P.node_ptr = pk.add(S.node_ptr); P.node_code = pk.add(S.node_code);
+    P.g_rowptr = pk.add(S.g_rowptr); P.g_col = pk.add(S.g_col);
+    P.c_rowptr = pk.add(S.c_rowptr); P.c_col = pk.add(S.c_col);
+    P.b_rowptr = pk.add(S.b_rowptr); P.b_col = pk.add(S.b_col);
+    P.dev_node = pk.add(S.dev_node); P.perm = pk.add(S.perm);
+  }
+  for (int k = 0; k < n_inst; ++k) {
+    const expri_circuit &K = ckt[k];
+    Inst &I = c->inst[k];
+    const Symbolic &S = c->pats[I.pat].sym;
+    I.g_val = pk.add(gather(K.G.val, S.g_src));
+    I.c_val = pk.add(gather(K.C.val, S.c_src));
+    I.b_val = pk.add(gather(K.B.val, S.b_src));
+    std::vector<double> par(4 * (size_t)K.dev.n);
+    for (int i = 0; i < K.dev.n; ++i) {
+      par[4 * i] = K.dev.type[i];
+      par[4 * i + 1] = K.dev.kp[i] * K.dev.wl[i];
+      par[4 * i + 2] = K.dev.vth[i];
+      par[4 * i + 3] = K.dev.lam[i];
+    }
+    I.dev_par = pk.add(par);
+    std::vector<int32_t> sp(K.n_src + 1, 0);
+    std::vector<double> st, sv, bps;
+    for (int q = 0; q < K.n_src; ++q) {
+      sp[q + 1] = sp[q] + K.src[q].npts;
+      st.insert(st.end(), K.src[q].t, K.src[q].t + K.src[q].npts);
+      sv.insert(sv.end(), K.src[q].v, K.src[q].v + K.src[q].npts);
+      for (int i = 0; i < K.src[q].npts; ++i)
+        if (K.src[q].t[i] > 0 && K.src[q].t[i] < K.T) bps.push_back(K.src[q].t[i]);
+    }
+    std::sort(bps.begin(), bps.end());
+    bps.erase(std::unique(bps.begin(), bps.end()), bps.end());
+    bps.push_back(K.T);
+    I.n_bp = (int32_t)bps.size();
+    I.src_ptr = pk.add(sp);
+    I.src_t = pk.add(st);
+    I.src_v = pk.add(sv);
+    I.bp = pk.add(bps);
+    std::vector<int32_t> pr(K.n_probe);
+    for (int q = 0; q < K.n_probe; ++q) pr[q] = S.iperm[K.probe[q]];
+    I.probe = pk.add(pr);
+  }
+  c->const_bytes = pk.img.size();
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, c->const_bytes);
+  if (e != hipSuccess) { *out = c.release(); (*out)->err = "constant upload allocation failed"; return EXPRI_ENOMEM; }
+  c->d_const = static_cast<char *>(p);
+  e = hipMemcpy(c->d_const, pk.img.data(), c->const_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_desc), sizeof(InstDesc) * n_inst);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_ptrs), sizeof(void *) * 4 * n_inst);
+  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "setup upload"); }
+
+  // ---- launch shape ----
+  int dev = 0;
+  hipDeviceProp_t prop;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "device query"); }
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
+    c->wall_hz = 1e3 * wall_khz;
+  c->bs = op.block_size ? op.block_size : (n_max <= 2048 ? 256 : (n_max <= 8192 ? 512 : 1024));
+  const size_t limit = prop.sharedMemPerBlock;
+  const size_t extras = lds_bytes(c->bs, 0);
+  size_t R = std::max<size_t>(n_max, 8192);
+  if (8 * R + extras > limit) R = std::max<size_t>(n_max, (limit - extras) / 8);
+  if (8 * R + extras > limit) {
+    *out = c.release();
+    (*out)->err = "circuit too large for the one-workgroup engine (n = " + std::to_string(n_max) + ")";
+    return EXPRI_EINVAL;
+  }
+  c->R = (int)R;
+  e = set_lds_limits(lds_bytes(c->bs, c->R));
+  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "LDS limit"); }
+  c->ws_bytes = layout_workspace(c.get());
+  *out = c.release();
+  return EXPRI_OK;
+}
+
+expri_status expri_workspace_size(const expri_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return EXPRI_EINVAL;
+  *bytes = c->ws_bytes;
+  return EXPRI_OK;
+}
+
+expri_status expri_bind_workspace(expri_ctx *c, void *dev_ptr, size_t bytes) {
+  if (!c) return EXPRI_EINVAL;
+  if (!dev_ptr || bytes < c->ws_bytes) return fail(c, EXPRI_EINVAL, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign) return fail(c, EXPRI_EINVAL, "workspace not 256-byte aligned");
+  if (c->d_ws && c->ws_owned) (void)hipFree(c->d_ws);
+  c->d_ws = static_cast<char *>(dev_ptr);
+  c->ws_owned = false;
+  fill_descs(c);
+  return upload_descs(c);
+}
+
+expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {
+  if (!c || !x) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  const int n = (int)c->inst.size();
+  if ((s = upload_descs(c)) != EXPRI_OK) return s;
+  if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
+  HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t0, c->opts.h_init, c->stream));
+  HIPCHK(c, launch_dc(c->d_desc, n, kernel_opts(c->opts), t0, 20000, c->bs, c->R, c->stream));
+  std::vector<InstState> st;
+  if ((s = read_states(c, st)) != EXPRI_OK) return s;
+  // write back only instances that converged (x keeps its input otherwise)
+  for (int k = 0; k < n; ++k) {
+    c->inst[k].info = expri_run_info{t0, st[k].steps, st[k].steps, 0, 0, st[k].status, {0, 0, 0, 0, 0, 0}};
+  }
+  if ((s = first_error(c, st, "DC")) != EXPRI_OK) return s;
+  HIPCHK(c, launch_end(c->d_desc, n, reinterpret_cast<double *const *>(c->d_ptrs), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EXPRI_OK;
+}
+
+expri_status expri_factor(expri_ctx *c, const double *const *x) {
+  if (!c || !x) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  const int n = (int)c->inst.size();
+  if ((s = upload_descs(c)) != EXPRI_OK) return s;
+  if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
+  HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), 0.0, c->opts.h_init, c->stream));
+  HIPCHK(c, launch_factor(c->d_desc, n, kernel_opts(c->opts), c->bs, c->R, c->stream));
+  std::vector<InstState> st;
+  if ((s = read_states(c, st)) != EXPRI_OK) return s;
+  return first_error(c, st, "factor");
+}
+
+expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y) {
+  if (!c || !b || !y) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  const int n = (int)c->inst.size();
+  if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(b))) != EXPRI_OK) return s;
+  if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(y))) != EXPRI_OK) return s;
+  HIPCHK(c, launch_solve(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs),
+                         reinterpret_cast<double *const *>(c->d_ptrs + n), c->bs, c->R, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EXPRI_OK;
+}
+
+expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out, double h, double eps,
+                        int32_t *m, double *rho) {
+  if (!c || !v || !out || !(h > 0) || !(eps > 0)) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  const int n = (int)c->inst.size();
+  if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(v))) != EXPRI_OK) return s;
+  if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(out))) != EXPRI_OK) return s;
+  HIPCHK(c, launch_mevp(c->d_desc, n, kernel_opts(c->opts), reinterpret_cast<const double *const *>(c->d_ptrs),
+                        reinterpret_cast<double *const *>(c->d_ptrs + n), h, eps, c->bs, c->R, c->stream));
+  std::vector<InstState> st;
+  if ((s = read_states(c, st)) != EXPRI_OK) return s;
+  for (int k = 0; k < n; ++k) {
+    if (m) m[k] = st[k].arnoldi;
+    if (rho) rho[k] = st[k].t;
+  }
+  return first_error(c, st, "mevp");
+}
+
+expri_status expri_run(expri_ctx *c, double *const *x, double t0, int32_t max_steps_per_launch) {
+  if (!c || !x) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  for (size_t k = 0; k < c->inst.size(); ++k) {
+    const Inst &I = c->inst[k];
+    c->h_desc[k].bp = reinterpret_cast<const double *>(c->d_const + I.bp);
+    c->h_desc[k].n_bp = I.n_bp;
+  }
+  return drive(c, x, t0, max_steps_per_launch, 0);
+}
+
+expri_status expri_run_schedule(expri_ctx *c, double *const *x, double t0, const double *const *t_seq,
+                                const int32_t *n_steps) {
+  if (!c || !x || !t_seq || !n_steps) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  const int n = (int)c->inst.size();
+  size_t total = 0;
+  int32_t most = 1;
+  for (int k = 0; k < n; ++k) {
+    if (n_steps[k] < 0 || (n_steps[k] > 0 && !t_seq[k])) return fail(c, EXPRI_EINVAL, "bad schedule");
+    double prev = t0;
+    for (int i = 0; i < n_steps[k]; ++i) {
+      if (!(t_seq[k][i] > prev) || !std::isfinite(t_seq[k][i])) return fail(c, EXPRI_EINVAL, "schedule not increasing");
+      prev = t_seq[k][i];
+    }
+    total += align_up(8 * (size_t)std::max(n_steps[k], 1));
+    most = std::max(most, n_steps[k]);
+  }
+  char *d = nullptr;
+  HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&d), total));
+  size_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    if (n_steps[k] > 0)
+      if (hipMemcpy(d + off, t_seq[k], 8 * (size_t)n_steps[k], hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return fail(c, EXPRI_EHIP, "schedule upload");
+      }
+    c->h_desc[k].bp = reinterpret_cast<const double *>(d + off);
+    c->h_desc[k].n_bp = n_steps[k];
+    off += align_up(8 * (size_t)std::max(n_steps[k], 1));
+  }
+  s = drive(c, x, t0, std::min(most, c->opts.trace_cap), 1);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  return s;
+}
+
+expri_status expri_step(expri_ctx *c, double *const *x, double t, double h, expri_run_info *info) {
+  if (!c || !x || !(h > 0)) return EXPRI_EINVAL;
+  const int n = (int)c->inst.size();
+  std::vector<double> tn(n, t + h);
+  std::vector<const double *> seq(n);
+  std::vector<int32_t> cnt(n, 1);
+  for (int k = 0; k < n; ++k) seq[k] = &tn[k];
+  expri_status s = expri_run_schedule(c, x, t, seq.data(), cnt.data());
+  if (info)
+    for (int k = 0; k < n; ++k) info[k] = c->inst[k].info;
+  return s;
+}
+
+expri_status expri_trace(const expri_ctx *c, int32_t inst, double *out, int64_t cap, int64_t *n_rec) {
+  if (!c || inst < 0 || inst >= (int32_t)c->inst.size() || !n_rec) return EXPRI_EINVAL;
+  const Inst &I = c->inst[inst];
+  const size_t rec = kRecFixed + I.n_probe;
+  const int64_t avail = (int64_t)(I.trace_host.size() / rec);
+  *n_rec = avail;
+  if (out && cap > 0) std::memcpy(out, I.trace_host.data(), sizeof(double) * rec * std::min(cap, avail));
+  return EXPRI_OK;
+}
+
+expri_status expri_get_run_info(const expri_ctx *c, int32_t inst, expri_run_info *info) {
+  if (!c || inst < 0 || inst >= (int32_t)c->inst.size() || !info) return EXPRI_EINVAL;
+  *info = c->inst[inst].info;
+  return EXPRI_OK;
+}
+
+expri_status expri_lu_pattern(const expri_ctx *c, int32_t inst, int32_t *rowptr, int32_t *col, int32_t *perm,
+                              int64_t *nnz, int32_t *n_lev, int32_t *n_ulev, int64_t *flops) {
+  if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return EXPRI_EINVAL;
+  const Symbolic &S = c->pats[c->inst[inst].pat].sym;
+  if (rowptr) std::memcpy(rowptr, S.lu_rowptr.data(), sizeof(int32_t) * S.lu_rowptr.size());
+  if (col) std::memcpy(col, S.lu_col.data(), sizeof(int32_t) * S.lu_col.size());
+  if (perm) std::memcpy(perm, S.perm.data(), sizeof(int32_t) * S.perm.size());
+  if (nnz) *nnz = (int64_t)S.lu_col.size();
+  if (n_lev) *n_lev = (int32_t)S.lev_ptr.size() - 1;
+  if (n_ulev) *n_ulev = (int32_t)S.ulev_ptr.size() - 1;
+  if (flops) *flops = S.flops;
+  return EXPRI_OK;
+}
+
+expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
+  if (!c || !out || inst < 0 || inst >= (int32_t)c->inst.size() || !c->d_ws) return EXPRI_EINVAL;
+  const Inst &I = c->inst[inst];
+  const size_t nnz = c->pats[I.pat].sym.lu_col.size();
+  if (hipMemcpy(out, c->d_ws + I.lu, sizeof(double) * nnz, hipMemcpyDeviceToHost) != hipSuccess)
+    return EXPRI_EHIP;
+  return EXPRI_OK;
+}
+
+const char *expri_last_error(const expri_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void expri_destroy(expri_ctx *c) {
+  if (!c) return;
+  if (c->d_ws && c->ws_owned) (void)hipFree(c->d_ws);
+  if (c->d_const) (void)hipFree(c->d_const);
+  if (c->d_desc) (void)hipFree(c->d_desc);
+  if (c->d_ptrs) (void)hipFree(c->d_ptrs);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Plain-old-data structures shared by the host runtime and the gfx950 kernels.
+// One InstDesc describes one circuit instance: device pointers to its
+// (possibly shared) symbolic arrays, its own values, its workspace and its
+// run state.  Every node id inside is in the internal (permuted) numbering.
+#pragma once
+
+#include <stdint.h>
+
+namespace expri {
+
+constexpr int kMaxKrylov = 60;        // hard upper bound on m
+constexpr int kHLd = kMaxKrylov + 1;  // leading dimension of stored Hessenbergs
+constexpr int kRecFixed = 8;          // fixed doubles per trace record
+constexpr int kPhases = 6;            // profiled phases of a step
+// status codes (mirror expri_status of the public header)
+constexpr int kOK = 0, kEINVAL = -1, kENOMEM = -2, kESINGULAR = -3, kEKRYLOV = -4,
+              kESTEPMIN = -5, kENONFINITE = -6, kEHIP = -7, kEPATTERN = -8, kENOCONV = -9;
+
+struct Opts {
+  double E_rr;        // step error budget (V, infinity norm)
+  double eps_K;       // Krylov residual tolerance (V)
+  double alpha;       // step reduction after a rejection
+  double beta;        // step growth
+  double h_init, h_min, h_max;
+  double breakdown;   // happy-breakdown threshold, relative to max |H|
+  double piv_tol;     // small-pivot threshold, relative to the row's max |G_k|
+  int32_t grow_if_rejects_lt;
+  int32_t m_max;
+};
+
+// Run state of one instance; lives in device memory between launches.
+struct InstState {
+  double t;           // current time
+  double h_prop;      // proposed step
+  int32_t bp_idx;     // first breakpoint strictly after t
+  int32_t steps;      // accepted steps so far in this run
+  int32_t status;     // 0 running/ok, <0 error code
+  int32_t done;       // 1 when t reached T (or error)
+  int32_t lu_count;   // numeric factorisations in this run
+  int32_t rejects;    // total rejected trials
+  int32_t arnoldi;    // total Arnoldi iterations
+  int32_t lu_valid;   // factors of G_k are current (linear circuits keep them)
+  // wall-clock ticks per phase: factor, rhs, arnoldi solve, mgs, phi, trial
+  double ph[kPhases];
+};
+
+struct InstDesc {
+  int32_t n, n_dev, n_src, n_bp;
+  int32_t nnz_lu, n_lev, n_ulev, n_probe;
+  int32_t has_dev, pad0, pad1, pad2;
+  double vdd, T, h_max;
+
+  // symbolic (shared by instances of one pattern)
+  const int32_t *lu_rowptr, *lu_col, *lu_diag;
+  const int32_t *lev_ptr, *lev_rows, *ulev_ptr, *ulev_rows;
+  const int32_t *row_grp, *grp_pos, *grp_diag, *grp_ptr, *pair_src, *pair_dst;
+  const int32_t *lu_gidx, *jac_ptr, *jac_code, *node_ptr, *node_code;
+  const int32_t *g_rowptr, *g_col, *c_rowptr, *c_col, *b_rowptr, *b_col;
+  const int32_t *dev_node;      // 3 per device
+  const int32_t *perm;          // perm[internal] = caller's node id
+  const int32_t *probe;         // internal ids of the probed nodes
+
+  // values (per instance, permuted to the internal numbering)
+  const double *g_val, *c_val, *b_val;
+  const double *dev_par;        // 4 per device: type (+1/-1), K = k' W/L, V_th, lambda
+  const int32_t *src_ptr;       // n_src + 1
+  const double *src_t, *src_v;  // PWL corners
+  const double *bp;             // breakpoints in (0, T), then T
+
+  // workspace (per instance)
+  double *xk, *x1, *w, *p, *z, *tmp, *e;
+  double *devI, *devD, *devI1;  // per device: I(x_k), dI/d(d,g,s)(x_k), I(x_{k+1})
+  double *Ik;                   // node currents at x_k
+  double *lu;                   // L\U values
+  double *V, *Ve;               // Krylov bases, n x (m_max + 1), column j at j * ldv
+  double *H, *He;               // Hessenbergs, kHLd x kMaxKrylov column-major
+  double *mat;                  // small dense matrices when they do not fit in LDS
+  int64_t ldv;                  // column stride of V / Ve (>= n, multiple of 32)
+  InstState *state;
+  double *trace;                // records of kRecFixed + n_probe doubles
+  int32_t trace_cap;            // records available
+  int32_t pad3;
+};
+
+}  // namespace expri

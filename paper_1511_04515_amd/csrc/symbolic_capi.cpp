@@ -1,0 +1,59 @@
+// Host-only C entry points exposing the symbolic analysis (diagnostics and
+// CPU tests of the schedules the kernels execute).
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/expri.h"
+#include "symbolic.hpp"
+
+struct expri_symbolic {
+  expri::Symbolic sym;
+};
+
+extern "C" {
+
+expri_status expri_symbolic_create(expri_symbolic **out, const expri_circuit *k) {
+  if (!out || !k) return EXPRI_EINVAL;
+  *out = nullptr;
+  expri::PatternInput pin;
+  pin.n = k->n;
+  if (k->G.n_rows != k->n || k->C.n_rows != k->n || k->B.n_rows != k->n || k->B.n_cols != k->n_src)
+    return EXPRI_EINVAL;
+  pin.g_rowptr = k->G.rowptr; pin.g_col = k->G.colidx;
+  pin.c_rowptr = k->C.rowptr; pin.c_col = k->C.colidx;
+  pin.b_rowptr = k->B.rowptr; pin.b_col = k->B.colidx;
+  pin.n_src = k->n_src;
+  pin.n_dev = k->dev.n;
+  pin.dev_d = k->dev.d; pin.dev_g = k->dev.g; pin.dev_s = k->dev.s;
+  expri_symbolic *s = new (std::nothrow) expri_symbolic();
+  if (!s) return EXPRI_ENOMEM;
+  if (!expri::analyse(pin, s->sym)) {
+    delete s;
+    return EXPRI_EINVAL;
+  }
+  *out = s;
+  return EXPRI_OK;
+}
+
+expri_status expri_symbolic_array(const expri_symbolic *s, const char *name, int32_t *out, int64_t cap,
+                                  int64_t *len) {
+  if (!s || !name || !len) return EXPRI_EINVAL;
+  const expri::Symbolic &S = s->sym;
+  const std::vector<int32_t> *v = nullptr;
+  const std::string nm(name);
+#define A(X) if (nm == #X) v = &S.X;
+  A(perm) A(lu_rowptr) A(lu_col) A(lu_diag) A(lev_ptr) A(lev_rows) A(ulev_ptr) A(ulev_rows)
+  A(row_grp) A(grp_pos) A(grp_diag) A(grp_ptr) A(pair_src) A(pair_dst) A(lu_gidx) A(jac_ptr)
+  A(jac_code) A(node_ptr) A(node_code) A(g_rowptr) A(g_col) A(g_src) A(c_rowptr) A(c_col)
+  A(c_src) A(b_rowptr) A(b_col) A(b_src) A(dev_node) A(block_of)
+#undef A
+  if (!v) return EXPRI_EINVAL;
+  *len = (int64_t)v->size();
+  if (out && cap > 0) std::memcpy(out, v->data(), sizeof(int32_t) * (size_t)std::min<int64_t>(cap, *len));
+  return EXPRI_OK;
+}
+
+void expri_symbolic_destroy(expri_symbolic *s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+"""Writes the stored oracle results the GPU parity tests compare against.
+
+Calls only the oracle and the seeded circuit generators:
+
+    python tests/golden/make_golden.py            # all
+    python tests/golden/make_golden.py mesh       # one
+
+Files (numpy .npz, no pickles): for each workload the DC point, the accepted
+time grid and per-step counters of the adaptive oracle run, and the probe
+voltages of the oracle's replay of that grid (the reference of the GPU
+replay-parity tests).
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import netgen  # noqa: E402
+from oracle import Oracle  # noqa: E402
+
+WORKLOADS = {
+    # RC mesh 32x32, 1,024 nodes, linear, pulse loads, 5 ns
+    "mesh": lambda: netgen.config(1),
+    # inverter chain, 200 stages, 4,201 nodes, 4 ns
+    "chain": lambda: netgen.config(2),
+    # a short chain that switches fully inside its window (edge-case coverage)
+    "chain12": lambda: netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9, t_ramp=0.2e-9),
+}
+
+
+def make(name: str):
+    net = WORKLOADS[name]()
+    t0 = time.time()
+    o = Oracle(net)
+    x0 = o.dc()
+    run = o.run(x0, keep=net.probes)
+    t_run = time.time() - t0
+    rep = Oracle(net).replay(x0, run.t, keep="all")
+    X = np.array(rep.x)
+    out = dict(
+        x0=x0, t=np.array(run.t), h=np.array(run.h), h_try=np.array(run.h_try),
+        m=np.array(run.m), m_err=np.array(run.m_err), rejects=np.array(run.rejects),
+        err=np.array(run.err), rho=np.array(run.rho), probes=np.asarray(net.probes),
+        run_probe_x=np.array(run.x),
+        replay_probe_x=X[:, net.probes], replay_m=np.array(rep.m), replay_m_err=np.array(rep.m_err),
+        replay_err=np.array(rep.err), replay_rho=np.array(rep.rho),
+        x_final=X[-1], lu_count=run.lu_count, arnoldi=run.arnoldi_iters, seconds=t_run,
+    )
+    path = os.path.join(HERE, f"{name}.npz")
+    np.savez_compressed(path, **out)
+    print(f"{name}: {len(run.t)} steps, {sum(run.rejects)} rejections, {t_run:.1f} s -> {path}")
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(WORKLOADS)):
+        make(name)

@@ -1,0 +1,248 @@
+"""GPU parity of libexpri against the oracle (run on an MI355X).
+
+Every call goes through the C-ABI (ctypes binding).  Tolerances:
+  * LU of G_k: ||L U - P G_k P^T|| <= 1e-12 ||G_k||; solves: normwise
+    backward error <= 1e-12 (the linear-solve bar is 1e-10);
+  * MEVP and one-step results: 1e-10 relative to the vector norm (same
+    arithmetic in a different summation order);
+  * transient waveforms: max_k ||x_gpu(t_k) - x_ref(t_k)||_inf /
+    max(max_k ||x_ref||_inf, 1 V) <= 1e-6 on the replayed grid (both sides take
+    the same steps; the observed error is far smaller).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import netgen
+from oracle import Oracle, Options, InvertKrylov, device_currents
+from tests.exact import ladder_step, linear_exact
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def Solver(nets, **kw):
+    import paper_1511_04515_amd as E
+    return E.Solver(nets, **kw)
+
+
+def rel_wave_err(x, ref):
+    return np.max(np.abs(np.asarray(x) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1.0)
+
+
+def lu_residual(s, inst, net, x):
+    pat = s.lu_pattern(inst)
+    lu = s.lu_values(inst)
+    n = net.n
+    F = sp.csr_matrix((lu, pat["col"], pat["rowptr"]), shape=(n, n)).toarray()
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    _, Jd = device_currents(net, x)
+    perm = pat["perm"]
+    Gk = (net.G + Jd).toarray()[np.ix_(perm, perm)]
+    return np.linalg.norm(L @ U - Gk) / np.linalg.norm(Gk), Gk, perm
+
+
+def test_factor_and_solve_match_oracle():
+    net = netgen.inverter_chain(seed=3, n_stages=20)
+    o = Oracle(net)
+    x0 = o.dc()
+    x = x0 + np.random.default_rng(1).normal(0, 0.05, net.n)
+    s = Solver(net)
+    xs = s.to_device([x])
+    s.factor(xs)
+    r, Gk, perm = lu_residual(s, 0, net, x)
+    assert r <= 1e-12
+    b = np.random.default_rng(2).standard_normal(net.n)
+    ys = s.zeros()
+    s.solve(s.to_device([b]), ys)
+    y = ys[0].cpu().numpy()
+    _, Jd = device_currents(net, x)
+    G = (net.G + Jd).tocsr()
+    berr = np.abs(G @ y - b).max() / (abs(G).sum(1).max() * np.abs(y).max() + np.abs(b).max())
+    assert berr <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("h", [2e-14, 1e-12, 5e-11])
+def test_mevp_matches_oracle(h):
+    net = netgen.inverter_chain(seed=4, n_stages=20)
+    o = Oracle(net)
+    x0 = o.dc()
+    _, Jd = device_currents(net, x0)
+    lu = spla.splu((net.G + Jd).tocsc())
+    A = lambda q: -lu.solve(net.C @ q)
+    v = A(np.random.default_rng(5).standard_normal(net.n))
+    eps = 1e-7 * np.linalg.norm(v)
+    k = InvertKrylov(A, v, 60)
+    d, rho = k.converge(h, eps)
+    ref = k.combine(d)
+    s = Solver(net)
+    s.factor(s.to_device([x0]))
+    outs = s.zeros()
+    m, rho_g = s.mevp(s.to_device([v]), outs, h, eps)
+    got = outs[0].cpu().numpy()
+    assert m[0] == k.m
+    assert rho_g[0] == pytest.approx(rho, rel=1e-6, abs=1e-30)
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.linalg.norm(v)
+    s.close()
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_dc_matches_oracle(cfg):
+    net = netgen.config(cfg)
+    ref = Oracle(net).dc()
+    s = Solver(net)
+    xs = s.zeros()
+    info = s.dc(xs)
+    assert info[0]["status"] == 0
+    assert np.max(np.abs(xs[0].cpu().numpy() - ref)) <= 1e-10
+    s.close()
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}.npz")
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run tests/golden/make_golden.py")
+    return np.load(path, allow_pickle=False)
+
+
+@pytest.mark.parametrize("name,cfg", [("mesh", 1), ("chain", 2), ("chain12", None)])
+def test_replay_parity_full_run(name, cfg):
+    g = _golden(name)
+    net = netgen.config(cfg) if cfg else netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9,
+                                                               t_ramp=0.2e-9)
+    s = Solver(net, trace_cap=4096)
+    xs = s.to_device([g["x0"]])
+    info = s.run_schedule(xs, [g["t"]])
+    assert info[0]["status"] == 0 and info[0]["steps"] == len(g["t"])
+    tr = s.trace(0)
+    assert np.array_equal(tr["t"], g["t"])
+    err = rel_wave_err(tr["x"], g["replay_probe_x"])
+    assert err <= 1e-6
+    # the final full state as well
+    assert rel_wave_err(xs[0].cpu().numpy(), g["x_final"]) <= 1e-6
+    # Krylov sizes agree except where the residual sits on the threshold
+    assert np.mean(tr["m"] == g["replay_m"]) > 0.95
+    if net.n_dev:
+        big = g["replay_err"] > 1e-3 * net.tol
+        assert np.allclose(tr["err"][big], g["replay_err"][big], rtol=1e-3)
+    print(f"{name}: {len(g['t'])} steps, waveform rel err {err:.2e}")
+    s.close()
+
+
+def test_adaptive_run_follows_oracle_grid():
+    g = _golden("chain12")
+    net = netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9, t_ramp=0.2e-9)
+    s = Solver(net)
+    xs = s.to_device([g["x0"]])
+    info = s.run(xs)
+    tr = s.trace(0)
+    assert info[0]["status"] == 0 and tr["t"][-1] == net.T
+    # same controller, same decisions except where err sits on E_rr
+    n_ref = len(g["t"])
+    assert abs(len(tr["t"]) - n_ref) <= max(3, n_ref // 50)
+    common = np.intersect1d(tr["t"], g["t"])
+    assert common.size > 0.9 * n_ref
+    ia = np.searchsorted(tr["t"], common)
+    ib = np.searchsorted(g["t"], common)
+    assert rel_wave_err(tr["x"][ia], g["run_probe_x"][ib]) <= 1e-5
+    # one LU per accepted step, none on a rejection
+    assert info[0]["lu_count"] == info[0]["steps"] and info[0]["rejects"] > 0
+    s.close()
+
+
+def test_closed_forms_on_gpu():
+    R, Cap = 1e3, 1e-12
+    for wave in ("step", "ramp"):
+        net = netgen.rc_single(R=R, Cap=Cap, wave=wave)
+        s = Solver(net)
+        xs = s.zeros()
+        s.run(xs)
+        tr = s.trace(0)
+        t = tr["t"]
+        ex = 1 - np.exp(-t / (R * Cap)) if wave == "step" else (t - R * Cap * (1 - np.exp(-t / (R * Cap)))) / net.T
+        assert np.max(np.abs(tr["x"][:, 0] - ex)) < 1e-13
+        s.close()
+    N, Rl, c = 16, 100.0, 10e-15
+    net = netgen.rc_ladder(N=N, R=Rl, c=c)
+    s = Solver(net, E_rr=1e-12)
+    xs = s.zeros()
+    s.run(xs)
+    tr = s.trace(0)
+    assert np.max(np.abs(tr["x"] - ladder_step(N, Rl, c, 1.0, tr["t"]))) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_singular_C_tiny_circuits_on_gpu(seed):
+    net = netgen.tiny_linear(seed)
+    x0 = Oracle(net).dc()
+    s = Solver(net, E_rr=1e-12)
+    xs = s.to_device([x0])
+    s.run(xs)
+    tr = s.trace(0)
+    ex = linear_exact(net, x0, tr["t"])
+    assert np.max(np.abs(tr["x"] - ex[:, net.probes])) < 1e-12
+    s.close()
+
+
+def test_batch_matches_single_instance_runs():
+    base = netgen.inverter_chain(seed=1004, n_stages=30, T=0.8e-9, t_ramp=0.3e-9)
+    vals = base.meta["values"]
+    nets = [netgen.inverter_chain(seed=1004, n_stages=30, T=0.8e-9, t_ramp=0.3e-9, base=vals,
+                                  variation=dict(seed=3000 + i)) for i in range(3)]
+    nets.append(netgen.inverter_chain(seed=9, n_stages=17, T=0.8e-9, t_ramp=0.3e-9))
+    x0s = [Oracle(n).dc() for n in nets]
+    sb = Solver(nets, block_size=512)
+    xb = sb.to_device(x0s)
+    sb.run(xb)
+    for i, net in enumerate(nets):
+        s1 = Solver(net, block_size=512)
+        x1 = s1.to_device([x0s[i]])
+        s1.run(x1)
+        a, b = sb.trace(i), s1.trace(0)
+        assert np.array_equal(a["t"], b["t"]) and np.array_equal(a["x"], b["x"])
+        assert np.array_equal(xb[i].cpu().numpy(), x1[0].cpu().numpy())
+        s1.close()
+    sb.close()
+
+
+def test_error_paths_keep_last_state():
+    import paper_1511_04515_amd as E
+    net = netgen.single_inverter()
+    x0 = Oracle(net).dc()
+    # step below h_min: an error budget no step can meet (forced from the host)
+    s = Solver(net, E_rr=1e-30, eps_krylov=1e-9)
+    xs = s.to_device([x0])
+    with pytest.raises(E.ExpriError) as ei:
+        s.run(xs)
+    assert ei.value.status == -5
+    assert np.array_equal(xs[0].cpu().numpy(), x0)
+    s.close()
+    # Krylov basis capped below what the residual needs
+    net = netgen.config(1)
+    s = Solver(net, m_max=1)
+    xs = s.to_device([Oracle(net).dc()])
+    with pytest.raises(E.ExpriError) as ei:
+        s.run(xs)
+    assert ei.value.status == -4
+    s.close()
+    # a node with no conductance: G_k is singular
+    b = netgen.Builder()
+    a, f = b.node(), b.node()
+    b.resistor(a, -1, 100.0)
+    b.capacitor(a, -1, 1e-15)
+    b.capacitor(f, -1, 1e-15)
+    b.voltage_source(a, 10.0, netgen.PWL([0.0, 1e-12], [0.0, 1.0]))
+    bad = b.build("floating", T=1e-11)
+    s = Solver(bad)
+    xs = s.zeros()
+    with pytest.raises(E.ExpriError) as ei:
+        s.run(xs)
+    assert ei.value.status == -3
+    s.close()

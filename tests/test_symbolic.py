@@ -1,0 +1,156 @@
+"""Host-side symbolic analysis of libexpri (no GPU): the integer arrays that
+drive the kernels are replayed here in NumPy -- G_k assembly from the stamp
+maps, the level-scheduled row-wise refactor and the level-scheduled
+triangular solves -- and checked against SciPy and the oracle's G_k."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import netgen
+from oracle import device_currents, mosfet_eval
+from paper_1511_04515_amd import symbolic_analysis
+
+
+def _device_derivs(net, x):
+    d = net.mosfets
+    def tv(node):
+        v = np.zeros(node.shape)
+        v[node >= 0] = x[node[node >= 0]]
+        v[node == -2] = net.vdd
+        return v
+    I, dd, dg, ds = mosfet_eval(d["type"], tv(d["d"]), tv(d["g"]), tv(d["s"]), d["kp"], d["wl"],
+                                d["vth"], d["lam"])
+    return I, np.stack([dd, dg, ds], axis=1)
+
+
+def emulate_factor(net, S, x):
+    """Assemble G_k into the L\\U storage and run the row-wise refactor in
+    level order, exactly as the kernels index it."""
+    nnz = S["lu_col"].size
+    gval = net.G.data[S["g_src"]]
+    Idev, D = _device_derivs(net, x) if net.n_dev else (np.zeros(0), np.zeros((0, 3)))
+    lu = np.zeros(nnz)
+    for p in range(nnz):
+        gi = S["lu_gidx"][p]
+        v = gval[gi] if gi >= 0 else 0.0
+        for c in S["jac_code"][S["jac_ptr"][p]:S["jac_ptr"][p + 1]]:
+            dv = D[c >> 4, c & 3]
+            v += -dv if (c >> 2) & 1 else dv
+        lu[p] = v
+    G_perm_k = lu.copy()
+    for lv in range(S["lev_ptr"].size - 1):
+        for i in S["lev_rows"][S["lev_ptr"][lv]:S["lev_ptr"][lv + 1]]:
+            for g in range(S["row_grp"][i], S["row_grp"][i + 1]):
+                l = lu[S["grp_pos"][g]] / lu[S["grp_diag"][g]]
+                lu[S["grp_pos"][g]] = l
+                for u in range(S["grp_ptr"][g], S["grp_ptr"][g + 1]):
+                    lu[S["pair_dst"][u]] -= l * lu[S["pair_src"][u]]
+    return G_perm_k, lu, Idev
+
+
+def emulate_solve(S, lu, b):
+    x = b.copy()
+    rp, col, dg = S["lu_rowptr"], S["lu_col"], S["lu_diag"]
+    for lv in range(S["lev_ptr"].size - 1):
+        for i in S["lev_rows"][S["lev_ptr"][lv]:S["lev_ptr"][lv + 1]]:
+            x[i] -= lu[rp[i]:dg[i]] @ x[col[rp[i]:dg[i]]]
+    for lv in range(S["ulev_ptr"].size - 1):
+        for i in S["ulev_rows"][S["ulev_ptr"][lv]:S["ulev_ptr"][lv + 1]]:
+            x[i] = (x[i] - lu[dg[i] + 1:rp[i + 1]] @ x[col[dg[i] + 1:rp[i + 1]]]) / lu[dg[i]]
+    return x
+
+
+def csr_of(S, n, vals):
+    return sp.csr_matrix((vals, S["lu_col"], S["lu_rowptr"]), shape=(n, n))
+
+
+CIRCUITS = [
+    lambda: netgen.single_inverter(),
+    lambda: netgen.inverter_chain(n_stages=8, n_seg=3),
+    lambda: netgen.tiny_linear(2),
+    lambda: netgen.rc_mesh(seed=5, side=9, n_loads=3),
+    lambda: netgen.rc_ladder(N=20),
+]
+
+
+@pytest.mark.parametrize("make", CIRCUITS)
+def test_refactor_and_solve_schedule_reproduce_scipy(make):
+    net = make()
+    S = symbolic_analysis(net)
+    n = net.n
+    perm = S["perm"]
+    assert sorted(perm) == list(range(n))
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0.0, 1.0, n)
+    Gk_vals, lu, Idev = emulate_factor(net, S, x)
+    # the assembled values are P G_k P^T (G_k from the oracle's device model)
+    _, Jd = device_currents(net, x)
+    Gk = (net.G + Jd).toarray()[np.ix_(perm, perm)]
+    assembled = csr_of(S, n, Gk_vals).toarray()
+    assert np.allclose(assembled, Gk, rtol=1e-14, atol=1e-300)
+    # L U == P G_k P^T
+    F = csr_of(S, n, lu).toarray()
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    assert np.linalg.norm(L @ U - Gk) <= 1e-12 * np.linalg.norm(Gk)
+    # level-scheduled solve: normwise backward error at rounding level (a random
+    # state can leave G_k badly conditioned, so compare residuals, not solutions)
+    b = rng.standard_normal(n)
+    y = emulate_solve(S, lu, b[perm])
+    res = Gk @ y - b[perm]
+    berr = np.abs(res).max() / (np.abs(Gk).sum(1).max() * np.abs(y).max() + np.abs(b).max())
+    assert berr <= 1e-14
+
+
+def test_schedules_respect_dependencies_on_workloads():
+    for net in (netgen.config(1), netgen.config(2)):
+        S = symbolic_analysis(net)
+        n = net.n
+        rp, col, dg = S["lu_rowptr"], S["lu_col"], S["lu_diag"]
+        for ptr, rows, lower in ((S["lev_ptr"], S["lev_rows"], True), (S["ulev_ptr"], S["ulev_rows"], False)):
+            level = np.full(n, -1)
+            for lv in range(ptr.size - 1):
+                level[rows[ptr[lv]:ptr[lv + 1]]] = lv
+            assert np.all(level >= 0) and rows.size == n
+            for i in range(n):
+                deps = col[rp[i]:dg[i]] if lower else col[dg[i] + 1:rp[i + 1]]
+                assert np.all(level[deps] < level[i])
+        # refactor update pairs stay inside their rows
+        for i in range(0, n, 7):
+            for g in range(S["row_grp"][i], S["row_grp"][i + 1]):
+                assert rp[i] <= S["grp_pos"][g] < dg[i]
+                for u in range(S["grp_ptr"][g], S["grp_ptr"][g + 1]):
+                    assert rp[i] <= S["pair_dst"][u] < rp[i + 1]
+        # every row has its diagonal and sorted columns
+        assert np.all(col[dg] == np.arange(n))
+        for i in range(0, n, 11):
+            assert np.all(np.diff(col[rp[i]:rp[i + 1]]) > 0)
+
+
+def test_chain_ordering_is_shallow_and_dc_blocks_match_oracle():
+    from oracle import Oracle
+    net = netgen.config(2)
+    S = symbolic_analysis(net)
+    assert S["lev_ptr"].size - 1 <= 16          # nested dissection of a path
+    perm = S["perm"]
+    blocks = Oracle(net).dc_blocks()
+    ours = S["block_of"]                           # internal numbering
+    lab = np.empty(net.n, int)
+    lab[perm] = ours
+    for mem in blocks:
+        assert np.unique(lab[mem]).size == 1
+    assert np.unique(ours).size == len(blocks)
+
+
+def test_node_current_gather_matches_oracle():
+    net = netgen.inverter_chain(n_stages=5, n_seg=2)
+    S = symbolic_analysis(net)
+    x = np.random.default_rng(3).uniform(0, 1, net.n)
+    Idev, _ = _device_derivs(net, x)
+    I_ref, _ = device_currents(net, x)
+    got = np.zeros(net.n)
+    for i in range(net.n):
+        for c in S["node_code"][S["node_ptr"][i]:S["node_ptr"][i + 1]]:
+            got[i] += -Idev[c >> 1] if c & 1 else Idev[c >> 1]
+    assert np.allclose(got, I_ref[S["perm"]], rtol=1e-14, atol=1e-20)
