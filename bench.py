@@ -1,0 +1,199 @@
+"""Benchmark of the exponential Rosenbrock-Euler transient on one MI355X.
+
+Workload (default "batch"): 256 variants of a 200-stage CMOS inverter chain
+(4,201 nodes each, identical sparsity; R/C x U(0.9,1.1), V_th + N(0, 20 mV),
+input delay U(0, 0.5 ns)) plus 64 chains of U{50..400} stages, 4 ns
+transients at E_rr = 1e-6 V, every instance stepped by the GPU library in
+one launch.  A bench step is one whole transient of the batch from its DC
+point (computed on the GPU, untimed) to T.  value = accepted ER steps summed
+over instances per second of wall time.
+
+Also reported: the same library on the single 200-stage chain ("plain", one
+instance), the roofline figures of the transient kernel (algorithmic bytes
+per launch / its HIP-event duration), and the oracle's CPU throughput on a
+bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload batch|chain|mesh]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Rosenbrock-Euler steps/s; batched+learned vs plain at 1e-6 rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    import netgen
+    if name == "batch":
+        nets = netgen.config(4)
+        desc = ("batch: 256 variants of a 200-stage inverter chain (4,201 nodes, shared sparsity) "
+                "+ 64 chains of 50-400 stages; level-1 MOSFETs; T = 4 ns; E_rr = 1e-6 V")
+    elif name == "chain":
+        nets = [netgen.config(2)]
+        desc = "one 200-stage inverter chain (4,201 nodes, 400 MOSFETs); T = 4 ns; E_rr = 1e-6 V"
+    elif name == "mesh":
+        nets = [netgen.config(1)]
+        desc = "RC mesh 32x32 (1,024 nodes), 16 pulse loads; T = 5 ns; E_rr = 1e-6 V"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return nets, desc
+
+
+def algorithmic_bytes(sym, net, info):
+    """Bytes an ideal implementation moves for the recorded work of one
+    instance (8-byte values, 4-byte indices): refactor and assembly per LU;
+    the three right-hand sides per step; SpMV + solve pair + vector traffic per
+    Arnoldi step; one read of v_i per Gram-Schmidt product; one read of each
+    combined basis column; re-stamp, dF solve and basis start per trial."""
+    n = net.n
+    zLU = sym["lu_col"].size
+    zG = net.G.nnz
+    zC = net.C.nnz
+    D = net.n_dev
+    b = info["lu_count"] * (20 * zLU + 12 * zG + 100 * D)
+    b += info["steps"] * (12 * zG + 36 * zLU + 12 * zC + 80 * n)
+    b += info["arnoldi"] * (12 * zC + 12 * zLU + 40 * n)
+    b += info["mgs_terms"] * 8 * n
+    b += info["comb_terms"] * 8 * n
+    b += info["trials"] * (64 * n + 100 * D + 12 * zLU)
+    return b
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle on the 200-stage chain from its DC point, single thread:
+    a 20-step probe sizes a run of about budget_s seconds, which is timed."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    import netgen
+    from oracle import Oracle
+    net = netgen.config(2)
+    x0 = Oracle(net).dc()
+    t = time.perf_counter()
+    Oracle(net).run(x0, keep=None, max_steps=20)
+    per = (time.perf_counter() - t) / 20
+    n = max(20, int(budget_s / per))
+    o = Oracle(net)
+    t = time.perf_counter()
+    tr = o.run(x0, keep=None, max_steps=n)
+    el = time.perf_counter() - t
+    return {"value": len(tr.t) / el, "unit": "instance-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {len(tr.t)} accepted ER steps of one 200-stage chain (4,201 nodes) "
+                      f"from its DC point ({el:.1f} s), NumPy/SciPy FP64 on one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batch")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is not sharded "
+              f"across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1511_04515_amd as E
+
+    torch.cuda.set_device(0)
+    nets, desc = workload(args.workload)
+    syms = {}
+    for net in nets:
+        key = (net.n, net.G.nnz, net.n_dev)
+        if key not in syms:
+            syms[key] = E.symbolic_analysis(net)
+    s = E.Solver(nets, probes=[np.zeros(0, np.int32)] * len(nets), trace_cap=8192,
+                 block_size=args.block_size)
+    x0 = s.zeros()
+    s.dc(x0)
+    xs = [x.clone() for x in x0]
+
+    def one_run():
+        for x, x_init in zip(xs, x0):
+            x.copy_(x_init)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = s.run(xs, max_steps_per_launch=8192)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, info, s.kernel_time()
+
+    for _ in range(args.warmup):
+        one_run()
+    torch.cuda.synchronize()
+    times, infos, ktimes = [], [], []
+    for _ in range(args.steps):
+        el, info, kt = one_run()
+        times.append(el)
+        infos.append(info)
+        ktimes.append(kt)
+    total_steps = sum(sum(i["steps"] for i in info) for info in infos)
+    elapsed = sum(times)
+    value = total_steps / elapsed
+
+    # roofline of the transient kernel (one launch per run here)
+    info = infos[-1]
+    byts = 0
+    for net, inf in zip(nets, info):
+        byts += algorithmic_bytes(syms[(net.n, net.G.nnz, net.n_dev)], net, inf)
+    ksec, nlaunch = ktimes[-1]
+    per_launch_bytes = byts / max(nlaunch, 1)
+    per_launch_s = ksec / max(nlaunch, 1)
+    achieved = per_launch_bytes / per_launch_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_run",
+            "launches_per_step": nlaunch, "bytes_per_launch": per_launch_bytes,
+            "launch_ms": 1e3 * per_launch_s}
+    phases = {}
+    for inf in info:
+        for k, v in inf["phase_s"].items():
+            phases[k] = phases.get(k, 0.0) + v
+    out = {
+        "metric": METRIC, "value": value, "unit": "instance-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded netgen circuits)",
+        "config": {"workload": desc, "instances": len(nets), "nodes": int(sum(n.n for n in nets)),
+                   "accepted_steps_per_run": int(sum(i["steps"] for i in info)),
+                   "rejected_trials_per_run": int(sum(i["rejects"] for i in info)),
+                   "arnoldi_iterations_per_run": int(sum(i["arnoldi"] for i in info)),
+                   "controller": "plain (paper's alpha/beta rule)",
+                   "block_size": s.opts.block_size or "auto"},
+        "roofline": roof,
+        "phase_share": {k: v / max(sum(phases.values()), 1e-30) for k, v in phases.items()},
+    }
+    s.close()
+    if args.workload == "batch" and not args.no_plain:
+        nets1, _ = workload("chain")
+        s1 = E.Solver(nets1, probes=[np.zeros(0, np.int32)], trace_cap=8192)
+        y0 = s1.zeros()
+        s1.dc(y0)
+        y = [y0[0].clone()]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        inf1 = s1.run(y, max_steps_per_launch=8192)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t
+        out["plain"] = {"workload": "one 200-stage chain, same library", "value": inf1[0]["steps"] / el1,
+                        "unit": "steps/s", "seconds": el1}
+        out["batched_vs_plain"] = value / out["plain"]["value"]
+        s1.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,9 @@ typedef struct {
    * SpMV + triangular solves, 3 modified Gram-Schmidt, 4 Hessenberg
    * exponential and residual, 5 trial update, re-stamp, error set-up */
   double phase_s[6];
+  int32_t trials;     /* step trials (accepted + rejected) */
+  int64_t mgs_terms;  /* Gram-Schmidt inner products (sum over Arnoldi steps of j+1) */
+  int64_t comb_terms; /* Krylov basis columns combined into x_{k+1} and e_rr */
 } expri_run_info;
 
 /* Trace record layout (doubles): t, h, h_try, m, m_err, rejects, err_inf,
@@ -194,6 +197,11 @@ expri_status expri_step(expri_ctx *ctx, double *const *x, double t, double h,
 /* Copy up to cap trace records of instance inst (host buffer of
  * cap * (EXPRI_REC_FIXED + n_probe) doubles); *n_rec = records available. */
 expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_t cap, int64_t *n_rec);
+
+/* Summed device duration (HIP events on the context's stream) of the
+ * transient-kernel launches of the last expri_run / expri_run_schedule /
+ * expri_step call, and their number. */
+expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *launches);
 
 /* Counters of the last transient / DC call of instance inst. */
 expri_status expri_get_run_info(const expri_ctx *ctx, int32_t inst, expri_run_info *info);

@@ -26,7 +26,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -
 ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_workspace_size", "expri_bind_workspace",
                 "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run",
                 "expri_run_schedule", "expri_step", "expri_trace", "expri_get_run_info",
-                "expri_lu_pattern", "expri_lu_values", "expri_symbolic_create", "expri_symbolic_array",
+                "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_symbolic_create",
+                "expri_symbolic_array",
                 "expri_symbolic_destroy", "expri_last_error", "expri_destroy")
 
 _p = C.c_void_p
@@ -65,7 +66,8 @@ class Opts(C.Structure):
 class RunInfo(C.Structure):
     _fields_ = [("t", C.c_double), ("steps", C.c_int32), ("lu_count", C.c_int32),
                 ("rejects", C.c_int32), ("arnoldi", C.c_int32), ("status", C.c_int32),
-                ("phase_s", C.c_double * 6)]
+                ("phase_s", C.c_double * 6), ("trials", C.c_int32), ("mgs_terms", C.c_int64),
+                ("comb_terms", C.c_int64)]
 
 
 PHASES = ("factor", "rhs", "arnoldi_solve", "mgs", "hess_phi", "trial")
@@ -106,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "expri_lu_pattern": ([_p, C.c_int32, _i32p, _i32p, _i32p, C.POINTER(C.c_int64), _i32p, _i32p,
                               C.POINTER(C.c_int64)], C.c_int),
         "expri_lu_values": ([_p, C.c_int32, _f64p], C.c_int),
+        "expri_kernel_time": ([_p, _f64p, _i32p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
         "expri_symbolic_array": ([_p, C.c_char_p, _i32p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
         "expri_symbolic_destroy": ([_p], None),
@@ -311,7 +314,8 @@ class Solver:
     def _info_dict(r):
         return {"t": r.t, "steps": r.steps, "lu_count": r.lu_count, "rejects": r.rejects,
                 "arnoldi": r.arnoldi, "status": r.status,
-                "phase_s": dict(zip(PHASES, list(r.phase_s)))}
+                "phase_s": dict(zip(PHASES, list(r.phase_s))), "trials": r.trials,
+                "mgs_terms": r.mgs_terms, "comb_terms": r.comb_terms}
 
     def run_info(self, inst: int):
         r = RunInfo()
@@ -329,6 +333,13 @@ class Solver:
         out = {k: buf[:, i] for i, k in enumerate(REC_FIELDS)}
         out["x"] = buf[:, REC_FIXED:]
         return out
+
+    def kernel_time(self):
+        """(seconds, launches) of the transient kernel in the last run call."""
+        sec = C.c_double()
+        n = C.c_int32()
+        self._check(self.lib.expri_kernel_time(self.ctx, C.byref(sec), C.byref(n)))
+        return sec.value, n.value
 
     def lu_pattern(self, inst: int):
         nnz = C.c_int64()

@@ -376,10 +376,10 @@ __device__ double *expm_pade13(Lds<BS> &L, double *A, double *buf, int n) {
     cs = nmax(cs, s);
   }
   const double nrm = wg_max(L, cs);
+  // 2^64 theta13 ~ 1e20: beyond that every entry of exp(A) under- or
+  // overflows anyway, and a non-finite norm is caught by the caller
   int s = 0;
-  if (nrm > theta13) s = (int)ceil(log2(nrm / theta13));
-  if (!(s >= 0)) s = 0;         // NaN norm: carry on, the result is checked later
-  if (s > 1000) s = 1000;
+  if (nrm > theta13) s = (nrm < theta13 * 0x1p64) ? (int)ceil(log2(nrm / theta13)) : 64;
   if (s > 0) {
     const double sc = ldexp(1.0, -s);
     for (int i = threadIdx.x; i < nn; i += BS) A[i] *= sc;
@@ -435,6 +435,10 @@ __device__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m
   }
   __syncthreads();
   lu_solve<BS>(L, P, M, m, m);  // M = h H^{-1}
+  double mbad = 0.0;
+  for (int i = threadIdx.x; i < m * m; i += BS)
+    if (!isfinite(M[i])) mbad = 1.0;
+  if (wg_max(L, mbad) != 0.0) return INFINITY;  // H_m singular: not converged
   for (int i = threadIdx.x; i < n1 * n1; i += BS) {
     const int r = i / n1, c = i - r * n1;
     double v = 0.0;
@@ -471,6 +475,11 @@ struct Basis {
   int exact;
   double beta;
   double hscale;
+};
+
+struct Work {  // exact work counters of one launch
+  int64_t mgs, comb;
+  int trials;
 };
 
 // one Arnoldi step j = B.m: solve -G w = C v_j, MGS against v_0..v_j,
@@ -530,7 +539,7 @@ __device__ void basis_start(const InstDesc &D, Lds<BS> &L, const double *v, doub
 template <int BS>
 __device__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, double *V, double *H,
                              Basis &B, double h, double eps, double *dout, double &rho,
-                             int &iters, Prof &pf) {
+                             int &iters, Prof &pf, Work &wk) {
   if (B.beta == 0.0) {
     rho = 0.0;
     return kOK;
@@ -545,6 +554,7 @@ __device__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, doubl
     if (B.m >= o.m_max) return kEKRYLOV;
     arnoldi_step<BS>(D, L, V, H, B, o.breakdown, pf);
     ++iters;
+    wk.mgs += B.m;
     rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : H[B.m + (B.m - 1) * kHLd], dout);
     pf.mark(4);
     if (rho <= eps) return kOK;
@@ -586,6 +596,9 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
     S.rejects = 0;
     S.arnoldi = 0;
     S.lu_valid = 0;
+    S.trials = 0;
+    S.mgs_terms = 0;
+    S.comb_terms = 0;
     for (int i = 0; i < kPhases; ++i) S.ph[i] = 0.0;
     int b = 0;
     while (b < D.n_bp - 1 && D.bp[b] <= t0) ++b;
@@ -620,6 +633,7 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
   const int rec = kRecFixed + D.n_probe;
   Prof pf;
   pf.start();
+  Work wk{0, 0, 0};
 
   for (int it = 0; it < max_steps; ++it) {
     if (replay ? (steps >= D.n_bp) : !(t < D.T)) {
@@ -688,8 +702,10 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
     double h = h_try, rho = 0.0, err = 0.0;
     int rej = 0, m_err = 0;
     for (;;) {
-      status = mevp_converge<BS>(D, L, o, D.V, D.H, Bm, h, o.eps_K, L.dmain, rho, iters, pf);
+      ++wk.trials;
+      status = mevp_converge<BS>(D, L, o, D.V, D.H, Bm, h, o.eps_K, L.dmain, rho, iters, pf, wk);
       if (status != kOK) break;
+      wk.comb += Bm.m;
       // x_{k+1} = x_k + h p + beta V_m d
       double bad = 0.0;
       for (int i = threadIdx.x; i < n; i += BS) {
@@ -726,9 +742,10 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
         basis_start<BS>(D, L, xs, D.Ve, Be);
         pf.mark(5);
         double rho_e;
-        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf);
+        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk);
         if (status != kOK) break;
         m_err = Be.m;
+        wk.comb += Be.m;
         double emax = 0.0;
         for (int i = threadIdx.x; i < n; i += BS) {
           double acc = 0.0;
@@ -771,6 +788,9 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
     S.rejects = rej_total;
     S.arnoldi = iters;
     S.lu_valid = lu_valid;
+    S.trials += wk.trials;
+    S.mgs_terms += wk.mgs;
+    S.comb_terms += wk.comb;
 #pragma unroll
     for (int i = 0; i < kPhases; ++i) S.ph[i] += (double)pf.acc[i];
     if (status != kOK) {
@@ -878,7 +898,8 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
   int iters = 0;
   Prof pf;
   pf.start();
-  const int st = mevp_converge<BS>(D, L, o, D.V, D.H, B, h, eps, L.dmain, rho, iters, pf);
+  Work wk{0, 0, 0};
+  const int st = mevp_converge<BS>(D, L, o, D.V, D.H, B, h, eps, L.dmain, rho, iters, pf, wk);
   for (int i = threadIdx.x; i < D.n; i += BS) {
     double acc = 0.0;
     for (int j = 0; j < B.m; ++j) acc += D.V[(int64_t)j * D.ldv + i] * L.dmain[j];

@@ -94,6 +94,9 @@ struct expri_ctx {
   void **d_ptrs = nullptr;  // 4 * n_inst device pointers
   int bs = 512, R = 8192;
   double wall_hz = 1e8;  // GPU wall-clock counter rate
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double run_kernel_s = 0.0;  // summed duration of the k_run launches of the last call
+  int32_t run_launches = 0;
   std::string err;
 };
 
@@ -320,14 +323,22 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
   HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t0, c->opts.h_init,
                          c->stream));
   for (auto &I : c->inst) I.trace_host.clear();
+  c->run_kernel_s = 0.0;
+  c->run_launches = 0;
   std::vector<int32_t> prev(n, 0);
   std::vector<InstState> st;
   const int64_t max_launches = kMaxRunSteps / max_steps + 1;
   for (int64_t launches = 0;; ++launches) {
     if (launches >= max_launches)
       return fail(c, EXPRI_ESTEPMIN, "step budget of " + std::to_string(kMaxRunSteps) + " accepted steps exhausted");
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_run(c->d_desc, n, ko, max_steps, replay, c->bs, c->R, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     if ((s = read_states(c, st)) != EXPRI_OK) return s;
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->run_kernel_s += 1e-3 * ms;
+    ++c->run_launches;
     bool all = true;
     for (int k = 0; k < n; ++k) {
       Inst &I = c->inst[k];
@@ -356,6 +367,9 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
     in.arnoldi = st[k].arnoldi;
     in.status = st[k].status;
     for (int p = 0; p < 6; ++p) in.phase_s[p] = st[k].ph[p] / c->wall_hz;
+    in.trials = st[k].trials;
+    in.mgs_terms = st[k].mgs_terms;
+    in.comb_terms = st[k].comb_terms;
   }
   return first_error(c, st, "transient");
 }
@@ -533,6 +547,9 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     return EXPRI_EINVAL;
   }
   c->R = (int)R;
+  e = hipEventCreate(&c->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "event create"); }
   e = set_lds_limits(lds_bytes(c->bs, c->R));
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "LDS limit"); }
   c->ws_bytes = layout_workspace(c.get());
@@ -570,7 +587,8 @@ expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   // write back only instances that converged (x keeps its input otherwise)
   for (int k = 0; k < n; ++k) {
-    c->inst[k].info = expri_run_info{t0, st[k].steps, st[k].steps, 0, 0, st[k].status, {0, 0, 0, 0, 0, 0}};
+    c->inst[k].info = expri_run_info{t0, st[k].steps, st[k].steps, 0, 0, st[k].status, {0, 0, 0, 0, 0, 0},
+                                     0, 0, 0};
   }
   if ((s = first_error(c, st, "DC")) != EXPRI_OK) return s;
   HIPCHK(c, launch_end(c->d_desc, n, reinterpret_cast<double *const *>(c->d_ptrs), c->stream));
@@ -725,6 +743,13 @@ expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
   return EXPRI_OK;
 }
 
+expri_status expri_kernel_time(const expri_ctx *c, double *seconds, int32_t *launches) {
+  if (!c || !seconds || !launches) return EXPRI_EINVAL;
+  *seconds = c->run_kernel_s;
+  *launches = c->run_launches;
+  return EXPRI_OK;
+}
+
 const char *expri_last_error(const expri_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void expri_destroy(expri_ctx *c) {
@@ -733,6 +758,8 @@ void expri_destroy(expri_ctx *c) {
   if (c->d_const) (void)hipFree(c->d_const);
   if (c->d_desc) (void)hipFree(c->d_desc);
   if (c->d_ptrs) (void)hipFree(c->d_ptrs);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
 }
 

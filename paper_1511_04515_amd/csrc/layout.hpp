@@ -40,6 +40,10 @@ struct InstState {
   int32_t rejects;    // total rejected trials
   int32_t arnoldi;    // total Arnoldi iterations
   int32_t lu_valid;   // factors of G_k are current (linear circuits keep them)
+  int32_t trials;     // step trials (accepted + rejected)
+  int32_t pad1;
+  int64_t mgs_terms;  // inner products of modified Gram-Schmidt (sum of j+1)
+  int64_t comb_terms; // basis columns combined into x_{k+1} and e_rr
   // wall-clock ticks per phase: factor, rhs, arnoldi solve, mgs, phi, trial
   double ph[kPhases];
 };
