@@ -130,15 +130,21 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t, info, s.kernel_time()
 
-    for _ in range(args.warmup):
-        one_run()
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"{args.workload}: {len(nets)} instances, {sum(n.n for n in nets)} nodes, block size {s.bs}")
+    for w in range(args.warmup):
+        el, _, _ = one_run()
+        log(f"warmup {w}: {el:.2f} s")
     torch.cuda.synchronize()
     times, infos, ktimes = [], [], []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         el, info, kt = one_run()
         times.append(el)
         infos.append(info)
         ktimes.append(kt)
+        log(f"step {k}: {el:.2f} s, {sum(i['steps'] for i in info)} accepted ER steps")
     total_steps = sum(sum(i["steps"] for i in info) for info in infos)
     elapsed = sum(times)
     value = total_steps / elapsed
@@ -170,7 +176,7 @@ def main():
                    "rejected_trials_per_run": int(sum(i["rejects"] for i in info)),
                    "arnoldi_iterations_per_run": int(sum(i["arnoldi"] for i in info)),
                    "controller": "plain (paper's alpha/beta rule)",
-                   "block_size": s.opts.block_size or "auto"},
+                   "block_size": s.bs},
         "roofline": roof,
         "phase_share": {k: v / max(sum(phases.values()), 1e-30) for k, v in phases.items()},
     }

@@ -203,6 +203,17 @@ expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_
  * expri_step call, and their number. */
 expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *launches);
 
+/* Diagnostic: device time (seconds per repetition, GPU wall clock) of one
+ * building block of the step on instance 0's current factors and vectors:
+ * what = 0 full G_k solve, 1 L solve, 2 U solve, 3 C SpMV, 4 workgroup
+ * reduction, 5 the solve's level loop with barriers only, 6 one
+ * Gram-Schmidt sweep over 9 basis vectors. */
+expri_status expri_diag_time(expri_ctx *ctx, int32_t what, int32_t reps, double *seconds);
+
+/* Threads per workgroup the kernels are launched with (one workgroup per
+ * instance). */
+expri_status expri_block_size(const expri_ctx *ctx, int32_t *bs);
+
 /* Counters of the last transient / DC call of instance inst. */
 expri_status expri_get_run_info(const expri_ctx *ctx, int32_t inst, expri_run_info *info);
 
@@ -228,6 +239,11 @@ expri_status expri_lu_values(const expri_ctx *ctx, int32_t inst, double *out);
  * full length.  EINVAL for an unknown name. */
 typedef struct expri_symbolic expri_symbolic;
 expri_status expri_symbolic_create(expri_symbolic **sym, const expri_circuit *ckt);
+/* Build the flattened solve schedules for block size bs (256, 512, 1024),
+ * exposed as arrays "lsched" / "usched" (6 ints per level: G, P, passes, 0,
+ * slot_base, row_base), "slot_pos", "slot_col", "row_of" and "c_ell_col"
+ * (ELL pattern of C, followed by its width). */
+expri_status expri_symbolic_schedule(expri_symbolic *sym, int32_t bs);
 expri_status expri_symbolic_array(const expri_symbolic *sym, const char *name, int32_t *out, int64_t cap,
                                   int64_t *len);
 void expri_symbolic_destroy(expri_symbolic *sym);

@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -
 ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_workspace_size", "expri_bind_workspace",
                 "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run",
                 "expri_run_schedule", "expri_step", "expri_trace", "expri_get_run_info",
-                "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_symbolic_create",
+                "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_block_size", "expri_diag_time", "expri_symbolic_create",
                 "expri_symbolic_array",
                 "expri_symbolic_destroy", "expri_last_error", "expri_destroy")
 
@@ -109,8 +109,11 @@ def load_library(path: str = LIB_PATH):
                               C.POINTER(C.c_int64)], C.c_int),
         "expri_lu_values": ([_p, C.c_int32, _f64p], C.c_int),
         "expri_kernel_time": ([_p, _f64p, _i32p], C.c_int),
+        "expri_block_size": ([_p, _i32p], C.c_int),
+        "expri_diag_time": ([_p, C.c_int32, C.c_int32, _f64p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
         "expri_symbolic_array": ([_p, C.c_char_p, _i32p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+        "expri_symbolic_schedule": ([_p, C.c_int32], C.c_int),
         "expri_symbolic_destroy": ([_p], None),
         "expri_last_error": ([_p], C.c_char_p),
         "expri_destroy": ([_p], None),
@@ -244,6 +247,9 @@ class Solver:
         base = self._ws.data_ptr()
         aligned = (base + 255) // 256 * 256
         self._check(self.lib.expri_bind_workspace(self.ctx, C.c_void_p(aligned), C.c_size_t(self.ws_bytes)))
+        bs = C.c_int32()
+        self._check(self.lib.expri_block_size(self.ctx, C.byref(bs)))
+        self.bs = bs.value
 
     # -- helpers ---------------------------------------------------------
     def _check(self, st):
@@ -334,6 +340,12 @@ class Solver:
         out["x"] = buf[:, REC_FIXED:]
         return out
 
+    def diag_time(self, what: int, reps: int = 100) -> float:
+        """Seconds per repetition of one step building block (see expri.h)."""
+        sec = C.c_double()
+        self._check(self.lib.expri_diag_time(self.ctx, what, reps, C.byref(sec)))
+        return sec.value
+
     def kernel_time(self):
         """(seconds, launches) of the transient kernel in the last run call."""
         sec = C.c_double()
@@ -384,9 +396,13 @@ SYMBOLIC_ARRAYS = ("perm", "lu_rowptr", "lu_col", "lu_diag", "lev_ptr", "lev_row
                    "block_of")
 
 
-def symbolic_analysis(net) -> dict:
+SCHEDULE_ARRAYS = ("lsched", "usched", "slot_pos", "slot_col", "row_of", "c_ell_col")
+
+
+def symbolic_analysis(net, block_size: int | None = None) -> dict:
     """Host-only symbolic analysis of one netlist (no GPU): every integer
-    array the kernels are driven by, by name."""
+    array the kernels are driven by, by name; with block_size also the
+    flattened solve schedules built for that launch block size."""
     lib = load_library()
     m = _Marshal()
     k = m.circuit(net)
@@ -396,7 +412,13 @@ def symbolic_analysis(net) -> dict:
         raise ExpriError(st, "symbolic analysis failed")
     out = {}
     try:
-        for name in SYMBOLIC_ARRAYS:
+        names = SYMBOLIC_ARRAYS
+        if block_size is not None:
+            st = lib.expri_symbolic_schedule(h, int(block_size))
+            if st != 0:
+                raise ExpriError(st, "schedule build failed")
+            names = SYMBOLIC_ARRAYS + SCHEDULE_ARRAYS
+        for name in names:
             n = C.c_int64()
             lib.expri_symbolic_array(h, name.encode(), None, 0, C.byref(n))
             a = np.zeros(max(n.value, 1), np.int32)

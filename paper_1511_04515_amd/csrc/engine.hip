@@ -28,10 +28,34 @@ namespace expri {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// Wave-wide reductions on the DPP network: a butterfly inside each 16-lane
+// row (pairs of lanes 1 and 2 apart, then the 8- and 16-lane mirrors), then
+// the four row results read out in a fixed order.  Every lane ends with the
+// bit-identical value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i in each 8 lanes
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i in each 16 lanes
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  v += dpp_d<kDppHalfMirror>(v);
+  v += dpp_d<kDppMirror>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // max that propagates NaN
@@ -40,8 +64,22 @@ __device__ __forceinline__ double nmax(double a, double b) {
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = nmax(v, __shfl_xor(v, o, 64));
+  v = nmax(v, dpp_d<kDppXor1>(v));
+  v = nmax(v, dpp_d<kDppXor2>(v));
+  v = nmax(v, dpp_d<kDppHalfMirror>(v));
+  v = nmax(v, dpp_d<kDppMirror>(v));
+  return nmax(nmax(readlane_d(v, 0), readlane_d(v, 16)), nmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+// sum over aligned groups of G lanes (G a power of two <= 64); the group's
+// lanes end with the same value
+__device__ __forceinline__ double group_sum(double v, int G) {
+  if (G >= 2) v += dpp_d<kDppXor1>(v);
+  if (G >= 4) v += dpp_d<kDppXor2>(v);
+  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+  if (G >= 16) v += dpp_d<kDppMirror>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -56,7 +94,10 @@ struct Lds {
   double *slots;
   double *dmain;
   double *derr;
-  int *ipiv;
+  int *ipiv;   // 4 ints of pivot exchange
+  double *bc;  // 1 double of broadcast from wave 0
+  double *hcol; // kHLd doubles: current Hessenberg column
+  long long *prof;  // kPhases phase counters
   int R;
   int par;
 };
@@ -92,16 +133,16 @@ __device__ __forceinline__ double wg_max(Lds<BS> &L, double v) {
 // 2 Arnoldi SpMV + solve, 3 modified Gram-Schmidt, 4 Hessenberg exponential,
 // 5 trial update, device re-stamp and error-estimate set-up.
 struct Prof {
-  long long acc[kPhases];
+  long long *acc;  // kPhases counters in LDS, updated by the first thread
   long long last;
-  __device__ void start() {
-#pragma unroll
-    for (int i = 0; i < kPhases; ++i) acc[i] = 0;
+  __device__ void start(long long *lds) {
+    acc = lds;
+    if (threadIdx.x < kPhases) acc[threadIdx.x] = 0;
     last = wall_clock64();
   }
   __device__ __forceinline__ void mark(int p) {
     const long long now = wall_clock64();
-    acc[p] += now - last;
+    if (threadIdx.x == 0) acc[p] += now - last;
     last = now;
   }
 };
@@ -258,9 +299,9 @@ __device__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
   return wg_max(L, (double)bad) == 0.0;
 }
 
-// in-place solve G_k y = b with b (and then y) in LDS vector xs
+// row-wise (CSR) level-scheduled solve: one thread per row
 template <int BS>
-__device__ void solve_lds(const InstDesc &D, double *xs) {
+__device__ void solve_lds_rows(const InstDesc &D, double *xs) {
   const double *a = D.lu;
   for (int lv = 0; lv < D.n_lev; ++lv) {
     for (int q = D.lev_ptr[lv] + threadIdx.x; q < D.lev_ptr[lv + 1]; q += BS) {
@@ -283,11 +324,302 @@ __device__ void solve_lds(const InstDesc &D, double *xs) {
   }
 }
 
+// in-place solve G_k y = b with b (and then y) in LDS vector xs, following
+// the flattened level schedules: on every level the rows are handled by
+// groups of G lanes, lane t of the block reading slots (q P + j) BS + t of the
+// level (coalesced index and position arrays; the L\U values are gathered);
+// group partial sums meet in a butterfly over the group's lanes.
+// one pass of one level: lane t multiplies its (at most kSlots) entries;
+// every load is issued before the first product is formed
+constexpr int kSlots = 8;
+template <int BS>
+__device__ __forceinline__ double level_pass(const double *__restrict__ a, const int *__restrict__ spos,
+                                             const int *__restrict__ scol, const double *xs, int base,
+                                             int P) {
+  int pos[kSlots], col[kSlots];
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j) {
+    pos[j] = j < P ? spos[base + j * BS] : -1;
+    col[j] = j < P ? scol[base + j * BS] : 0;
+  }
+  double av[kSlots], xv[kSlots];
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j) {
+    av[j] = pos[j] >= 0 ? a[pos[j]] : 0.0;
+    xv[j] = pos[j] >= 0 ? xs[col[j]] : 0.0;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j) acc += av[j] * xv[j];
+  return acc;
+}
+
+template <int BS>
+__device__ void solve_lds(const InstDesc &D, double *xs, int variant = 0) {
+  if (variant & 4) {
+    solve_lds_rows<BS>(D, xs);
+    return;
+  }
+  // descriptor fields in registers (a barrier would otherwise make the
+  // compiler reload them from memory on every level)
+  const double *__restrict__ a = D.lu;
+  const SolveLevel *__restrict__ ls = D.lsched;
+  const SolveLevel *__restrict__ us = D.usched;
+  const int *__restrict__ spos = D.slot_pos;
+  const int *__restrict__ scol = D.slot_col;
+  const int *__restrict__ rowof = D.row_of;
+  const int *__restrict__ diag = D.lu_diag;
+  const int nl = D.n_lsched, nu = D.n_usched;
+  const int t = threadIdx.x;
+  for (int l = 0; l < nl; ++l) {
+    const SolveLevel S = ls[l];
+    for (int q = 0; q < S.passes; ++q) {
+      double acc = level_pass<BS>(a, spos, scol, xs, S.slot_base + q * S.P * BS + t, S.P);
+      acc = group_sum(acc, S.G);
+      if ((t & (S.G - 1)) == 0) {
+        const int r = rowof[S.row_base + q * (BS / S.G) + t / S.G];
+        if (r >= 0) xs[r] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int l = 0; l < nu; ++l) {
+    const SolveLevel S = us[l];
+    for (int q = 0; q < S.passes; ++q) {
+      const int ridx = S.row_base + q * (BS / S.G) + t / S.G;
+      const int r = rowof[ridx];
+      const double dv = r >= 0 ? a[diag[r]] : 1.0;
+      double acc = level_pass<BS>(a, spos, scol, xs, S.slot_base + q * S.P * BS + t, S.P);
+      acc = group_sum(acc, S.G);
+      if ((t & (S.G - 1)) == 0 && r >= 0) xs[r] = (xs[r] - acc) / dv;
+    }
+    __syncthreads();
+  }
+}
+
+// (C v)_i from the ELL copy of C (entries in the CSR order of the row)
+__device__ __forceinline__ double c_row(const InstDesc &D, const double *v, int i) {
+  double s = 0.0;
+  for (int k = 0; k < D.c_ell_k; ++k) {
+    const int c = D.c_ell_col[(int64_t)k * D.n + i];
+    if (c >= 0) s += D.c_ell_val[(int64_t)k * D.n + i] * v[c];
+  }
+  return s;
+}
+
 __device__ __forceinline__ double csr_row_dot(const int *rp, const int *ci, const double *val,
                                               const double *v, int i) {
   double s = 0.0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) s += val[e] * v[ci[e]];
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// The same small-matrix algebra executed by one wave (wave 0) for
+// n <= 32: lanes own matrix columns, matrices live in LDS, and a wavefront
+// fence orders the LDS traffic between phases (a wave's LDS operations
+// complete in order).  No workgroup barrier is needed inside.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Solve P X = Q (n x n, nrhs columns; LDS) by Gaussian elimination with
+// partial pivoting (largest magnitude, first on ties); Q <- X.  Lane c owns
+// the columns c, c + 64, ... of [P | Q].
+__device__ void w_lu_solve(double *P, double *Q, int n, int nrhs, int lane) {
+  const int ncol = n + nrhs;
+  for (int k = 0; k < n; ++k) {
+    wfence();
+    int pr = k;
+    double best = fabs(P[k * n + k]);
+    for (int r = k + 1; r < n; ++r) {
+      const double v = fabs(P[r * n + k]);
+      if (v > best) { best = v; pr = r; }
+    }
+    if (pr != k)
+      for (int c = lane; c < ncol; c += 64) {
+        double *A = c < n ? P : Q;
+        const int cc = c < n ? c : c - n, ld = c < n ? n : nrhs;
+        const double t = A[k * ld + cc];
+        A[k * ld + cc] = A[pr * ld + cc];
+        A[pr * ld + cc] = t;
+      }
+    wfence();
+    const double piv = P[k * n + k];
+    for (int r = k + 1; r < n; ++r) {
+      const double l = P[r * n + k] / piv;
+      for (int c = lane; c < ncol; c += 64) {
+        if (c < n) {
+          if (c > k) P[r * n + c] -= l * P[k * n + c];
+        } else {
+          Q[r * nrhs + (c - n)] -= l * Q[k * nrhs + (c - n)];
+        }
+      }
+    }
+  }
+  wfence();
+  for (int c = lane; c < nrhs; c += 64)
+    for (int r = n - 1; r >= 0; --r) {
+      double sacc = Q[r * nrhs + c];
+      for (int j = r + 1; j < n; ++j) sacc -= P[r * n + j] * Q[j * nrhs + c];
+      Q[r * nrhs + c] = sacc / P[r * n + r];
+    }
+  wfence();
+}
+
+// Solve P X = Q for upper Hessenberg P (n x n, LDS): partial pivoting only
+// ever compares rows k and k+1, so each elimination step touches one row.
+__device__ void w_hess_solve(double *P, double *Q, int n, int nrhs, int lane) {
+  const int ncol = n + nrhs;
+  for (int k = 0; k + 1 < n; ++k) {
+    wfence();
+    const bool sw = fabs(P[(k + 1) * n + k]) > fabs(P[k * n + k]);
+    if (sw)
+      for (int c = lane; c < ncol; c += 64) {
+        double *A = c < n ? P : Q;
+        const int cc = c < n ? c : c - n, ld = c < n ? n : nrhs;
+        const double t = A[k * ld + cc];
+        A[k * ld + cc] = A[(k + 1) * ld + cc];
+        A[(k + 1) * ld + cc] = t;
+      }
+    wfence();
+    const double l = P[(k + 1) * n + k] / P[k * n + k];
+    for (int c = lane; c < ncol; c += 64) {
+      if (c < n) {
+        if (c > k) P[(k + 1) * n + c] -= l * P[k * n + c];
+      } else {
+        Q[(k + 1) * nrhs + (c - n)] -= l * Q[k * nrhs + (c - n)];
+      }
+    }
+  }
+  wfence();
+  for (int c = lane; c < nrhs; c += 64)
+    for (int r = n - 1; r >= 0; --r) {
+      double sacc = Q[r * nrhs + c];
+      for (int j = r + 1; j < n; ++j) sacc -= P[r * n + j] * Q[j * nrhs + c];
+      Q[r * nrhs + c] = sacc / P[r * n + r];
+    }
+  wfence();
+}
+
+// C = A B (n x n, n <= 32): lane -> column (lane & 31), half of the rows.
+__device__ __forceinline__ void w_mat_mul(const double *A, const double *B, double *C, int n, int lane) {
+  wfence();
+  const int c = lane & 31, half = (n + 1) >> 1;
+  const int r0 = (lane >> 5) ? half : 0, r1 = (lane >> 5) ? n : half;
+  if (c < n)
+    for (int r = r0; r < r1; ++r) {
+      double sacc = 0.0;
+      for (int k = 0; k < n; ++k) sacc += A[r * n + k] * B[k * n + c];
+      C[r * n + c] = sacc;
+    }
+  wfence();
+}
+
+__device__ __forceinline__ double w_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = nmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// exp(A) by scaling and squaring with the degree-13 Pade approximant in one
+// wave; buf holds 5 n x n matrices; returns the matrix holding exp(A).
+__device__ double *w_expm_pade13(double *A, double *buf, int n, int lane) {
+  const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
+                        1187353796428800.0,  129060195264000.0,   10559470521600.0,
+                        670442572800.0,      33522128640.0,       1323241920.0,
+                        40840800.0,          960960.0,            16380.0,
+                        182.0,               1.0};
+  const double theta13 = 5.371920351148152;
+  const int nn = n * n;
+  double *A2 = buf, *A4 = buf + nn, *A6 = buf + 2 * nn, *T1 = buf + 3 * nn, *T2 = buf + 4 * nn;
+  wfence();
+  double cs = 0.0;
+  if (lane < n)
+    for (int r = 0; r < n; ++r) cs += fabs(A[r * n + lane]);
+  const double nrm = w_max(cs);
+  int s = 0;
+  if (nrm > theta13) s = (nrm < theta13 * 0x1p64) ? (int)ceil(log2(nrm / theta13)) : 64;
+  if (s > 0) {
+    const double sc = ldexp(1.0, -s);
+    for (int i = lane; i < nn; i += 64) A[i] *= sc;
+  }
+  w_mat_mul(A, A, A2, n, lane);
+  w_mat_mul(A2, A2, A4, n, lane);
+  w_mat_mul(A4, A2, A6, n, lane);
+  for (int i = lane; i < nn; i += 64) T1[i] = b[13] * A6[i] + b[11] * A4[i] + b[9] * A2[i];
+  w_mat_mul(A6, T1, T2, n, lane);
+  for (int i = lane; i < nn; i += 64) {
+    const int r = i / n, c = i - r * n;
+    T2[i] += b[7] * A6[i] + b[5] * A4[i] + b[3] * A2[i] + (r == c ? b[1] : 0.0);
+  }
+  w_mat_mul(A, T2, T1, n, lane);  // T1 = U
+  for (int i = lane; i < nn; i += 64) T2[i] = b[12] * A6[i] + b[10] * A4[i] + b[8] * A2[i];
+  w_mat_mul(A6, T2, A, n, lane);
+  for (int i = lane; i < nn; i += 64) {
+    const int r = i / n, c = i - r * n;
+    const double V = A[i] + b[6] * A6[i] + b[4] * A4[i] + b[2] * A2[i] + (r == c ? b[0] : 0.0);
+    A2[i] = V - T1[i];
+    A4[i] = V + T1[i];
+  }
+  w_lu_solve(A2, A4, n, n, lane);
+  double *X = A4, *Y = A6;
+  for (int k = 0; k < s; ++k) {
+    w_mat_mul(X, X, Y, n, lane);
+    double *t = X; X = Y; Y = t;
+  }
+  return X;
+}
+
+// One-wave version of hess_phi for m + 1 <= 32 (R holds 7 (m+1)^2 doubles in
+// LDS).  Wave 0 computes; the result is broadcast through LDS.
+template <int BS>
+__device__ double hess_phi_wave(Lds<BS> &L, const double *H, int m, double h, double beta,
+                                double h_next, double *dout) {
+  const int n1 = m + 1;
+  double *M = L.region, *Aug = L.region + n1 * n1, *buf = L.region + 2 * n1 * n1;
+  double *bcast = L.bc;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double *P = Aug;
+    if (lane < m)
+      for (int r = 0; r < m; ++r) {
+        P[r * m + lane] = (r <= lane + 1) ? H[r + lane * kHLd] : 0.0;
+        M[r * m + lane] = (r == lane) ? h : 0.0;
+      }
+    w_lu_solve(P, M, m, m, lane);  // M = h H^{-1}
+    double bad = 0.0;
+    for (int i = lane; i < m * m; i += 64)
+      if (!isfinite(M[i])) bad = 1.0;
+    double rho = INFINITY;
+    if (w_max(bad) == 0.0) {
+      for (int i = lane; i < n1 * n1; i += 64) {
+        const int r = i / n1, c = i - r * n1;
+        double v = 0.0;
+        if (r < m && c < m) v = M[r * m + c];
+        else if (r == 0 && c == m) v = 1.0;
+        Aug[i] = v;
+      }
+      const double *E = w_expm_pade13(Aug, buf, n1, lane);
+      double part = 0.0;
+      bad = 0.0;
+      if (lane < m) {
+        double sacc = 0.0;
+        for (int c = 0; c < m; ++c) sacc += M[lane * m + c] * E[c * n1 + m];
+        dout[lane] = -sacc;
+        if (!isfinite(sacc)) bad = 1.0;
+        part = M[(m - 1) * m + lane] * E[lane * n1];
+      }
+      const double my = wave_sum(part);
+      rho = beta * h_next * fabs(my / h);
+      if (w_max(bad) != 0.0 || !isfinite(rho)) rho = INFINITY;
+    }
+    if (lane == 0) bcast[0] = rho;
+  }
+  __syncthreads();
+  const double rho = bcast[0];
+  __syncthreads();
+  return rho;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,7 +691,7 @@ __device__ void lu_solve(Lds<BS> &L, double *P, double *Q, int n, int nrhs) {
 // (Higham, SIAM J. Matrix Anal. Appl. 26(4), 2005).  buf holds 6 n x n
 // matrices; A is destroyed; returns the matrix holding exp(A).
 template <int BS>
-__device__ double *expm_pade13(Lds<BS> &L, double *A, double *buf, int n) {
+__device__ double *expm_pade13(Lds<BS> &L, double *A, double *buf, int n, bool in_lds) {
   const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
                         1187353796428800.0,  129060195264000.0,   10559470521600.0,
                         670442572800.0,      33522128640.0,       1323241920.0,
@@ -407,7 +739,12 @@ __device__ double *expm_pade13(Lds<BS> &L, double *A, double *buf, int n) {
     A4[i] = V + T1[i];  // Q = V + U
   }
   __syncthreads();
-  lu_solve<BS>(L, A2, A4, n, n);
+  if (in_lds) {  // one wave eliminates: no barrier per pivot step
+    if (threadIdx.x < 64) w_lu_solve(A2, A4, n, n, threadIdx.x);
+    __syncthreads();
+  } else {
+    lu_solve<BS>(L, A2, A4, n, n);
+  }
   double *X = A4, *Y = A6;
   for (int k = 0; k < s; ++k) {
     mat_mul<BS>(X, X, Y, n);
@@ -424,8 +761,11 @@ template <int BS>
 __device__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m, double h,
                            double beta, double h_next, double *dout) {
   const int n1 = m + 1;
+  if ((D.variant & 1) && n1 <= 32 && 7 * n1 * n1 <= L.R)
+    return hess_phi_wave<BS>(L, H, m, h, beta, h_next, dout);
   // 7 matrices of n1 x n1: M, Aug, and 5 work matrices (A2, A4, A6, T1, T2)
-  double *R = (7 * n1 * n1 <= L.R) ? L.region : D.mat;
+  const bool in_lds = 7 * n1 * n1 <= L.R;
+  double *R = in_lds ? L.region : D.mat;
   double *M = R, *Aug = R + n1 * n1, *buf = R + 2 * n1 * n1;
   double *P = Aug;  // H_m copy (m x m) for the inverse, before Aug is built
   for (int i = threadIdx.x; i < m * m; i += BS) {
@@ -434,7 +774,12 @@ __device__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m
     M[i] = (r == c) ? h : 0.0;
   }
   __syncthreads();
-  lu_solve<BS>(L, P, M, m, m);  // M = h H^{-1}
+  if (in_lds) {  // M = h H^{-1}, one wave, Hessenberg elimination
+    if (threadIdx.x < 64) w_hess_solve(P, M, m, m, threadIdx.x);
+    __syncthreads();
+  } else {
+    lu_solve<BS>(L, P, M, m, m);
+  }
   double mbad = 0.0;
   for (int i = threadIdx.x; i < m * m; i += BS)
     if (!isfinite(M[i])) mbad = 1.0;
@@ -447,7 +792,7 @@ __device__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m
     Aug[i] = v;
   }
   __syncthreads();
-  const double *E = expm_pade13<BS>(L, Aug, buf, n1);
+  const double *E = expm_pade13<BS>(L, Aug, buf, n1, in_lds);
   // d = -M f  with f = E[:m, m]
   for (int r = threadIdx.x; r < m; r += BS) {
     double s = 0.0;
@@ -488,35 +833,65 @@ template <int BS>
 __device__ void arnoldi_step(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
                              double breakdown, Prof &pf) {
   const int n = D.n, j = B.m;
+  const int64_t ldv = D.ldv;
   double *xs = L.region;
-  const double *vj = V + (int64_t)j * D.ldv;
-  for (int i = threadIdx.x; i < n; i += BS)
-    xs[i] = -csr_row_dot(D.c_rowptr, D.c_col, D.c_val, vj, i);
+  double *hcol = L.hcol;  // this step's Hessenberg column, stored to H once at the end
+  const double *vj = V + (int64_t)j * ldv;
+  for (int i = threadIdx.x; i < n; i += BS) xs[i] = -c_row(D, vj, i);
   __syncthreads();
-  solve_lds<BS>(D, xs);
+  solve_lds<BS>(D, xs, D.variant);
   pf.mark(2);
-  for (int i = 0; i <= j; ++i) {
-    const double *vi = V + (int64_t)i * D.ldv;
-    double part = 0.0;
-    for (int t = threadIdx.x; t < n; t += BS) part += xs[t] * vi[t];
-    const double hij = wg_sum(L, part);
-    for (int t = threadIdx.x; t < n; t += BS) xs[t] -= hij * vi[t];
-    if (threadIdx.x == 0) H[i + j * kHLd] = hij;
-    B.hscale = nmax(B.hscale, fabs(hij));
+  constexpr int E = (4608 + BS - 1) / BS;  // elements per thread in registers (n <= E * BS)
+  const int t0 = threadIdx.x;
+  if (!(D.variant & 2) && n <= E * BS) {
+    // modified Gram-Schmidt with v_i held in registers for its inner
+    // product and its update, and v_{i+1} loaded before the reduction
+    double cur[E], nxt[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) cur[e] = (t0 + e * BS < n) ? V[t0 + e * BS] : 0.0;
+    for (int i = 0; i <= j; ++i) {
+      double part = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (t0 + e * BS < n) part += xs[t0 + e * BS] * cur[e];
+      if (i < j) {
+        const double *vn = V + (int64_t)(i + 1) * ldv;
+#pragma unroll
+        for (int e = 0; e < E; ++e) nxt[e] = (t0 + e * BS < n) ? vn[t0 + e * BS] : 0.0;
+      }
+      const double hij = wg_sum(L, part);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (t0 + e * BS < n) xs[t0 + e * BS] -= hij * cur[e];
+      if (t0 == 0) hcol[i] = hij;
+      B.hscale = nmax(B.hscale, fabs(hij));
+#pragma unroll
+      for (int e = 0; e < E; ++e) cur[e] = nxt[e];
+    }
+  } else {
+    for (int i = 0; i <= j; ++i) {
+      const double *vi = V + (int64_t)i * ldv;
+      double part = 0.0;
+      for (int t = t0; t < n; t += BS) part += xs[t] * vi[t];
+      const double hij = wg_sum(L, part);
+      for (int t = t0; t < n; t += BS) xs[t] -= hij * vi[t];
+      if (t0 == 0) hcol[i] = hij;
+      B.hscale = nmax(B.hscale, fabs(hij));
+    }
   }
   double part = 0.0;
-  for (int t = threadIdx.x; t < n; t += BS) part += xs[t] * xs[t];
+  for (int t = t0; t < n; t += BS) part += xs[t] * xs[t];
   const double hn = sqrt(wg_sum(L, part));
   B.hscale = nmax(B.hscale, hn);
   B.m = j + 1;
-  if (hn <= breakdown * B.hscale) {
-    B.exact = 1;
-    if (threadIdx.x == 0) H[j + 1 + j * kHLd] = 0.0;
-  } else {
-    if (threadIdx.x == 0) H[j + 1 + j * kHLd] = hn;
-    double *vn = V + (int64_t)(j + 1) * D.ldv;
-    for (int t = threadIdx.x; t < n; t += BS) vn[t] = xs[t] / hn;
+  const bool brk = hn <= breakdown * B.hscale;
+  if (brk) B.exact = 1;
+  if (!brk) {
+    double *vn = V + (int64_t)(j + 1) * ldv;
+    for (int t = t0; t < n; t += BS) vn[t] = xs[t] / hn;
   }
+  for (int i = t0; i <= j; i += BS) H[i + j * kHLd] = hcol[i];
+  if (t0 == 0) H[j + 1 + j * kHLd] = brk ? 0.0 : hn;
   __syncthreads();
   pf.mark(3);
 }
@@ -575,6 +950,9 @@ __device__ Lds<BS> lds_setup(int R) {
   L.dmain = L.slots + 2 * (BS / 64);
   L.derr = L.dmain + kHLd;
   L.ipiv = reinterpret_cast<int *>(L.derr + kHLd);
+  L.bc = L.derr + kHLd + 2;
+  L.prof = reinterpret_cast<long long *>(L.derr + kHLd + 4);
+  L.hcol = L.derr + kHLd + 4 + kPhases;
   L.R = R;
   L.par = 0;
   return L;
@@ -617,9 +995,10 @@ __global__ void k_end(const InstDesc *descs, double *const *xout) {
 // steps of every unfinished instance.  replay != 0: the step ends are taken
 // from D.bp (the given grid) and every first trial is accepted.
 template <int BS>
-__global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int max_steps,
-                                            int replay, int R) {
-  const InstDesc &D = descs[blockIdx.x];
+__global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *order, Opts o,
+                                            int max_steps, int replay, int R) {
+  // workgroups start in blockIdx order: order[] lists the largest instances first
+  const InstDesc &D = descs[order[blockIdx.x]];
   InstState &S = *D.state;
   if (S.done) return;
   Lds<BS> L = lds_setup<BS>(R);
@@ -632,8 +1011,9 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
   const int steps0 = steps;
   const int rec = kRecFixed + D.n_probe;
   Prof pf;
-  pf.start();
+  pf.start(L.prof);
   Work wk{0, 0, 0};
+  __syncthreads();
 
   for (int it = 0; it < max_steps; ++it) {
     if (replay ? (steps >= D.n_bp) : !(t < D.T)) {
@@ -690,7 +1070,7 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
     for (int i = threadIdx.x; i < n; i += BS) D.p[i] = xs[i];
     __syncthreads();
     // ---- z = G^{-1} C p ;  v = w - z ----
-    for (int i = threadIdx.x; i < n; i += BS) xs[i] = csr_row_dot(D.c_rowptr, D.c_col, D.c_val, D.p, i);
+    for (int i = threadIdx.x; i < n; i += BS) xs[i] = c_row(D, D.p, i);
     __syncthreads();
     solve_lds<BS>(D, xs);
     for (int i = threadIdx.x; i < n; i += BS) D.tmp[i] = D.w[i] - xs[i];
@@ -792,7 +1172,7 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, Opts o, int m
     S.mgs_terms += wk.mgs;
     S.comb_terms += wk.comb;
 #pragma unroll
-    for (int i = 0; i < kPhases; ++i) S.ph[i] += (double)pf.acc[i];
+    for (int i = 0; i < kPhases; ++i) S.ph[i] += (double)L.prof[i];
     if (status != kOK) {
       S.status = status;
       S.done = 1;
@@ -897,8 +1277,9 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
   double rho = 0.0;
   int iters = 0;
   Prof pf;
-  pf.start();
+  pf.start(L.prof);
   Work wk{0, 0, 0};
+  __syncthreads();
   const int st = mevp_converge<BS>(D, L, o, D.V, D.H, B, h, eps, L.dmain, rho, iters, pf, wk);
   for (int i = threadIdx.x; i < D.n; i += BS) {
     double acc = 0.0;
@@ -909,6 +1290,7 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
     D.state->status = st;
     D.state->arnoldi = B.m;
     D.state->t = rho;
+    for (int i = 0; i < kPhases; ++i) D.state->ph[i] = (double)L.prof[i];
   }
 }
 
@@ -924,7 +1306,9 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
   }
 
 size_t lds_bytes(int bs, int R) {
-  return sizeof(double) * ((size_t)R + 2 * (bs / 64) + 2 * kHLd) + 8 * sizeof(int);
+  // region, reduction slots, dmain, derr, then 4 doubles (pivot ints,
+  // broadcast) and kPhases profile counters
+  return sizeof(double) * ((size_t)R + 2 * (bs / 64) + 3 * kHLd + 4 + kPhases);
 }
 
 hipError_t set_lds_limits(size_t bytes) {
@@ -940,6 +1324,89 @@ hipError_t set_lds_limits(size_t bytes) {
   return e;
 }
 
+
+// Diagnostic: times `reps` repetitions of one primitive on instance 0's data
+// (what: 0 full solve, 1 L solve, 2 U solve, 3 C SpMV, 4 workgroup sum,
+// 5 level loop with barriers only, 6 MGS step against 9 basis vectors).
+// Writes wall-clock ticks to out[0].
+template <int BS>
+__global__ void __launch_bounds__(BS) k_diag(const InstDesc *descs, int what, int reps, long long *out,
+                                             int R) {
+  const InstDesc &D = descs[0];
+  Lds<BS> L = lds_setup<BS>(R);
+  double *xs = L.region;
+  const int n = D.n;
+  for (int i = threadIdx.x; i < n; i += BS) xs[i] = D.p[i];
+  __syncthreads();
+  double acc = 0.0;
+  const long long t0 = wall_clock64();
+  for (int r = 0; r < reps; ++r) {
+    if (what == 0) {
+      solve_lds<BS>(D, xs);
+    } else if (what == 1 || what == 2) {
+      InstDesc E = D;
+      if (what == 1) E.n_usched = 0; else E.n_lsched = 0;
+      solve_lds<BS>(E, xs);
+    } else if (what == 3) {
+      for (int i = threadIdx.x; i < n; i += BS) xs[i] = c_row(D, D.p, i);
+      __syncthreads();
+    } else if (what == 4) {
+      acc += wg_sum(L, acc + 1.0);
+    } else if (what == 5) {
+      for (int l = 0; l < D.n_lsched + D.n_usched; ++l) __syncthreads();
+    } else if (what == 6) {
+      for (int i = 0; i < 9; ++i) {
+        const double *vi = D.V + (int64_t)i * D.ldv;
+        double part = 0.0;
+        for (int t = threadIdx.x; t < n; t += BS) part += xs[t] * vi[t];
+        const double hij = wg_sum(L, part) * 1e-300;
+        for (int t = threadIdx.x; t < n; t += BS) xs[t] -= hij * vi[t];
+      }
+    } else if (what == 7 || what == 8 || what == 9) {
+      // 7: register MGS as in arnoldi_step; 8: its loads and dots without the
+      // reduction; 9: its reductions without loads
+      constexpr int E = (4608 + BS - 1) / BS;
+      const int t0 = threadIdx.x;
+      const double *V = D.V;
+      const int64_t ldv = D.ldv;
+      double cur[E], nxt[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) cur[e] = (what != 9 && t0 + e * BS < n) ? V[t0 + e * BS] : 0.0;
+      for (int i = 0; i < 9; ++i) {
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (t0 + e * BS < n) part += xs[t0 + e * BS] * cur[e];
+        if (what != 9 && i < 8) {
+          const double *vn = V + (int64_t)(i + 1) * ldv;
+#pragma unroll
+          for (int e = 0; e < E; ++e) nxt[e] = (t0 + e * BS < n) ? vn[t0 + e * BS] : 0.0;
+        }
+        const double hij = (what != 8 ? wg_sum(L, part) : part) * 1e-300;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (t0 + e * BS < n) xs[t0 + e * BS] -= hij * cur[e];
+        if (what != 9)
+#pragma unroll
+          for (int e = 0; e < E; ++e) cur[e] = nxt[e];
+      }
+    }
+  }
+  const long long t1 = wall_clock64();
+  if (threadIdx.x == 0) { out[0] = t1 - t0; out[1] = (long long)acc; }
+}
+
+hipError_t launch_diag(const InstDesc *d, int what, int reps, long long *out, int bs, int R, hipStream_t s) {
+  const size_t sh = lds_bytes(bs, R);
+  EXPRI_DISPATCH(bs, {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_diag<BS>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag<BS>, dim3(1), dim3(BS), sh, s, d, what, reps, out, R);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_begin, dim3(n_inst), dim3(256), 0, s, d, xin, t0, h0);
@@ -951,10 +1418,11 @@ hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_run(const InstDesc *d, int n_inst, const Opts &o, int max_steps, int replay, int bs,
-                      int R, hipStream_t s) {
+hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
+                      int replay, int bs, int R, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_run<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, max_steps, replay, R));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_run<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, o, max_steps,
+                                        replay, R));
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -24,8 +25,8 @@ hipError_t set_lds_limits(size_t bytes);
 hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
                         hipStream_t s);
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
-hipError_t launch_run(const InstDesc *d, int n_inst, const Opts &o, int max_steps, int replay, int bs,
-                      int R, hipStream_t s);
+hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
+                      int replay, int bs, int R, hipStream_t s);
 hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R,
                      hipStream_t s);
 hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, hipStream_t s);
@@ -33,6 +34,7 @@ hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, d
                         int R, hipStream_t s);
 hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
                        double *const *out, double h, double eps, int bs, int R, hipStream_t s);
+hipError_t launch_diag(const InstDesc *d, int what, int reps, long long *out, int bs, int R, hipStream_t s);
 }  // namespace expri
 
 using namespace expri;
@@ -60,6 +62,11 @@ struct Packer {
 
 struct PatternDev {
   Symbolic sym;
+  // flattened solve schedules and C ELL pattern (depend on the block size)
+  std::vector<SolveLevel> lsched, usched;
+  std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col;
+  int32_t c_ell_k = 0;
+  size_t o_lsched, o_usched, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col;
   size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
       grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
       g_rowptr, g_col, c_rowptr, c_col, b_rowptr, b_col, dev_node, perm;
@@ -69,7 +76,7 @@ struct Inst {
   int pat = 0;
   int32_t n = 0, n_dev = 0, n_src = 0, n_probe = 0, n_bp = 0;
   double vdd = 1.0, T = 0.0, h_max = 0.0;
-  size_t g_val, c_val, b_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
+  size_t g_val, c_val, b_val, c_ell_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
   // workspace offsets
   size_t xk, x1, w, p, z, tmp, e, Ik, devI, devD, devI1, lu, V, Ve, H, He, mat, state, trace;
   int64_t ldv = 0;
@@ -92,6 +99,8 @@ struct expri_ctx {
   InstDesc *d_desc = nullptr;
   std::vector<InstDesc> h_desc;
   void **d_ptrs = nullptr;  // 4 * n_inst device pointers
+  int *d_order = nullptr;   // launch order of the transient kernel (largest first)
+  int variant = 0;          // EXPRI_VARIANT: code-path selection for A/B measurements
   int bs = 512, R = 8192;
   double wall_hz = 1e8;  // GPU wall-clock counter rate
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -145,6 +154,7 @@ std::vector<double> gather(const double *val, const std::vector<int32_t> &src) {
   for (size_t e = 0; e < src.size(); ++e) out[e] = val[src[e]];
   return out;
 }
+
 
 expri_status validate_circuit(expri_ctx *c, const expri_circuit &k, int idx) {
   const std::string w = "instance " + std::to_string(idx) + ": ";
@@ -229,6 +239,7 @@ void fill_descs(expri_ctx *c) {
     d.n_ulev = (int32_t)S.ulev_ptr.size() - 1;
     d.n_probe = I.n_probe;
     d.has_dev = I.n_dev > 0;
+    d.variant = c->variant;
     d.vdd = I.vdd;
     d.T = I.T;
     d.h_max = I.h_max;
@@ -243,6 +254,13 @@ void fill_descs(expri_ctx *c) {
     d.c_rowptr = ci(P.c_rowptr); d.c_col = ci(P.c_col);
     d.b_rowptr = ci(P.b_rowptr); d.b_col = ci(P.b_col);
     d.dev_node = ci(P.dev_node); d.perm = ci(P.perm);
+    d.lsched = reinterpret_cast<const SolveLevel *>(c->d_const + P.o_lsched);
+    d.usched = reinterpret_cast<const SolveLevel *>(c->d_const + P.o_usched);
+    d.n_lsched = (int32_t)P.lsched.size();
+    d.n_usched = (int32_t)P.usched.size();
+    d.slot_pos = ci(P.o_slot_pos); d.slot_col = ci(P.o_slot_col); d.row_of = ci(P.o_row_of);
+    d.c_ell_col = ci(P.o_c_ell_col); d.c_ell_k = P.c_ell_k;
+    d.c_ell_val = cd(I.c_ell_val);
     d.probe = ci(I.probe);
     d.g_val = cd(I.g_val); d.c_val = cd(I.c_val); d.b_val = cd(I.b_val);
     d.dev_par = cd(I.dev_par); d.src_ptr = ci(I.src_ptr); d.src_t = cd(I.src_t);
@@ -332,7 +350,7 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
     if (launches >= max_launches)
       return fail(c, EXPRI_ESTEPMIN, "step budget of " + std::to_string(kMaxRunSteps) + " accepted steps exhausted");
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_run(c->d_desc, n, ko, max_steps, replay, c->bs, c->R, c->stream));
+    HIPCHK(c, launch_run(c->d_desc, c->d_order, n, ko, max_steps, replay, c->bs, c->R, c->stream));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     if ((s = read_states(c, st)) != EXPRI_OK) return s;
     float ms = 0.0f;
@@ -404,6 +422,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   if (!c) return EXPRI_ENOMEM;
   if (!ckt || n_inst <= 0) return EXPRI_EINVAL;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (const char *v = std::getenv("EXPRI_VARIANT")) c->variant = std::atoi(v);
   if (o) c->opts = *o; else expri_default_opts(&c->opts);
   const expri_opts &op = c->opts;
   if (!(op.E_rr > 0) || !(op.eps_krylov > 0) || !(op.alpha > 0 && op.alpha < 1) || !(op.beta >= 1) ||
@@ -465,6 +484,33 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     n_max = std::max(n_max, K.n);
   }
 
+  // ---- launch shape ----
+  int dev = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "device query"); }
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
+    c->wall_hz = 1e3 * wall_khz;
+  // 1024-thread blocks spill registers in the transient kernel; 512 covers the
+  // LDS-resident sizes this engine targets
+  c->bs = op.block_size ? op.block_size : (n_max <= 2048 ? 256 : 512);
+  const size_t limit = prop.sharedMemPerBlock;
+  const size_t extras = lds_bytes(c->bs, 0);
+  size_t R = std::max<size_t>(n_max, 8192);
+  if (8 * R + extras > limit) R = std::max<size_t>(n_max, (limit - extras) / 8);
+  if (8 * R + extras > limit) {
+    *out = c.release();
+    (*out)->err = "circuit too large for the one-workgroup engine (n = " + std::to_string(n_max) + ")";
+    return EXPRI_EINVAL;
+  }
+  // flattened solve schedules and the C ELL pattern for this block size
+  for (auto &P : c->pats) {
+    build_solve_schedule(P.sym, c->bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of);
+    build_solve_schedule(P.sym, c->bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of);
+    P.c_ell_k = build_c_ell(P.sym, P.c_ell_col);
+  }
   // ---- pack constant data ----
   Packer pk;
   for (auto &P : c->pats) {
@@ -480,13 +526,24 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.c_rowptr = pk.add(S.c_rowptr); P.c_col = pk.add(S.c_col);
     P.b_rowptr = pk.add(S.b_rowptr); P.b_col = pk.add(S.b_col);
     P.dev_node = pk.add(S.dev_node); P.perm = pk.add(S.perm);
+    P.o_lsched = pk.add(P.lsched); P.o_usched = pk.add(P.usched);
+    P.o_slot_pos = pk.add(P.slot_pos); P.o_slot_col = pk.add(P.slot_col); P.o_row_of = pk.add(P.row_of);
+    P.o_c_ell_col = pk.add(P.c_ell_col);
   }
   for (int k = 0; k < n_inst; ++k) {
     const expri_circuit &K = ckt[k];
     Inst &I = c->inst[k];
     const Symbolic &S = c->pats[I.pat].sym;
     I.g_val = pk.add(gather(K.G.val, S.g_src));
-    I.c_val = pk.add(gather(K.C.val, S.c_src));
+    const std::vector<double> cperm = gather(K.C.val, S.c_src);
+    I.c_val = pk.add(cperm);
+    {
+      const PatternDev &PD = c->pats[I.pat];
+      std::vector<double> ell((size_t)std::max(PD.c_ell_k, 1) * K.n, 0.0);
+      for (int i = 0; i < K.n; ++i)
+        for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e) ell[(size_t)(e - S.c_rowptr[i]) * K.n + i] = cperm[e];
+      I.c_ell_val = pk.add(ell);
+    }
     I.b_val = pk.add(gather(K.B.val, S.b_src));
     std::vector<double> par(4 * (size_t)K.dev.n);
     for (int i = 0; i < K.dev.n; ++i) {
@@ -519,33 +576,26 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   }
   c->const_bytes = pk.img.size();
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, c->const_bytes);
+  e = hipMalloc(&p, c->const_bytes);
   if (e != hipSuccess) { *out = c.release(); (*out)->err = "constant upload allocation failed"; return EXPRI_ENOMEM; }
   c->d_const = static_cast<char *>(p);
   e = hipMemcpy(c->d_const, pk.img.data(), c->const_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_desc), sizeof(InstDesc) * n_inst);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_ptrs), sizeof(void *) * 4 * n_inst);
+  if (e == hipSuccess) {
+    // longest-processing-time-first: larger instances (more nodes, then more
+    // devices) are launched first so they do not wait for a free compute unit
+    std::vector<int> order(n_inst);
+    for (int k = 0; k < n_inst; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (ckt[a].n != ckt[b].n) return ckt[a].n > ckt[b].n;
+      return ckt[a].dev.n > ckt[b].dev.n;
+    });
+    e = hipMalloc(reinterpret_cast<void **>(&c->d_order), sizeof(int) * n_inst);
+    if (e == hipSuccess) e = hipMemcpy(c->d_order, order.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "setup upload"); }
 
-  // ---- launch shape ----
-  int dev = 0;
-  hipDeviceProp_t prop;
-  e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "device query"); }
-  int wall_khz = 0;
-  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
-    c->wall_hz = 1e3 * wall_khz;
-  c->bs = op.block_size ? op.block_size : (n_max <= 2048 ? 256 : (n_max <= 8192 ? 512 : 1024));
-  const size_t limit = prop.sharedMemPerBlock;
-  const size_t extras = lds_bytes(c->bs, 0);
-  size_t R = std::max<size_t>(n_max, 8192);
-  if (8 * R + extras > limit) R = std::max<size_t>(n_max, (limit - extras) / 8);
-  if (8 * R + extras > limit) {
-    *out = c.release();
-    (*out)->err = "circuit too large for the one-workgroup engine (n = " + std::to_string(n_max) + ")";
-    return EXPRI_EINVAL;
-  }
   c->R = (int)R;
   e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
@@ -638,6 +688,11 @@ expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out
   for (int k = 0; k < n; ++k) {
     if (m) m[k] = st[k].arnoldi;
     if (rho) rho[k] = st[k].t;
+    expri_run_info &in = c->inst[k].info;
+    in = expri_run_info{};
+    in.arnoldi = st[k].arnoldi;
+    in.status = st[k].status;
+    for (int p = 0; p < 6; ++p) in.phase_s[p] = st[k].ph[p] / c->wall_hz;
   }
   return first_error(c, st, "mevp");
 }
@@ -743,6 +798,28 @@ expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
   return EXPRI_OK;
 }
 
+expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, double *seconds) {
+  if (!c || !seconds || what < 0 || what > 9 || reps < 1) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  long long *d = nullptr;
+  HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&d), 2 * sizeof(long long)));
+  hipError_t e = launch_diag(c->d_desc, what, reps, d, c->bs, c->R, c->stream);
+  long long h[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(c, e, "diag");
+  *seconds = h[0] / c->wall_hz / reps;
+  return EXPRI_OK;
+}
+
+expri_status expri_block_size(const expri_ctx *c, int32_t *bs) {
+  if (!c || !bs) return EXPRI_EINVAL;
+  *bs = c->bs;
+  return EXPRI_OK;
+}
+
 expri_status expri_kernel_time(const expri_ctx *c, double *seconds, int32_t *launches) {
   if (!c || !seconds || !launches) return EXPRI_EINVAL;
   *seconds = c->run_kernel_s;
@@ -758,6 +835,7 @@ void expri_destroy(expri_ctx *c) {
   if (c->d_const) (void)hipFree(c->d_const);
   if (c->d_desc) (void)hipFree(c->d_desc);
   if (c->d_ptrs) (void)hipFree(c->d_ptrs);
+  if (c->d_order) (void)hipFree(c->d_order);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;

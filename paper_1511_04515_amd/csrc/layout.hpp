@@ -26,6 +26,8 @@ struct Opts {
   double piv_tol;     // small-pivot threshold, relative to the row's max |G_k|
   int32_t grow_if_rejects_lt;
   int32_t m_max;
+  int32_t variant;    // code-path selection for A/B measurements (0 = default)
+  int32_t pad;
 };
 
 // Run state of one instance; lives in device memory between launches.
@@ -48,10 +50,19 @@ struct InstState {
   double ph[kPhases];
 };
 
+// One level of a flattened triangular-solve schedule: rows of the level are
+// handled by groups of G lanes (G a power of two), each lane multiplying up
+// to P stored entries; the level's rows need `passes` sweeps of the block.
+struct SolveLevel {
+  int32_t G, P, passes, pad;
+  int32_t slot_base;  // into slot_pos / slot_col: index (q * P + j) * BS + t
+  int32_t row_base;   // into row_of: index q * (BS / G) + t / G
+};
+
 struct InstDesc {
   int32_t n, n_dev, n_src, n_bp;
   int32_t nnz_lu, n_lev, n_ulev, n_probe;
-  int32_t has_dev, pad0, pad1, pad2;
+  int32_t has_dev, variant, pad1, pad2;
   double vdd, T, h_max;
 
   // symbolic (shared by instances of one pattern)
@@ -61,11 +72,19 @@ struct InstDesc {
   const int32_t *lu_gidx, *jac_ptr, *jac_code, *node_ptr, *node_code;
   const int32_t *g_rowptr, *g_col, *c_rowptr, *c_col, *b_rowptr, *b_col;
   const int32_t *dev_node;      // 3 per device
+  // flattened solve schedules (built for the launch block size)
+  const SolveLevel *lsched, *usched;
+  const int32_t *slot_pos, *slot_col, *row_of;
+  int32_t n_lsched, n_usched;
+  // C in ELL layout: entry k of row i at k * n + i (column -1 = padding)
+  const int32_t *c_ell_col;
+  int32_t c_ell_k, pad4;
   const int32_t *perm;          // perm[internal] = caller's node id
   const int32_t *probe;         // internal ids of the probed nodes
 
   // values (per instance, permuted to the internal numbering)
   const double *g_val, *c_val, *b_val;
+  const double *c_ell_val;
   const double *dev_par;        // 4 per device: type (+1/-1), K = k' W/L, V_th, lambda
   const int32_t *src_ptr;       // n_src + 1
   const double *src_t, *src_v;  // PWL corners

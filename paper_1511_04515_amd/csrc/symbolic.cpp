@@ -496,4 +496,70 @@ bool analyse(const PatternInput &in, Symbolic &sym) {
   return true;
 }
 
+constexpr int kSlotMax = 8;  // entries per lane and level before more lanes share a row
+
+// Flattened schedule of one triangular solve: for every level choose the
+// smallest power-of-two group of lanes per row that keeps each lane at
+// <= kSlotMax entries, and lay the entries out so that lane t of the block
+// reads slot (q * P + j) * bs + t (coalesced).
+void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
+                          std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
+                          std::vector<int32_t> &row_of) {
+  const auto &ptr = lower ? S.lev_ptr : S.ulev_ptr;
+  const auto &rows = lower ? S.lev_rows : S.ulev_rows;
+  const int nlev = (int)ptr.size() - 1;
+  sched.clear();
+  for (int l = 0; l < nlev; ++l) {
+    const int r0 = ptr[l], r1 = ptr[l + 1], nr = r1 - r0;
+    int K = 0;
+    for (int q = r0; q < r1; ++q) {
+      const int i = rows[q];
+      const int k = lower ? S.lu_diag[i] - S.lu_rowptr[i] : S.lu_rowptr[i + 1] - S.lu_diag[i] - 1;
+      K = std::max(K, k);
+    }
+    if (lower && K == 0) continue;  // unit diagonal: nothing to do on this level
+    int G = 1;
+    while (G < 64 && (K + G - 1) / G > kSlotMax) G *= 2;
+    const int P = std::max(1, (K + G - 1) / G);
+    const int per_pass = bs / G;
+    const int passes = (nr + per_pass - 1) / per_pass;
+    SolveLevel L{};
+    L.G = G;
+    L.P = P;
+    L.passes = passes;
+    L.slot_base = (int32_t)slot_pos.size();
+    L.row_base = (int32_t)row_of.size();
+    slot_pos.resize(slot_pos.size() + (size_t)passes * P * bs, -1);
+    slot_col.resize(slot_col.size() + (size_t)passes * P * bs, 0);
+    row_of.resize(row_of.size() + (size_t)passes * per_pass, -1);
+    for (int idx = 0; idx < nr; ++idx) {
+      const int i = rows[r0 + idx];
+      const int q = idx / per_pass, g = idx % per_pass;
+      row_of[L.row_base + q * per_pass + g] = i;
+      const int b = lower ? S.lu_rowptr[i] : S.lu_diag[i] + 1;
+      const int e = lower ? S.lu_diag[i] : S.lu_rowptr[i + 1];
+      for (int k = 0; k < e - b; ++k) {
+        const int li = k % G, j = k / G;
+        const int t = g * G + li;
+        const size_t o = (size_t)L.slot_base + ((size_t)q * P + j) * bs + t;
+        slot_pos[o] = b + k;
+        slot_col[o] = S.lu_col[b + k];
+      }
+    }
+    sched.push_back(L);
+  }
+}
+
+// ELL layout of C's pattern: entry k of row i at k * n + i; returns K.
+int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col) {
+  const int n = S.n;
+  int K = 0;
+  for (int i = 0; i < n; ++i) K = std::max(K, S.c_rowptr[i + 1] - S.c_rowptr[i]);
+  col.assign((size_t)std::max(K, 1) * n, -1);
+  for (int i = 0; i < n; ++i)
+    for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e) col[(size_t)(e - S.c_rowptr[i]) * n + i] = S.c_col[e];
+  return K;
+}
+
+
 }  // namespace expri

@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include "layout.hpp"
+
 namespace expri {
 
 struct PatternInput {
@@ -73,6 +75,16 @@ bool analyse(const PatternInput &in, Symbolic &sym);
 
 // Hash of a pattern (for sharing symbolic data across instances).
 uint64_t pattern_hash(const PatternInput &in);
+
+// Flattened schedule of one triangular solve for block size bs (lower = L
+// solve, else U solve); appends to the slot / row arrays.
+void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
+                          std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
+                          std::vector<int32_t> &row_of);
+
+// ELL layout of C's (permuted) pattern: entry k of row i at k * n + i, -1 =
+// padding; returns the ELL width.
+int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col);
 
 // Fill-reducing order of a symmetric graph (adjacency without self loops) by
 // recursive BFS-level bisection (nested dissection).  Exposed for tests.

@@ -9,6 +9,8 @@
 
 struct expri_symbolic {
   expri::Symbolic sym;
+  // flattened schedules for one block size (expri_symbolic_schedule)
+  std::vector<int32_t> lsched, usched, slot_pos, slot_col, row_of, c_ell_col;
 };
 
 extern "C" {
@@ -36,6 +38,25 @@ expri_status expri_symbolic_create(expri_symbolic **out, const expri_circuit *k)
   return EXPRI_OK;
 }
 
+expri_status expri_symbolic_schedule(expri_symbolic *s, int32_t bs) {
+  if (!s || (bs != 256 && bs != 512 && bs != 1024)) return EXPRI_EINVAL;
+  std::vector<expri::SolveLevel> L, U;
+  s->slot_pos.clear();
+  s->slot_col.clear();
+  s->row_of.clear();
+  expri::build_solve_schedule(s->sym, bs, true, L, s->slot_pos, s->slot_col, s->row_of);
+  expri::build_solve_schedule(s->sym, bs, false, U, s->slot_pos, s->slot_col, s->row_of);
+  auto flat = [](const std::vector<expri::SolveLevel> &v, std::vector<int32_t> &o) {
+    o.clear();
+    for (const auto &l : v) o.insert(o.end(), {l.G, l.P, l.passes, l.pad, l.slot_base, l.row_base});
+  };
+  flat(L, s->lsched);
+  flat(U, s->usched);
+  const int32_t k = expri::build_c_ell(s->sym, s->c_ell_col);
+  s->c_ell_col.push_back(k);  // last element: the ELL width
+  return EXPRI_OK;
+}
+
 expri_status expri_symbolic_array(const expri_symbolic *s, const char *name, int32_t *out, int64_t cap,
                                   int64_t *len) {
   if (!s || !name || !len) return EXPRI_EINVAL;
@@ -48,6 +69,9 @@ expri_status expri_symbolic_array(const expri_symbolic *s, const char *name, int
   A(jac_code) A(node_ptr) A(node_code) A(g_rowptr) A(g_col) A(g_src) A(c_rowptr) A(c_col)
   A(c_src) A(b_rowptr) A(b_col) A(b_src) A(dev_node) A(block_of)
 #undef A
+#define B(X) if (nm == #X) v = &s->X;
+  B(lsched) B(usched) B(slot_pos) B(slot_col) B(row_of) B(c_ell_col)
+#undef B
   if (!v) return EXPRI_EINVAL;
   *len = (int64_t)v->size();
   if (out && cap > 0) std::memcpy(out, v->data(), sizeof(int32_t) * (size_t)std::min<int64_t>(cap, *len));

@@ -154,3 +154,77 @@ def test_node_current_gather_matches_oracle():
         for c in S["node_code"][S["node_ptr"][i]:S["node_ptr"][i + 1]]:
             got[i] += -Idev[c >> 1] if c & 1 else Idev[c >> 1]
     assert np.allclose(got, I_ref[S["perm"]], rtol=1e-14, atol=1e-20)
+
+
+def emulate_flat_solve(S, lu, b, bs):
+    """The kernel's flattened level schedule: lane t of pass q reads slots
+    (q P + j) bs + t; groups of G lanes sum their partial products."""
+    x = b.copy()
+    n = b.size
+    nnz = lu.size
+    for lower, sched in ((True, S["lsched"].reshape(-1, 6)), (False, S["usched"].reshape(-1, 6))):
+        for G, P, passes, _, sb, rb in sched:
+            assert G in (1, 2, 4, 8, 16, 32, 64) and P >= 1 and passes >= 1
+            for q in range(passes):
+                idx = sb + (q * P + np.arange(P))[:, None] * bs + np.arange(bs)[None, :]
+                assert idx.max() < S["slot_pos"].size
+                pos = S["slot_pos"][idx]
+                col = S["slot_col"][idx]
+                assert pos.max() < nnz and col.min() >= 0 and col.max() < n
+                prod = np.where(pos >= 0, lu[np.maximum(pos, 0)] * x[col], 0.0)
+                acc = prod.sum(0).reshape(bs // G, G).sum(1)
+                ridx = rb + q * (bs // G) + np.arange(bs // G)
+                assert ridx.max() < S["row_of"].size
+                rows = S["row_of"][ridx]
+                ok = rows >= 0
+                assert rows.max() < n
+                if lower:
+                    x[rows[ok]] -= acc[ok]
+                else:
+                    x[rows[ok]] = (x[rows[ok]] - acc[ok]) / lu[S["lu_diag"][rows[ok]]]
+    return x
+
+
+@pytest.mark.parametrize("bs", [256, 512, 1024])
+@pytest.mark.parametrize("make", CIRCUITS + [lambda: netgen.config(2), lambda: netgen.config(1)])
+def test_flattened_solve_schedule_matches_row_solve(make, bs):
+    net = make()
+    S = symbolic_analysis(net, block_size=bs)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0.0, 1.0, net.n)
+    if net.n <= 400:
+        _, lu, _ = emulate_factor(net, S, x)
+    else:  # any values on the pattern exercise the schedule
+        lu = rng.uniform(0.5, 1.5, S["lu_col"].size)
+        lu[S["lu_diag"]] += 10.0
+    b = rng.standard_normal(net.n)
+    ref = emulate_solve(S, lu, b)
+    got = emulate_flat_solve(S, lu, b, bs)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # every row appears exactly once per direction (L levels without entries are skipped)
+    ls, us = S["lsched"].reshape(-1, 6), S["usched"].reshape(-1, 6)
+    def rows_of(sched):
+        out = []
+        for G, P, passes, _, sb, rb in sched:
+            r = S["row_of"][rb: rb + passes * (bs // G)]
+            out.extend(r[r >= 0].tolist())
+        return out
+    ur = rows_of(us)
+    assert sorted(ur) == list(range(net.n))
+    lr = rows_of(ls)
+    assert len(set(lr)) == len(lr)
+    # C in ELL layout reproduces C v
+    K = S["c_ell_col"][-1]
+    ell = S["c_ell_col"][:-1].reshape(max(K, 1), net.n)
+    perm = S["perm"]
+    Cp = net.C.tocsr()[perm][:, perm]
+    v = rng.standard_normal(net.n)
+    vals = np.zeros_like(ell, dtype=float)
+    for i in range(net.n):
+        for k in range(K):
+            c = ell[k, i]
+            if c >= 0:
+                vals[k, i] = Cp[i, c]
+    got_cv = np.array([sum(vals[k, i] * v[ell[k, i]] for k in range(K) if ell[k, i] >= 0) for i in range(net.n)])
+    # rows with coupling caps cancel: compare against |C| |v|
+    assert np.max(np.abs(got_cv - Cp @ v)) <= 1e-14 * np.max(abs(Cp) @ np.abs(v))
