@@ -204,11 +204,14 @@ expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_
 expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *launches);
 
 /* Diagnostic: device time (seconds per repetition, GPU wall clock) of one
- * building block of the step on instance 0's current factors and vectors:
- * what = 0 full G_k solve, 1 L solve, 2 U solve, 3 C SpMV, 4 workgroup
- * reduction, 5 the solve's level loop with barriers only, 6 one
- * Gram-Schmidt sweep over 9 basis vectors. */
-expri_status expri_diag_time(expri_ctx *ctx, int32_t what, int32_t reps, double *seconds);
+ * building block of the step on instance 0's current factors:
+ * what = 0 full G_k solve, 1 L solve, 2 U solve, 3 one Arnoldi step
+ * j = arg (C SpMV, solve, Gram-Schmidt against arg + 1 vectors), 4 workgroup
+ * reduction, 5 one barrier per solve pass and nothing else, 6 the Hessenberg
+ * exponential and residual for m = arg on a synthetic H.  It overwrites
+ * instance 0's basis, Hessenbergs and solve vector with synthetic data.
+ * EXPRI_EINVAL unless 0 <= arg < m_max (and arg >= 1 for what = 6). */
+expri_status expri_diag_time(expri_ctx *ctx, int32_t what, int32_t reps, int32_t arg, double *seconds);
 
 /* Threads per workgroup the kernels are launched with (one workgroup per
  * instance). */

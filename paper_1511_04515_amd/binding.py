@@ -110,7 +110,7 @@ def load_library(path: str = LIB_PATH):
         "expri_lu_values": ([_p, C.c_int32, _f64p], C.c_int),
         "expri_kernel_time": ([_p, _f64p, _i32p], C.c_int),
         "expri_block_size": ([_p, _i32p], C.c_int),
-        "expri_diag_time": ([_p, C.c_int32, C.c_int32, _f64p], C.c_int),
+        "expri_diag_time": ([_p, C.c_int32, C.c_int32, C.c_int32, _f64p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
         "expri_symbolic_array": ([_p, C.c_char_p, _i32p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
         "expri_symbolic_schedule": ([_p, C.c_int32], C.c_int),
@@ -340,10 +340,11 @@ class Solver:
         out["x"] = buf[:, REC_FIXED:]
         return out
 
-    def diag_time(self, what: int, reps: int = 100) -> float:
-        """Seconds per repetition of one step building block (see expri.h)."""
+    def diag_time(self, what: int, reps: int = 100, arg: int = 8) -> float:
+        """Seconds per repetition of one step building block (see expri.h);
+        overwrites instance 0's basis and Hessenbergs."""
         sec = C.c_double()
-        self._check(self.lib.expri_diag_time(self.ctx, what, reps, C.byref(sec)))
+        self._check(self.lib.expri_diag_time(self.ctx, what, reps, arg, C.byref(sec)))
         return sec.value
 
     def kernel_time(self):

@@ -28,6 +28,25 @@ namespace expri {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// Pointers held in the instance descriptors are generic; accesses through
+// them compile to flat instructions, which also count against the LDS wait
+// counter (an LDS wait then drains in-flight memory loads too).  The hot
+// loops re-type them as global-memory pointers first.
+#define GMEM __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GMEM T *gbl(T *p) {
+  return (GMEM T *)p;
+}
+
+// The thread index as an opaque value.  Per-lane values derived from it
+// (addresses, masks) are then computed inside each phase instead of being
+// hoisted to the kernel entry and held in registers across the whole step.
+__device__ __forceinline__ int tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Wave-wide reductions on the DPP network: a butterfly inside each 16-lane
 // row (pairs of lanes 1 and 2 apart, then the 8- and 16-lane mirrors), then
 // the four row results read out in a fixed order.  Every lane ends with the
@@ -90,7 +109,8 @@ __device__ __forceinline__ double group_sum(double v, int G) {
 //   ipiv   : 8 ints
 template <int BS>
 struct Lds {
-  double *region;
+  double *region;  // vector area: solve vector / current Arnoldi basis vector
+  double *dense;   // small dense matrices of the Hessenberg exponential
   double *slots;
   double *dmain;
   double *derr;
@@ -98,7 +118,8 @@ struct Lds {
   double *bc;  // 1 double of broadcast from wave 0
   double *hcol; // kHLd doubles: current Hessenberg column
   long long *prof;  // kPhases phase counters
-  int R;
+  int R;   // region + dense, doubles
+  int RD;  // dense, doubles
   int par;
 };
 
@@ -106,7 +127,7 @@ template <int BS>
 __device__ __forceinline__ double wg_sum(Lds<BS> &L, double v) {
   v = wave_sum(v);
   double *s = L.slots + L.par * (BS / 64);
-  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  if ((tid() & 63) == 0) s[tid() >> 6] = v;
   __syncthreads();
   double r = 0.0;
 #pragma unroll
@@ -119,7 +140,7 @@ template <int BS>
 __device__ __forceinline__ double wg_max(Lds<BS> &L, double v) {
   v = wave_max(v);
   double *s = L.slots + L.par * (BS / 64);
-  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  if ((tid() & 63) == 0) s[tid() >> 6] = v;
   __syncthreads();
   double r = s[0];
 #pragma unroll
@@ -135,14 +156,14 @@ __device__ __forceinline__ double wg_max(Lds<BS> &L, double v) {
 struct Prof {
   long long *acc;  // kPhases counters in LDS, updated by the first thread
   long long last;
-  __device__ void start(long long *lds) {
+  __device__ __forceinline__ void start(long long *lds) {
     acc = lds;
-    if (threadIdx.x < kPhases) acc[threadIdx.x] = 0;
+    if (tid() < kPhases) acc[tid()] = 0;
     last = wall_clock64();
   }
   __device__ __forceinline__ void mark(int p) {
     const long long now = wall_clock64();
-    if (threadIdx.x == 0) acc[p] += now - last;
+    if (tid() == 0) acc[p] += now - last;
     last = now;
   }
 };
@@ -212,19 +233,19 @@ __device__ __forceinline__ int pwl_seg(const double *T, int lo, int hi, double t
 }
 
 __device__ __forceinline__ double pwl_value(const InstDesc &D, int src, double t) {
-  const int lo = D.src_ptr[src], hi = D.src_ptr[src + 1] - 1;
-  if (t <= D.src_t[lo]) return D.src_v[lo];
-  if (t >= D.src_t[hi]) return D.src_v[hi];
+  const int lo = gbl(D.src_ptr)[src], hi = gbl(D.src_ptr)[src + 1] - 1;
+  if (t <= gbl(D.src_t)[lo]) return gbl(D.src_v)[lo];
+  if (t >= gbl(D.src_t)[hi]) return gbl(D.src_v)[hi];
   const int i = pwl_seg(D.src_t, lo, hi, t);
-  const double slope = (D.src_v[i + 1] - D.src_v[i]) / (D.src_t[i + 1] - D.src_t[i]);
-  return D.src_v[i] + (t - D.src_t[i]) * slope;
+  const double slope = (D.src_v[i + 1] - gbl(D.src_v)[i]) / (D.src_t[i + 1] - gbl(D.src_t)[i]);
+  return gbl(D.src_v)[i] + (t - gbl(D.src_t)[i]) * slope;
 }
 
 __device__ __forceinline__ double pwl_slope(const InstDesc &D, int src, double tm) {
-  const int lo = D.src_ptr[src], hi = D.src_ptr[src + 1] - 1;
-  if (hi <= lo || tm < D.src_t[lo] || tm >= D.src_t[hi]) return 0.0;
+  const int lo = gbl(D.src_ptr)[src], hi = gbl(D.src_ptr)[src + 1] - 1;
+  if (hi <= lo || tm < gbl(D.src_t)[lo] || tm >= gbl(D.src_t)[hi]) return 0.0;
   const int i = pwl_seg(D.src_t, lo, hi, tm);
-  return (D.src_v[i + 1] - D.src_v[i]) / (D.src_t[i + 1] - D.src_t[i]);
+  return (D.src_v[i + 1] - gbl(D.src_v)[i]) / (D.src_t[i + 1] - gbl(D.src_t)[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,10 +253,10 @@ __device__ __forceinline__ double pwl_slope(const InstDesc &D, int src, double t
 // ---------------------------------------------------------------------------
 
 template <int BS>
-__device__ void stamp_devices(const InstDesc &D, const double *x, double *devI, double *devD) {
-  for (int k = threadIdx.x; k < D.n_dev; k += BS) {
-    const int nd = D.dev_node[3 * k], ng = D.dev_node[3 * k + 1], ns = D.dev_node[3 * k + 2];
-    const double *par = D.dev_par + 4 * k;
+__device__ __forceinline__ void stamp_devices(const InstDesc &D, const double *x, double *devI, double *devD) {
+  for (int k = tid(); k < D.n_dev; k += BS) {
+    const int nd = gbl(D.dev_node)[3 * k], ng = gbl(D.dev_node)[3 * k + 1], ns = gbl(D.dev_node)[3 * k + 2];
+    const GMEM double *par = gbl(D.dev_par) + 4 * k;
     double I, dd, dg, ds;
     mos_eval(par[0], node_v(x, nd, D.vdd), node_v(x, ng, D.vdd), node_v(x, ns, D.vdd), par[1],
              par[2], par[3], I, dd, dg, ds);
@@ -251,149 +272,174 @@ __device__ void stamp_devices(const InstDesc &D, const double *x, double *devI, 
 // lu <- G_lin + J_dev (drop the derivative couplings between DC blocks when
 // dc_block is set) ;  Ik <- I_dev(x) per node
 template <int BS>
-__device__ void assemble(const InstDesc &D, bool dc_block) {
-  for (int p = threadIdx.x; p < D.nnz_lu; p += BS) {
-    const int gi = D.lu_gidx[p];
-    double v = gi >= 0 ? D.g_val[gi] : 0.0;
-    for (int c = D.jac_ptr[p]; c < D.jac_ptr[p + 1]; ++c) {
-      const int code = D.jac_code[c];
+__device__ __forceinline__ void assemble(const InstDesc &D, bool dc_block) {
+  for (int p = tid(); p < D.nnz_lu; p += BS) {
+    const int gi = gbl(D.lu_gidx)[p];
+    double v = gi >= 0 ? gbl(D.g_val)[gi] : 0.0;
+    for (int c = gbl(D.jac_ptr)[p]; c < gbl(D.jac_ptr)[p + 1]; ++c) {
+      const int code = gbl(D.jac_code)[c];
       if (dc_block && ((code >> 3) & 1)) continue;
-      const double dv = D.devD[3 * (code >> 4) + (code & 3)];
+      const double dv = gbl(D.devD)[3 * (code >> 4) + (code & 3)];
       v += ((code >> 2) & 1) ? -dv : dv;
     }
-    D.lu[p] = v;
+    gbl(D.lu)[p] = v;
   }
-  for (int i = threadIdx.x; i < D.n; i += BS) {
+  for (int i = tid(); i < D.n; i += BS) {
     double s = 0.0;
-    for (int c = D.node_ptr[i]; c < D.node_ptr[i + 1]; ++c) {
-      const int code = D.node_code[c];
-      const double Iv = D.devI[code >> 1];
+    for (int c = gbl(D.node_ptr)[i]; c < gbl(D.node_ptr)[i + 1]; ++c) {
+      const int code = gbl(D.node_code)[c];
+      const double Iv = gbl(D.devI)[code >> 1];
       s += (code & 1) ? -Iv : Iv;
     }
-    D.Ik[i] = s;
+    gbl(D.Ik)[i] = s;
   }
+}
+
+// Slot-ordered copy of the factors for the solves: sval[k] is the L\U value
+// of slot k of the flattened schedules (0 on padding) and rdv[r] the pivot
+// u_ii of the row in row slot r (1 where the slot holds no row).  A solve pass
+// then reads its operands with coalesced loads that depend on nothing the
+// solve computes, so they can be issued a pass ahead.
+template <int BS>
+__device__ __forceinline__ void pack_slots(const InstDesc &D) {
+  const GMEM double *__restrict__ a = gbl(D.lu);
+  const GMEM int *__restrict__ spos = gbl(D.slot_pos);
+  GMEM double *__restrict__ sv = gbl(D.sval);
+  const GMEM int *__restrict__ rowof = gbl(D.row_of);
+  const GMEM int *__restrict__ diag = gbl(D.lu_diag);
+  GMEM double *__restrict__ rdv = gbl(D.rdv);
+  const int ns = D.n_slots;
+  for (int k0 = tid(); k0 < ns; k0 += 4 * BS) {
+    int p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[u] = k0 + u * BS < ns ? spos[k0 + u * BS] : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u * BS < ns) sv[k0 + u * BS] = p[u] >= 0 ? a[p[u]] : 0.0;
+  }
+  for (int r = tid(); r < D.n_srows; r += BS) {
+    const int i = rowof[r];
+    rdv[r] = i >= 0 ? a[diag[i]] : 1.0;
+  }
+  __syncthreads();
 }
 
 // numeric refactor of the L\U storage (row-wise Doolittle, static pivots).
 // Returns false when a pivot is small: |u_ii| <= piv_tol * max_j |G_k(i, j)|.
 template <int BS>
-__device__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
-  double *a = D.lu;
+__device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
+  GMEM double *a = gbl(D.lu);
+  const GMEM int *lev_ptr = gbl(D.lev_ptr), *lev_rows = gbl(D.lev_rows), *rowptr = gbl(D.lu_rowptr);
+  const GMEM int *row_grp = gbl(D.row_grp), *grp_pos = gbl(D.grp_pos), *grp_diag = gbl(D.grp_diag);
+  const GMEM int *grp_ptr = gbl(D.grp_ptr), *pair_dst = gbl(D.pair_dst), *pair_src = gbl(D.pair_src);
+  const GMEM int *diag = gbl(D.lu_diag);
   int bad = 0;
   for (int lv = 0; lv < D.n_lev; ++lv) {
-    for (int q = D.lev_ptr[lv] + threadIdx.x; q < D.lev_ptr[lv + 1]; q += BS) {
-      const int i = D.lev_rows[q];
+    for (int q = lev_ptr[lv] + tid(); q < lev_ptr[lv + 1]; q += BS) {
+      const int i = lev_rows[q];
       double rmax = 0.0;
-      for (int p = D.lu_rowptr[i]; p < D.lu_rowptr[i + 1]; ++p) rmax = fmax(rmax, fabs(a[p]));
-      for (int g = D.row_grp[i]; g < D.row_grp[i + 1]; ++g) {
-        const int pik = D.grp_pos[g];
-        const double l = a[pik] / a[D.grp_diag[g]];
+      for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) rmax = fmax(rmax, fabs(a[p]));
+      for (int g = row_grp[i]; g < row_grp[i + 1]; ++g) {
+        const int pik = grp_pos[g];
+        const double l = a[pik] / a[grp_diag[g]];
         a[pik] = l;
-        for (int u = D.grp_ptr[g]; u < D.grp_ptr[g + 1]; ++u) a[D.pair_dst[u]] -= l * a[D.pair_src[u]];
+        for (int u = grp_ptr[g]; u < grp_ptr[g + 1]; ++u) a[pair_dst[u]] -= l * a[pair_src[u]];
       }
-      const double dii = a[D.lu_diag[i]];
+      const double dii = a[diag[i]];
       if (!(fabs(dii) > piv_tol * rmax)) bad = 1;
     }
     __syncthreads();
   }
-  return wg_max(L, (double)bad) == 0.0;
+  if (wg_max(L, (double)bad) != 0.0) return false;
+  pack_slots<BS>(D);
+  return true;
 }
 
-// row-wise (CSR) level-scheduled solve: one thread per row
-template <int BS>
-__device__ void solve_lds_rows(const InstDesc &D, double *xs) {
-  const double *a = D.lu;
-  for (int lv = 0; lv < D.n_lev; ++lv) {
-    for (int q = D.lev_ptr[lv] + threadIdx.x; q < D.lev_ptr[lv + 1]; q += BS) {
-      const int i = D.lev_rows[q];
-      double s = xs[i];
-      for (int p = D.lu_rowptr[i]; p < D.lu_diag[i]; ++p) s -= a[p] * xs[D.lu_col[p]];
-      xs[i] = s;
-    }
-    __syncthreads();
+// Operands of one solve pass held by one lane: P slot values and columns,
+// the row its group owns and that row's pivot.
+template <int P>
+struct PassRegs {
+  double v[P];
+  int c[P];
+  int row;
+  double dv;
+};
+
+template <int BS, int P>
+__device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__restrict__ sv,
+                                           const GMEM int *__restrict__ scol, const GMEM int *__restrict__ rowof,
+                                           const GMEM double *__restrict__ rdv, int sbase, int rbase, int lg,
+                                           int t) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    o.v[j] = sv[sbase + j * BS + t];
+    o.c[j] = scol[sbase + j * BS + t];
   }
-  for (int lv = 0; lv < D.n_ulev; ++lv) {
-    for (int q = D.ulev_ptr[lv] + threadIdx.x; q < D.ulev_ptr[lv + 1]; q += BS) {
-      const int i = D.ulev_rows[q];
-      double s = xs[i];
-      const int dg = D.lu_diag[i];
-      for (int p = dg + 1; p < D.lu_rowptr[i + 1]; ++p) s -= a[p] * xs[D.lu_col[p]];
-      xs[i] = s / a[dg];
-    }
-    __syncthreads();
-  }
+  o.row = rowof[rbase + (t >> lg)];
+  o.dv = rdv[rbase + (t >> lg)];
 }
 
-// in-place solve G_k y = b with b (and then y) in LDS vector xs, following
-// the flattened level schedules: on every level the rows are handled by
-// groups of G lanes, lane t of the block reading slots (q P + j) BS + t of the
-// level (coalesced index and position arrays; the L\U values are gathered);
-// group partial sums meet in a butterfly over the group's lanes.
-// one pass of one level: lane t multiplies its (at most kSlots) entries;
-// every load is issued before the first product is formed
-constexpr int kSlots = 8;
-template <int BS>
-__device__ __forceinline__ double level_pass(const double *__restrict__ a, const int *__restrict__ spos,
-                                             const int *__restrict__ scol, const double *xs, int base,
-                                             int P) {
-  int pos[kSlots], col[kSlots];
-#pragma unroll
-  for (int j = 0; j < kSlots; ++j) {
-    pos[j] = j < P ? spos[base + j * BS] : -1;
-    col[j] = j < P ? scol[base + j * BS] : 0;
-  }
-  double av[kSlots], xv[kSlots];
-#pragma unroll
-  for (int j = 0; j < kSlots; ++j) {
-    av[j] = pos[j] >= 0 ? a[pos[j]] : 0.0;
-    xv[j] = pos[j] >= 0 ? xs[col[j]] : 0.0;
-  }
+template <int P, bool UPPER>
+__device__ __forceinline__ void pass_apply(const PassRegs<P> &o, double *xs, int lg, int t) {
   double acc = 0.0;
 #pragma unroll
-  for (int j = 0; j < kSlots; ++j) acc += av[j] * xv[j];
-  return acc;
+  for (int j = 0; j < P; ++j) acc += o.v[j] * xs[o.c[j]];
+  acc = group_sum(acc, 1 << lg);
+  if ((t & ((1 << lg) - 1)) == 0 && o.row >= 0) {
+    if (UPPER) xs[o.row] = (xs[o.row] - acc) / o.dv;
+    else xs[o.row] -= acc;
+  }
 }
 
+// The passes of one direction in order, each pass's loads issued while the
+// previous pass computes (two register sets, alternating).  Pass q reads
+// slots sbase + (q P + j) BS + t and row slot rbase + q BS + t / G; a barrier
+// follows the last pass of every level.
+template <int BS, int P, bool UPPER>
+__device__ __forceinline__ void solve_dir(const InstDesc &D, double *xs, const GMEM int *__restrict__ code,
+                                          int np, int sbase, int rbase) {
+  if (np == 0) return;
+  const GMEM double *__restrict__ sv = gbl(D.sval);
+  const GMEM int *__restrict__ scol = gbl(D.slot_col);
+  const GMEM int *__restrict__ rowof = gbl(D.row_of);
+  const GMEM double *__restrict__ rdv = gbl(D.rdv);
+  const int t = tid();
+  PassRegs<P> A, B;
+  int ca = code[0], cb;
+  pass_fetch<BS, P>(A, sv, scol, rowof, rdv, sbase, rbase, ca >> 8, t);
+  for (int q = 0; q < np; q += 2) {
+    // the pass after q (the last pass again past the end: in range, unused)
+    const int q1 = q + 1 < np ? q + 1 : np - 1;
+    cb = code[q1];
+    pass_fetch<BS, P>(B, sv, scol, rowof, rdv, sbase + q1 * P * BS, rbase + q1 * BS, cb >> 8, t);
+    pass_apply<P, UPPER>(A, xs, ca >> 8, t);
+    if (ca & kPassSync) __syncthreads();
+    if (q + 1 >= np) break;
+    const int q2 = q + 2 < np ? q + 2 : np - 1;
+    ca = code[q2];
+    pass_fetch<BS, P>(A, sv, scol, rowof, rdv, sbase + q2 * P * BS, rbase + q2 * BS, ca >> 8, t);
+    pass_apply<P, UPPER>(B, xs, cb >> 8, t);
+    if (cb & kPassSync) __syncthreads();
+  }
+}
+
+// in-place solve G_k y = b with b (and then y) in the LDS vector xs: the L
+// passes, then the U passes, of the flattened level schedules
 template <int BS>
-__device__ void solve_lds(const InstDesc &D, double *xs, int variant = 0) {
-  if (variant & 4) {
-    solve_lds_rows<BS>(D, xs);
-    return;
+__device__ __forceinline__ void solve_lds(const InstDesc &D, double *xs, bool lower = true, bool upper = true) {
+  const GMEM int *code = gbl(D.pass_code);
+  if (lower) switch (D.pl) {
+    case 1: solve_dir<BS, 1, false>(D, xs, code, D.n_lpass, 0, 0); break;
+    case 2: solve_dir<BS, 2, false>(D, xs, code, D.n_lpass, 0, 0); break;
+    case 4: solve_dir<BS, 4, false>(D, xs, code, D.n_lpass, 0, 0); break;
+    default: solve_dir<BS, 8, false>(D, xs, code, D.n_lpass, 0, 0); break;
   }
-  // descriptor fields in registers (a barrier would otherwise make the
-  // compiler reload them from memory on every level)
-  const double *__restrict__ a = D.lu;
-  const SolveLevel *__restrict__ ls = D.lsched;
-  const SolveLevel *__restrict__ us = D.usched;
-  const int *__restrict__ spos = D.slot_pos;
-  const int *__restrict__ scol = D.slot_col;
-  const int *__restrict__ rowof = D.row_of;
-  const int *__restrict__ diag = D.lu_diag;
-  const int nl = D.n_lsched, nu = D.n_usched;
-  const int t = threadIdx.x;
-  for (int l = 0; l < nl; ++l) {
-    const SolveLevel S = ls[l];
-    for (int q = 0; q < S.passes; ++q) {
-      double acc = level_pass<BS>(a, spos, scol, xs, S.slot_base + q * S.P * BS + t, S.P);
-      acc = group_sum(acc, S.G);
-      if ((t & (S.G - 1)) == 0) {
-        const int r = rowof[S.row_base + q * (BS / S.G) + t / S.G];
-        if (r >= 0) xs[r] -= acc;
-      }
-    }
-    __syncthreads();
-  }
-  for (int l = 0; l < nu; ++l) {
-    const SolveLevel S = us[l];
-    for (int q = 0; q < S.passes; ++q) {
-      const int ridx = S.row_base + q * (BS / S.G) + t / S.G;
-      const int r = rowof[ridx];
-      const double dv = r >= 0 ? a[diag[r]] : 1.0;
-      double acc = level_pass<BS>(a, spos, scol, xs, S.slot_base + q * S.P * BS + t, S.P);
-      acc = group_sum(acc, S.G);
-      if ((t & (S.G - 1)) == 0 && r >= 0) xs[r] = (xs[r] - acc) / dv;
-    }
-    __syncthreads();
+  code += D.n_lpass;
+  if (upper) switch (D.pu) {
+    case 1: solve_dir<BS, 1, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
+    case 2: solve_dir<BS, 2, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
+    case 4: solve_dir<BS, 4, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
+    default: solve_dir<BS, 8, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
   }
 }
 
@@ -401,8 +447,8 @@ __device__ void solve_lds(const InstDesc &D, double *xs, int variant = 0) {
 __device__ __forceinline__ double c_row(const InstDesc &D, const double *v, int i) {
   double s = 0.0;
   for (int k = 0; k < D.c_ell_k; ++k) {
-    const int c = D.c_ell_col[(int64_t)k * D.n + i];
-    if (c >= 0) s += D.c_ell_val[(int64_t)k * D.n + i] * v[c];
+    const int c = gbl(D.c_ell_col)[(int64_t)k * D.n + i];
+    if (c >= 0) s += gbl(D.c_ell_val)[(int64_t)k * D.n + i] * v[c];
   }
   return s;
 }
@@ -415,400 +461,208 @@ __device__ __forceinline__ double csr_row_dot(const int *rp, const int *ci, cons
 }
 
 // ---------------------------------------------------------------------------
-// The same small-matrix algebra executed by one wave (wave 0) for
-// n <= 32: lanes own matrix columns, matrices live in LDS, and a wavefront
-// fence orders the LDS traffic between phases (a wave's LDS operations
-// complete in order).  No workgroup barrier is needed inside.
+// Small-matrix part of the MEVP (the residual test of Algorithm 1 and the
+// coefficients of the update; the invert-Krylov section): with
+// M = h H_m^{-1} and E = exp([[M, e_1], [0, 0]]),
+//   y = E[:m, 0] = e^M e_1,  f = E[:m, m] = phi_1(M) e_1,
+//   d = -M f = (I - e^M) e_1  (no cancellation against e_1),
+//   rho = beta h_{m+1,m} |(H_m^{-1} y)_{m-1}| = beta h_{m+1,m} |(M y)_{m-1}| / h.
+// Matrices are NP x NP (NP = 16 ceil((m+1)/16), zero padded, row-major with
+// leading dimension NP + 1 so that a column read spreads over the LDS banks),
+// in the LDS dense area for NP <= 32 and in global scratch beyond.
+//  * H_m^{-1}: Hessenberg elimination with partial pivoting by one wave
+//    (lanes own columns of [H | h I], the row being eliminated is carried in
+//    registers), then back substitution with groups of G lanes per
+//    right-hand-side column that sum their share of each row's products on
+//    the DPP network.
+//  * exp: Taylor polynomial of degree 18 with scaling and squaring.  With
+//    2^-s ||A||_1 <= 1 the truncated tail is below e/19! ~ 2e-17 relative.
+//    The polynomial is evaluated in Paterson-Stockmeyer form (blocks of three
+//    in A^3): seven matrix products and no linear solve, each product on FP64
+//    MFMA 16x16x4 tiles, one output tile per wave.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// Solve P X = Q (n x n, nrhs columns; LDS) by Gaussian elimination with
-// partial pivoting (largest magnitude, first on ties); Q <- X.  Lane c owns
-// the columns c, c + 64, ... of [P | Q].
-__device__ void w_lu_solve(double *P, double *Q, int n, int nrhs, int lane) {
-  const int ncol = n + nrhs;
-  for (int k = 0; k < n; ++k) {
-    wfence();
-    int pr = k;
-    double best = fabs(P[k * n + k]);
-    for (int r = k + 1; r < n; ++r) {
-      const double v = fabs(P[r * n + k]);
-      if (v > best) { best = v; pr = r; }
-    }
-    if (pr != k)
-      for (int c = lane; c < ncol; c += 64) {
-        double *A = c < n ? P : Q;
-        const int cc = c < n ? c : c - n, ld = c < n ? n : nrhs;
-        const double t = A[k * ld + cc];
-        A[k * ld + cc] = A[pr * ld + cc];
-        A[pr * ld + cc] = t;
-      }
-    wfence();
-    const double piv = P[k * n + k];
-    for (int r = k + 1; r < n; ++r) {
-      const double l = P[r * n + k] / piv;
-      for (int c = lane; c < ncol; c += 64) {
-        if (c < n) {
-          if (c > k) P[r * n + c] -= l * P[k * n + c];
-        } else {
-          Q[r * nrhs + (c - n)] -= l * Q[k * nrhs + (c - n)];
-        }
-      }
-    }
-  }
-  wfence();
-  for (int c = lane; c < nrhs; c += 64)
-    for (int r = n - 1; r >= 0; --r) {
-      double sacc = Q[r * nrhs + c];
-      for (int j = r + 1; j < n; ++j) sacc -= P[r * n + j] * Q[j * nrhs + c];
-      Q[r * nrhs + c] = sacc / P[r * n + r];
-    }
-  wfence();
-}
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Solve P X = Q for upper Hessenberg P (n x n, LDS): partial pivoting only
-// ever compares rows k and k+1, so each elimination step touches one row.
-__device__ void w_hess_solve(double *P, double *Q, int n, int nrhs, int lane) {
-  const int ncol = n + nrhs;
-  for (int k = 0; k + 1 < n; ++k) {
-    wfence();
-    const bool sw = fabs(P[(k + 1) * n + k]) > fabs(P[k * n + k]);
-    if (sw)
-      for (int c = lane; c < ncol; c += 64) {
-        double *A = c < n ? P : Q;
-        const int cc = c < n ? c : c - n, ld = c < n ? n : nrhs;
-        const double t = A[k * ld + cc];
-        A[k * ld + cc] = A[(k + 1) * ld + cc];
-        A[(k + 1) * ld + cc] = t;
-      }
-    wfence();
-    const double l = P[(k + 1) * n + k] / P[k * n + k];
-    for (int c = lane; c < ncol; c += 64) {
-      if (c < n) {
-        if (c > k) P[(k + 1) * n + c] -= l * P[k * n + c];
-      } else {
-        Q[(k + 1) * nrhs + (c - n)] -= l * Q[k * nrhs + (c - n)];
-      }
-    }
-  }
-  wfence();
-  for (int c = lane; c < nrhs; c += 64)
-    for (int r = n - 1; r >= 0; --r) {
-      double sacc = Q[r * nrhs + c];
-      for (int j = r + 1; j < n; ++j) sacc -= P[r * n + j] * Q[j * nrhs + c];
-      Q[r * nrhs + c] = sacc / P[r * n + r];
-    }
-  wfence();
-}
+// 1 / k!, folded at compile time
+template <int K>
+struct InvFact {
+  static constexpr double v = InvFact<K - 1>::v / K;
+};
+template <>
+struct InvFact<0> {
+  static constexpr double v = 1.0;
+};
 
-// C = A B (n x n, n <= 32): lane -> column (lane & 31), half of the rows.
-__device__ __forceinline__ void w_mat_mul(const double *A, const double *B, double *C, int n, int lane) {
-  wfence();
-  const int c = lane & 31, half = (n + 1) >> 1;
-  const int r0 = (lane >> 5) ? half : 0, r1 = (lane >> 5) ? n : half;
-  if (c < n)
-    for (int r = r0; r < r1; ++r) {
-      double sacc = 0.0;
-      for (int k = 0; k < n; ++k) sacc += A[r * n + k] * B[k * n + c];
-      C[r * n + c] = sacc;
-    }
-  wfence();
-}
-
-__device__ __forceinline__ double w_max(double v) {
+// C = A B (+ c0 I + c1 P1 + c2 P2 when add), all NP x NP with leading
+// dimension ld.  Wave w computes output tiles w, w + NW, ...  MFMA f64
+// 16x16x4 lane layout: operand A lane i + 16 k holds A[i][k]; operand B lane
+// j + 16 k holds B[k][j]; result element v of lane j + 16 q is C[q + 4 v][j].
+template <int BS, int NP, class PT>
+__device__ __forceinline__ void mm_mfma(PT A, PT B, PT C, int ld, bool add, double c0, double c1, double c2,
+                                        PT P1, PT P2) {
+  constexpr int T = NP / 16, NW = BS / 64;
+  const int lane = tid() & 63, wave = tid() >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  for (int tile = wave; tile < T * T; tile += NW) {
+    const int i0 = (tile / T) * 16, j0 = (tile % T) * 16;
+    dbl4 acc;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = nmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// exp(A) by scaling and squaring with the degree-13 Pade approximant in one
-// wave; buf holds 5 n x n matrices; returns the matrix holding exp(A).
-__device__ double *w_expm_pade13(double *A, double *buf, int n, int lane) {
-  const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
-                        1187353796428800.0,  129060195264000.0,   10559470521600.0,
-                        670442572800.0,      33522128640.0,       1323241920.0,
-                        40840800.0,          960960.0,            16380.0,
-                        182.0,               1.0};
-  const double theta13 = 5.371920351148152;
-  const int nn = n * n;
-  double *A2 = buf, *A4 = buf + nn, *A6 = buf + 2 * nn, *T1 = buf + 3 * nn, *T2 = buf + 4 * nn;
-  wfence();
-  double cs = 0.0;
-  if (lane < n)
-    for (int r = 0; r < n; ++r) cs += fabs(A[r * n + lane]);
-  const double nrm = w_max(cs);
-  int s = 0;
-  if (nrm > theta13) s = (nrm < theta13 * 0x1p64) ? (int)ceil(log2(nrm / theta13)) : 64;
-  if (s > 0) {
-    const double sc = ldexp(1.0, -s);
-    for (int i = lane; i < nn; i += 64) A[i] *= sc;
-  }
-  w_mat_mul(A, A, A2, n, lane);
-  w_mat_mul(A2, A2, A4, n, lane);
-  w_mat_mul(A4, A2, A6, n, lane);
-  for (int i = lane; i < nn; i += 64) T1[i] = b[13] * A6[i] + b[11] * A4[i] + b[9] * A2[i];
-  w_mat_mul(A6, T1, T2, n, lane);
-  for (int i = lane; i < nn; i += 64) {
-    const int r = i / n, c = i - r * n;
-    T2[i] += b[7] * A6[i] + b[5] * A4[i] + b[3] * A2[i] + (r == c ? b[1] : 0.0);
-  }
-  w_mat_mul(A, T2, T1, n, lane);  // T1 = U
-  for (int i = lane; i < nn; i += 64) T2[i] = b[12] * A6[i] + b[10] * A4[i] + b[8] * A2[i];
-  w_mat_mul(A6, T2, A, n, lane);
-  for (int i = lane; i < nn; i += 64) {
-    const int r = i / n, c = i - r * n;
-    const double V = A[i] + b[6] * A6[i] + b[4] * A4[i] + b[2] * A2[i] + (r == c ? b[0] : 0.0);
-    A2[i] = V - T1[i];
-    A4[i] = V + T1[i];
-  }
-  w_lu_solve(A2, A4, n, n, lane);
-  double *X = A4, *Y = A6;
-  for (int k = 0; k < s; ++k) {
-    w_mat_mul(X, X, Y, n, lane);
-    double *t = X; X = Y; Y = t;
-  }
-  return X;
-}
-
-// One-wave version of hess_phi for m + 1 <= 32 (R holds 7 (m+1)^2 doubles in
-// LDS).  Wave 0 computes; the result is broadcast through LDS.
-template <int BS>
-__device__ double hess_phi_wave(Lds<BS> &L, const double *H, int m, double h, double beta,
-                                double h_next, double *dout) {
-  const int n1 = m + 1;
-  double *M = L.region, *Aug = L.region + n1 * n1, *buf = L.region + 2 * n1 * n1;
-  double *bcast = L.bc;
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    double *P = Aug;
-    if (lane < m)
-      for (int r = 0; r < m; ++r) {
-        P[r * m + lane] = (r <= lane + 1) ? H[r + lane * kHLd] : 0.0;
-        M[r * m + lane] = (r == lane) ? h : 0.0;
-      }
-    w_lu_solve(P, M, m, m, lane);  // M = h H^{-1}
-    double bad = 0.0;
-    for (int i = lane; i < m * m; i += 64)
-      if (!isfinite(M[i])) bad = 1.0;
-    double rho = INFINITY;
-    if (w_max(bad) == 0.0) {
-      for (int i = lane; i < n1 * n1; i += 64) {
-        const int r = i / n1, c = i - r * n1;
-        double v = 0.0;
-        if (r < m && c < m) v = M[r * m + c];
-        else if (r == 0 && c == m) v = 1.0;
-        Aug[i] = v;
-      }
-      const double *E = w_expm_pade13(Aug, buf, n1, lane);
-      double part = 0.0;
-      bad = 0.0;
-      if (lane < m) {
-        double sacc = 0.0;
-        for (int c = 0; c < m; ++c) sacc += M[lane * m + c] * E[c * n1 + m];
-        dout[lane] = -sacc;
-        if (!isfinite(sacc)) bad = 1.0;
-        part = M[(m - 1) * m + lane] * E[lane * n1];
-      }
-      const double my = wave_sum(part);
-      rho = beta * h_next * fabs(my / h);
-      if (w_max(bad) != 0.0 || !isfinite(rho)) rho = INFINITY;
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + q + 4 * v, j = j0 + r;
+      acc[v] = add ? ((i == j ? c0 : 0.0) + c1 * P1[i * ld + j]) + c2 * P2[i * ld + j] : 0.0;
     }
-    if (lane == 0) bcast[0] = rho;
-  }
-  __syncthreads();
-  const double rho = bcast[0];
-  __syncthreads();
-  return rho;
-}
-
-// ---------------------------------------------------------------------------
-// small dense linear algebra for the Hessenberg exponential (row-major, ld n)
-// ---------------------------------------------------------------------------
-
-template <int BS>
-__device__ void mat_mul(const double *A, const double *B, double *C, int n) {
-  for (int idx = threadIdx.x; idx < n * n; idx += BS) {
-    const int r = idx / n, c = idx - r * n;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += A[r * n + k] * B[k * n + c];
-    C[idx] = s;
-  }
-  __syncthreads();
-}
-
-// solve P X = Q (n x n, nrhs columns) by LU with partial pivoting (largest
-// magnitude, first on ties); Q is overwritten by X, P is destroyed.
-template <int BS>
-__device__ void lu_solve(Lds<BS> &L, double *P, double *Q, int n, int nrhs) {
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x < 64) {
-      const int r = k + (int)threadIdx.x;
-      double v = r < n ? fabs(P[r * n + k]) : -1.0;
-      int id = r < n ? r : 0x7fffffff;
+#pragma unroll 4
+    for (int k = 0; k < NP; k += 4) {
+      const double a = A[(i0 + r) * ld + k + q];
+      const double b = B[(k + q) * ld + j0 + r];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        const double ov = __shfl_xor(v, o, 64);
-        const int oid = __shfl_xor(id, o, 64);
-        if (ov > v || (ov == v && oid < id)) { v = ov; id = oid; }
-      }
-      if (threadIdx.x == 0) L.ipiv[0] = (id < n) ? id : k;
-    }
-    __syncthreads();
-    const int pr = L.ipiv[0];
-    if (pr != k) {
-      for (int c = threadIdx.x; c < n + nrhs; c += BS) {
-        double *A = c < n ? P : Q;
-        const int cc = c < n ? c : c - n, ld = c < n ? n : nrhs;
-        const double t0 = A[k * ld + cc];
-        A[k * ld + cc] = A[pr * ld + cc];
-        A[pr * ld + cc] = t0;
-      }
-      __syncthreads();
-    }
-    const double piv = P[k * n + k];
-    const int w = (n - k - 1) + nrhs;
-    const int rows = n - k - 1;
-    for (int idx = threadIdx.x; idx < rows * w; idx += BS) {
-      const int r = k + 1 + idx / w, c = idx % w;
-      const double l = P[r * n + k] / piv;
-      if (c < n - k - 1) P[r * n + (k + 1 + c)] -= l * P[k * n + (k + 1 + c)];
-      else Q[r * nrhs + (c - (n - k - 1))] -= l * Q[k * nrhs + (c - (n - k - 1))];
-    }
-    __syncthreads();
-  }
-  for (int c = threadIdx.x; c < nrhs; c += BS) {
-    for (int r = n - 1; r >= 0; --r) {
-      double s = Q[r * nrhs + c];
-      for (int j = r + 1; j < n; ++j) s -= P[r * n + j] * Q[j * nrhs + c];
-      Q[r * nrhs + c] = s / P[r * n + r];
-    }
+    for (int v = 0; v < 4; ++v) C[(i0 + q + 4 * v) * ld + j0 + r] = acc[v];
   }
   __syncthreads();
 }
 
-// E = exp(A) by scaling and squaring with the degree-13 Pade approximant
-// (Higham, SIAM J. Matrix Anal. Appl. 26(4), 2005).  buf holds 6 n x n
-// matrices; A is destroyed; returns the matrix holding exp(A).
-template <int BS>
-__device__ double *expm_pade13(Lds<BS> &L, double *A, double *buf, int n, bool in_lds) {
-  const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
-                        1187353796428800.0,  129060195264000.0,   10559470521600.0,
-                        670442572800.0,      33522128640.0,       1323241920.0,
-                        40840800.0,          960960.0,            16380.0,
-                        182.0,               1.0};
-  const double theta13 = 5.371920351148152;
-  const int nn = n * n;
-  double *A2 = buf, *A4 = buf + nn, *A6 = buf + 2 * nn, *T1 = buf + 3 * nn, *T2 = buf + 4 * nn;
-  // 1-norm
-  double cs = 0.0;
-  for (int c = threadIdx.x; c < n; c += BS) {
+// entry (r, c) of [H | h I] (m x 2m; zero beyond)
+__device__ __forceinline__ double hess_aug(const GMEM double *H, int m, double h, int r, int c) {
+  if (c >= 2 * m) return 0.0;
+  if (c >= m) return c - m == r ? h : 0.0;
+  return r <= c + 1 ? H[r + c * kHLd] : 0.0;
+}
+
+// X = h H^{-1} for the m x m upper Hessenberg H (column-major, leading
+// dimension kHLd, entries r <= c + 1 stored); U receives the triangular
+// factor.  Both m x m with leading dimension ld.
+template <int BS, bool IN_LDS, class PT>
+__device__ __forceinline__ void hess_inverse(const GMEM double *H, int m, double h, PT U, PT X, int ld) {
+  const int t = tid();
+  if (t < 64) {
+    // lane t owns columns t and t + 64 of [H | h I] (2 m <= 126)
+    double R0 = hess_aug(H, m, h, 0, t), R1 = hess_aug(H, m, h, 0, t + 64);  // the carried row
+    for (int k = 0; k + 1 < m; ++k) {
+      const double F0 = hess_aug(H, m, h, k + 1, t), F1 = hess_aug(H, m, h, k + 1, t + 64);
+      const double Rk = readlane_d(R0, k), Fk = readlane_d(F0, k);
+      const bool sw = fabs(Fk) > fabs(Rk);
+      const double P0 = sw ? F0 : R0, P1 = sw ? F1 : R1;
+      double O0 = sw ? R0 : F0, O1 = sw ? R1 : F1;
+      const double l = (sw ? Rk : Fk) / (sw ? Fk : Rk);
+      if (t > k) O0 -= l * P0;
+      else O0 = 0.0;
+      O1 -= l * P1;  // columns >= 64 are right-hand-side columns (m <= 63)
+      if (t < m) U[k * ld + t] = P0;
+      else if (t < 2 * m) X[k * ld + t - m] = P0;
+      if (t + 64 < 2 * m) X[k * ld + t + 64 - m] = P1;
+      R0 = O0;
+      R1 = O1;
+    }
+    if (t < m) U[(m - 1) * ld + t] = R0;
+    else if (t < 2 * m) X[(m - 1) * ld + t - m] = R0;
+    if (t + 64 < 2 * m) X[(m - 1) * ld + t + 64 - m] = R1;
+  }
+  __syncthreads();
+  // back substitution U X = Y, Y in X: column c by the G lanes of group c
+  const int G = 8 * m <= BS ? 8 : 4;
+  const int c = t / G, p = t % G;
+  const bool own = c < m;
+  for (int r = m - 1; r >= 0; --r) {
     double s = 0.0;
-    for (int r = 0; r < n; ++r) s += fabs(A[r * n + c]);
-    cs = nmax(cs, s);
+    if (own)
+      for (int j = r + 1 + p; j < m; j += G) s += U[r * ld + j] * X[j * ld + c];
+    s = group_sum(s, G);
+    if (own && p == 0) X[r * ld + c] = (X[r * ld + c] - s) / U[r * ld + r];
+    if (IN_LDS) wfence();  // the group's lanes share one wave; LDS is in order
+    else __syncthreads();
+  }
+  __syncthreads();
+}
+
+template <int BS, int NP, bool IN_LDS, class PT>
+__device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM double *H, int m, double h,
+                                              double beta, double h_next, double *dout) {
+  constexpr int ld = NP + 1;
+  PT P1 = base, P2 = base + NP * ld, P3 = base + 2 * NP * ld, Ta = base + 3 * NP * ld, Tb = base + 4 * NP * ld;
+  // ---- M = h H^{-1} into P3 (P2 holds the triangular factor) ----
+  hess_inverse<BS, IN_LDS>(H, m, h, P2, P3, ld);
+  double mbad = 0.0;
+  for (int i = tid(); i < m * m; i += BS)
+    if (!isfinite(P3[(i / m) * ld + i % m])) mbad = 1.0;
+  if (wg_max(L, mbad) != 0.0) return INFINITY;  // H_m singular: not converged
+  // ---- A = [[M, e_1], [0, 0]] padded to NP x NP, in P1 ----
+  for (int i = tid(); i < NP * NP; i += BS) {
+    const int r = i / NP, c = i % NP;
+    P1[r * ld + c] = (r < m && c < m) ? P3[r * ld + c] : (r == 0 && c == m ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double cs = 0.0;
+  if (tid() < NP) {
+#pragma unroll 8
+    for (int r = 0; r < NP; ++r) cs += fabs(P1[r * ld + tid()]);
   }
   const double nrm = wg_max(L, cs);
-  // 2^64 theta13 ~ 1e20: beyond that every entry of exp(A) under- or
-  // overflows anyway, and a non-finite norm is caught by the caller
+  // 2^-s ||A||_1 <= 1; beyond 2^64 every entry of exp(A) under- or overflows
+  // anyway and a non-finite norm is caught below
   int s = 0;
-  if (nrm > theta13) s = (nrm < theta13 * 0x1p64) ? (int)ceil(log2(nrm / theta13)) : 64;
+  if (nrm > 1.0) {
+    int e;
+    const double f = frexp(nrm, &e);
+    s = (!isfinite(nrm) || e > 64) ? 64 : (f == 0.5 ? e - 1 : e);
+  }
   if (s > 0) {
     const double sc = ldexp(1.0, -s);
-    for (int i = threadIdx.x; i < nn; i += BS) A[i] *= sc;
+    for (int i = tid(); i < NP * NP; i += BS) P1[(i / NP) * ld + i % NP] *= sc;
     __syncthreads();
   }
-  mat_mul<BS>(A, A, A2, n);
-  mat_mul<BS>(A2, A2, A4, n);
-  mat_mul<BS>(A4, A2, A6, n);
-  for (int i = threadIdx.x; i < nn; i += BS) T1[i] = b[13] * A6[i] + b[11] * A4[i] + b[9] * A2[i];
-  __syncthreads();
-  mat_mul<BS>(A6, T1, T2, n);
-  for (int i = threadIdx.x; i < nn; i += BS) {
-    const int r = i / n, c = i - r * n;
-    T2[i] += b[7] * A6[i] + b[5] * A4[i] + b[3] * A2[i] + (r == c ? b[1] : 0.0);
+  // ---- Taylor degree 18, Paterson-Stockmeyer with A^3 ----
+  mm_mfma<BS, NP>(P1, P1, P2, ld, false, 0.0, 0.0, 0.0, P1, P1);
+  mm_mfma<BS, NP>(P2, P1, P3, ld, false, 0.0, 0.0, 0.0, P1, P1);
+  for (int i = tid(); i < NP * NP; i += BS) {
+    const int r = i / NP, c = i % NP, o = r * ld + c;
+    Ta[o] = (((r == c ? InvFact<15>::v : 0.0) + InvFact<16>::v * P1[o]) + InvFact<17>::v * P2[o]) + InvFact<18>::v * P3[o];
   }
   __syncthreads();
-  mat_mul<BS>(A, T2, T1, n);  // T1 = U
-  for (int i = threadIdx.x; i < nn; i += BS) T2[i] = b[12] * A6[i] + b[10] * A4[i] + b[8] * A2[i];
-  __syncthreads();
-  mat_mul<BS>(A6, T2, A, n);  // A = A6 * (...)
-  for (int i = threadIdx.x; i < nn; i += BS) {
-    const int r = i / n, c = i - r * n;
-    const double V = A[i] + b[6] * A6[i] + b[4] * A4[i] + b[2] * A2[i] + (r == c ? b[0] : 0.0);
-    A2[i] = V - T1[i];  // P = V - U
-    A4[i] = V + T1[i];  // Q = V + U
-  }
-  __syncthreads();
-  if (in_lds) {  // one wave eliminates: no barrier per pivot step
-    if (threadIdx.x < 64) w_lu_solve(A2, A4, n, n, threadIdx.x);
-    __syncthreads();
-  } else {
-    lu_solve<BS>(L, A2, A4, n, n);
-  }
-  double *X = A4, *Y = A6;
+  mm_mfma<BS, NP>(Ta, P3, Tb, ld, true, InvFact<12>::v, InvFact<13>::v, InvFact<14>::v, P1, P2);
+  mm_mfma<BS, NP>(Tb, P3, Ta, ld, true, InvFact<9>::v, InvFact<10>::v, InvFact<11>::v, P1, P2);
+  mm_mfma<BS, NP>(Ta, P3, Tb, ld, true, InvFact<6>::v, InvFact<7>::v, InvFact<8>::v, P1, P2);
+  mm_mfma<BS, NP>(Tb, P3, Ta, ld, true, InvFact<3>::v, InvFact<4>::v, InvFact<5>::v, P1, P2);
+  mm_mfma<BS, NP>(Ta, P3, Tb, ld, true, InvFact<0>::v, InvFact<1>::v, InvFact<2>::v, P1, P2);
+  // ---- squaring ----
+  PT E = Tb, Y = Ta;
   for (int k = 0; k < s; ++k) {
-    mat_mul<BS>(X, X, Y, n);
-    double *t = X; X = Y; Y = t;
+    mm_mfma<BS, NP>(E, E, Y, ld, false, 0.0, 0.0, 0.0, P1, P1);
+    PT tmp = E;
+    E = Y;
+    Y = tmp;
   }
-  return X;
-}
-
-// Small-matrix part of the MEVP at step h (see hessenberg_phi in the design
-// notes): M = h H_m^{-1}; E = exp([[M, e1], [0, 0]]); y = E[:m, 0],
-// f = E[:m, m]; d = -M f = (I - e^M) e1; rho = beta h_{m+1,m} |(H_m^{-1} y)_m|.
-// d goes to dout (LDS, m doubles).  Returns rho (inf if anything is not finite).
-template <int BS>
-__device__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m, double h,
-                           double beta, double h_next, double *dout) {
-  const int n1 = m + 1;
-  if ((D.variant & 1) && n1 <= 32 && 7 * n1 * n1 <= L.R)
-    return hess_phi_wave<BS>(L, H, m, h, beta, h_next, dout);
-  // 7 matrices of n1 x n1: M, Aug, and 5 work matrices (A2, A4, A6, T1, T2)
-  const bool in_lds = 7 * n1 * n1 <= L.R;
-  double *R = in_lds ? L.region : D.mat;
-  double *M = R, *Aug = R + n1 * n1, *buf = R + 2 * n1 * n1;
-  double *P = Aug;  // H_m copy (m x m) for the inverse, before Aug is built
-  for (int i = threadIdx.x; i < m * m; i += BS) {
-    const int r = i / m, c = i - r * m;
-    P[i] = (r <= c + 1) ? H[r + c * kHLd] : 0.0;  // upper Hessenberg: only these are stored
-    M[i] = (r == c) ? h : 0.0;
+  // ---- d = -M f and (M y)_{m-1};  M = 2^s A[:m, :m] exactly ----
+  double bad = 0.0;
+  for (int r = tid(); r < m; r += BS) {
+    double acc = 0.0;
+    for (int c = 0; c < m; ++c) acc += ldexp(P1[r * ld + c], s) * E[c * ld + m];
+    dout[r] = -acc;
+    if (!isfinite(acc)) bad = 1.0;
   }
-  __syncthreads();
-  if (in_lds) {  // M = h H^{-1}, one wave, Hessenberg elimination
-    if (threadIdx.x < 64) w_hess_solve(P, M, m, m, threadIdx.x);
-    __syncthreads();
-  } else {
-    lu_solve<BS>(L, P, M, m, m);
-  }
-  double mbad = 0.0;
-  for (int i = threadIdx.x; i < m * m; i += BS)
-    if (!isfinite(M[i])) mbad = 1.0;
-  if (wg_max(L, mbad) != 0.0) return INFINITY;  // H_m singular: not converged
-  for (int i = threadIdx.x; i < n1 * n1; i += BS) {
-    const int r = i / n1, c = i - r * n1;
-    double v = 0.0;
-    if (r < m && c < m) v = M[r * m + c];
-    else if (r == 0 && c == m) v = 1.0;
-    Aug[i] = v;
-  }
-  __syncthreads();
-  const double *E = expm_pade13<BS>(L, Aug, buf, n1, in_lds);
-  // d = -M f  with f = E[:m, m]
-  for (int r = threadIdx.x; r < m; r += BS) {
-    double s = 0.0;
-    for (int c = 0; c < m; ++c) s += M[r * m + c] * E[c * n1 + m];
-    dout[r] = -s;
-  }
-  // (M y)_{m-1} with y = E[:m, 0]
-  double part = 0.0, bad = 0.0;
-  for (int c = threadIdx.x; c < m; c += BS) part += M[(m - 1) * m + c] * E[c * n1];
-  for (int r = threadIdx.x; r < m; r += BS)
-    if (!isfinite(dout[r])) bad = 1.0;
+  double part = 0.0;
+  for (int c = tid(); c < m; c += BS) part += ldexp(P1[(m - 1) * ld + c], s) * E[c * ld];
   const double my = wg_sum(L, part);
   const double anybad = wg_max(L, bad);
   double rho = beta * h_next * fabs(my / h);
   if (anybad != 0.0 || !isfinite(rho)) rho = INFINITY;
   return rho;
+}
+
+// d -> dout (LDS, m doubles); returns rho (inf if anything is not finite)
+template <int BS>
+__device__ __forceinline__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m, double h,
+                                           double beta, double h_next, double *dout) {
+  const int n1 = m + 1;
+  if (n1 <= 16 && 5 * 16 * 17 <= L.RD)
+    return hess_phi_np<BS, 16, true>(L, L.dense, gbl(H), m, h, beta, h_next, dout);
+  if (n1 <= 32 && 5 * 32 * 33 <= L.RD)
+    return hess_phi_np<BS, 32, true>(L, L.dense, gbl(H), m, h, beta, h_next, dout);
+  return hess_phi_np<BS, 64, false>(L, gbl(D.mat), gbl(H), m, h, beta, h_next, dout);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,113 +681,151 @@ struct Work {  // exact work counters of one launch
   int trials;
 };
 
-// one Arnoldi step j = B.m: solve -G w = C v_j, MGS against v_0..v_j,
-// h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
-template <int BS>
-__device__ void arnoldi_step(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
-                             double breakdown, Prof &pf) {
-  const int n = D.n, j = B.m;
+// One Arnoldi step j = B.m (Algorithm 1): w = -G^{-1} C v_j, modified
+// Gram-Schmidt against v_0..v_j in increasing order, h_{j+1,j} = ||w||_2,
+// v_{j+1} = w / h_{j+1,j}.  v_j is in the LDS vector area on entry and
+// v_{j+1} on exit.  Thread t owns rows t + e BS (e < E): C v_j is gathered
+// from LDS with the ELL loads of all E rows issued together, w stays in
+// registers through the Gram-Schmidt sweep, and v_{i+1} is loaded while the
+// inner product with v_i is reduced.
+template <int BS, int E>
+__device__ __forceinline__ void arnoldi_step_e(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
+                               double breakdown, Prof &pf) {
+  const int n = D.n, j = B.m, t0 = tid();
   const int64_t ldv = D.ldv;
   double *xs = L.region;
   double *hcol = L.hcol;  // this step's Hessenberg column, stored to H once at the end
-  const double *vj = V + (int64_t)j * ldv;
-  for (int i = threadIdx.x; i < n; i += BS) xs[i] = -c_row(D, vj, i);
+  GMEM double *Vg = gbl(V);
+  GMEM double *Hg = gbl(H);
+  // ---- q = C v_j: one ELL column at a time, its loads for all E rows together ----
+  double w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) w[e] = 0.0;
+  const int K = D.c_ell_k;
+  for (int k = 0; k < K; ++k) {
+    const GMEM int *__restrict__ ccol = gbl(D.c_ell_col) + (int64_t)k * n;
+    const GMEM double *__restrict__ cval = gbl(D.c_ell_val) + (int64_t)k * n;
+    int cc[E];
+    double cv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t0 + e * BS;
+      cc[e] = i < n ? ccol[i] : -1;
+      cv[e] = i < n ? cval[i] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (cc[e] >= 0) w[e] += cv[e] * xs[cc[e]];
+  }
   __syncthreads();
-  solve_lds<BS>(D, xs, D.variant);
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (t0 + e * BS < n) xs[t0 + e * BS] = -w[e];
+  __syncthreads();
+  solve_lds<BS>(D, xs);
   pf.mark(2);
-  constexpr int E = (4608 + BS - 1) / BS;  // elements per thread in registers (n <= E * BS)
-  const int t0 = threadIdx.x;
-  if (!(D.variant & 2) && n <= E * BS) {
-    // modified Gram-Schmidt with v_i held in registers for its inner
-    // product and its update, and v_{i+1} loaded before the reduction
-    double cur[E], nxt[E];
+  // ---- modified Gram-Schmidt ----
 #pragma unroll
-    for (int e = 0; e < E; ++e) cur[e] = (t0 + e * BS < n) ? V[t0 + e * BS] : 0.0;
-    for (int i = 0; i <= j; ++i) {
-      double part = 0.0;
+  for (int e = 0; e < E; ++e) w[e] = t0 + e * BS < n ? xs[t0 + e * BS] : 0.0;
+  double cur[E], nxt[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (t0 + e * BS < n) part += xs[t0 + e * BS] * cur[e];
-      if (i < j) {
-        const double *vn = V + (int64_t)(i + 1) * ldv;
+  for (int e = 0; e < E; ++e) cur[e] = t0 + e * BS < n ? Vg[t0 + e * BS] : 0.0;
+  for (int i = 0; i <= j; ++i) {
+    double part = 0.0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) nxt[e] = (t0 + e * BS < n) ? vn[t0 + e * BS] : 0.0;
-      }
-      const double hij = wg_sum(L, part);
+    for (int e = 0; e < E; ++e) part += w[e] * cur[e];
+    if (i < j) {
+      const GMEM double *vn = Vg + (int64_t)(i + 1) * ldv;
 #pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (t0 + e * BS < n) xs[t0 + e * BS] -= hij * cur[e];
-      if (t0 == 0) hcol[i] = hij;
-      B.hscale = nmax(B.hscale, fabs(hij));
-#pragma unroll
-      for (int e = 0; e < E; ++e) cur[e] = nxt[e];
+      for (int e = 0; e < E; ++e) nxt[e] = t0 + e * BS < n ? vn[t0 + e * BS] : 0.0;
     }
-  } else {
-    for (int i = 0; i <= j; ++i) {
-      const double *vi = V + (int64_t)i * ldv;
-      double part = 0.0;
-      for (int t = t0; t < n; t += BS) part += xs[t] * vi[t];
-      const double hij = wg_sum(L, part);
-      for (int t = t0; t < n; t += BS) xs[t] -= hij * vi[t];
-      if (t0 == 0) hcol[i] = hij;
-      B.hscale = nmax(B.hscale, fabs(hij));
-    }
+    const double hij = wg_sum(L, part);
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[e] -= hij * cur[e];
+    if (t0 == 0) hcol[i] = hij;
+    B.hscale = nmax(B.hscale, fabs(hij));
+#pragma unroll
+    for (int e = 0; e < E; ++e) cur[e] = nxt[e];
   }
   double part = 0.0;
-  for (int t = t0; t < n; t += BS) part += xs[t] * xs[t];
+#pragma unroll
+  for (int e = 0; e < E; ++e) part += w[e] * w[e];
   const double hn = sqrt(wg_sum(L, part));
   B.hscale = nmax(B.hscale, hn);
   B.m = j + 1;
   const bool brk = hn <= breakdown * B.hscale;
   if (brk) B.exact = 1;
   if (!brk) {
-    double *vn = V + (int64_t)(j + 1) * ldv;
-    for (int t = t0; t < n; t += BS) vn[t] = xs[t] / hn;
+    GMEM double *vn = Vg + (int64_t)(j + 1) * ldv;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (t0 + e * BS < n) {
+        const double v = w[e] / hn;
+        vn[t0 + e * BS] = v;
+        xs[t0 + e * BS] = v;
+      }
   }
-  for (int i = t0; i <= j; i += BS) H[i + j * kHLd] = hcol[i];
-  if (t0 == 0) H[j + 1 + j * kHLd] = brk ? 0.0 : hn;
+  for (int i = t0; i <= j; i += BS) Hg[i + j * kHLd] = hcol[i];
+  if (t0 == 0) Hg[j + 1 + j * kHLd] = brk ? 0.0 : hn;
   __syncthreads();
   pf.mark(3);
 }
 
-// Start a basis from the vector in LDS xs: beta = ||v||, v_0 = v / beta.
+// rows per thread: 4 when n <= 4 BS, else 9 (set-up keeps n <= 9 BS)
 template <int BS>
-__device__ void basis_start(const InstDesc &D, Lds<BS> &L, const double *v, double *V, Basis &B) {
+__device__ __forceinline__ void arnoldi_step(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
+                             double breakdown, Prof &pf) {
+  if (D.n <= 4 * BS) arnoldi_step_e<BS, 4>(D, L, V, H, B, breakdown, pf);
+  else arnoldi_step_e<BS, 9>(D, L, V, H, B, breakdown, pf);
+}
+
+// Start a basis from the vector v (global or the LDS vector area):
+// beta = ||v||_2, v_0 = v / beta, written to V and to the LDS vector area.
+template <int BS>
+__device__ __forceinline__ void basis_start(const InstDesc &D, Lds<BS> &L, const double *v, double *V, Basis &B) {
   double part = 0.0;
-  for (int t = threadIdx.x; t < D.n; t += BS) part += v[t] * v[t];
+  for (int t = tid(); t < D.n; t += BS) part += v[t] * v[t];
   B.beta = sqrt(wg_sum(L, part));
   B.m = 0;
   B.exact = B.beta == 0.0;
   B.hscale = 0.0;
   if (B.beta > 0.0)
-    for (int t = threadIdx.x; t < D.n; t += BS) V[t] = v[t] / B.beta;
+    for (int t = tid(); t < D.n; t += BS) {
+      const double u = v[t] / B.beta;
+      gbl(V)[t] = u;
+      L.region[t] = u;
+    }
   __syncthreads();
 }
 
 // grow the basis until rho_m(h) <= eps; d -> dout.  Returns a status code.
 template <int BS>
-__device__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, double *V, double *H,
+__device__ __forceinline__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, double *V, double *H,
                              Basis &B, double h, double eps, double *dout, double &rho,
                              int &iters, Prof &pf, Work &wk) {
   if (B.beta == 0.0) {
     rho = 0.0;
     return kOK;
   }
-  if (B.m > 0) {
-    rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : H[B.m + (B.m - 1) * kHLd], dout);
-    pf.mark(4);
-    if (rho <= eps) return kOK;
-    if (B.exact) return kEKRYLOV;
-  }
-  for (;;) {
+  // one call site each for the residual test and the Arnoldi step (the code
+  // is inlined: a second copy would only cost instruction cache)
+  for (int it = 0;; ++it) {
+    if (B.m > 0) {
+      rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : gbl(H)[B.m + (B.m - 1) * kHLd], dout);
+      pf.mark(4);
+      if (rho <= eps) return kOK;
+      if (B.exact) return kEKRYLOV;
+      if (it == 0) {
+        // a reused basis continues from v_m; the LDS vector area has been reused
+        const GMEM double *vm = gbl(V) + (int64_t)B.m * D.ldv;
+        for (int t = tid(); t < D.n; t += BS) L.region[t] = vm[t];
+        __syncthreads();
+      }
+    }
     if (B.m >= o.m_max) return kEKRYLOV;
     arnoldi_step<BS>(D, L, V, H, B, o.breakdown, pf);
     ++iters;
     wk.mgs += B.m;
-    rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : H[B.m + (B.m - 1) * kHLd], dout);
-    pf.mark(4);
-    if (rho <= eps) return kOK;
-    if (B.exact) return kEKRYLOV;
   }
 }
 
@@ -942,10 +834,11 @@ __device__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, doubl
 // ---------------------------------------------------------------------------
 
 template <int BS>
-__device__ Lds<BS> lds_setup(int R) {
+__device__ Lds<BS> lds_setup(int R, int NX) {
   extern __shared__ double smem[];
   Lds<BS> L;
   L.region = smem;
+  L.dense = smem + NX;
   L.slots = smem + R;
   L.dmain = L.slots + 2 * (BS / 64);
   L.derr = L.dmain + kHLd;
@@ -954,6 +847,7 @@ __device__ Lds<BS> lds_setup(int R) {
   L.prof = reinterpret_cast<long long *>(L.derr + kHLd + 4);
   L.hcol = L.derr + kHLd + 4 + kPhases;
   L.R = R;
+  L.RD = R - NX;
   L.par = 0;
   return L;
 }
@@ -962,8 +856,8 @@ __device__ Lds<BS> lds_setup(int R) {
 __global__ void k_begin(const InstDesc *descs, const double *const *xin, double t0, double h0) {
   const InstDesc &D = descs[blockIdx.x];
   const double *x = xin[blockIdx.x];
-  for (int i = threadIdx.x; i < D.n; i += blockDim.x) D.xk[i] = x[D.perm[i]];
-  if (threadIdx.x == 0) {
+  for (int i = tid(); i < D.n; i += blockDim.x) gbl(D.xk)[i] = x[gbl(D.perm)[i]];
+  if (tid() == 0) {
     InstState &S = *D.state;
     S.t = t0;
     S.h_prop = fmin(h0, D.h_max);
@@ -979,7 +873,7 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
     S.comb_terms = 0;
     for (int i = 0; i < kPhases; ++i) S.ph[i] = 0.0;
     int b = 0;
-    while (b < D.n_bp - 1 && D.bp[b] <= t0) ++b;
+    while (b < D.n_bp - 1 && gbl(D.bp)[b] <= t0) ++b;
     S.bp_idx = b;
   }
 }
@@ -988,20 +882,20 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
 __global__ void k_end(const InstDesc *descs, double *const *xout) {
   const InstDesc &D = descs[blockIdx.x];
   double *x = xout[blockIdx.x];
-  for (int i = threadIdx.x; i < D.n; i += blockDim.x) x[D.perm[i]] = D.xk[i];
+  for (int i = tid(); i < D.n; i += blockDim.x) x[gbl(D.perm)[i]] = gbl(D.xk)[i];
 }
 
 // The ER transient (Algorithm 2), resumable: runs at most max_steps accepted
 // steps of every unfinished instance.  replay != 0: the step ends are taken
-// from D.bp (the given grid) and every first trial is accepted.
+// from gbl(D.bp) (the given grid) and every first trial is accepted.
 template <int BS>
 __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *order, Opts o,
-                                            int max_steps, int replay, int R) {
+                                            int max_steps, int replay, int R, int NX) {
   // workgroups start in blockIdx order: order[] lists the largest instances first
   const InstDesc &D = descs[order[blockIdx.x]];
   InstState &S = *D.state;
   if (S.done) return;
-  Lds<BS> L = lds_setup<BS>(R);
+  Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
   const int n = D.n;
   double t = S.t, h_prop = S.h_prop;
@@ -1025,11 +919,11 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     double h_try, t_land;
     bool land;
     if (replay) {
-      t_land = D.bp[steps];
+      t_land = gbl(D.bp)[steps];
       h_try = t_land - t;
       land = true;
     } else {
-      t_land = D.bp[bp_idx];
+      t_land = gbl(D.bp)[bp_idx];
       h_try = fmin(h_prop, D.h_max);
       land = false;
       if (t + h_try * (1.0 + 1e-3) >= t_land) {
@@ -1049,32 +943,30 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
       lu_valid = 1;
     }
     pf.mark(0);
-    // ---- w = G^{-1} r,  r = B u(t) - G_lin x_k - I_dev(x_k) ----
-    for (int i = threadIdx.x; i < n; i += BS) {
-      double bu = 0.0;
-      for (int e = D.b_rowptr[i]; e < D.b_rowptr[i + 1]; ++e) bu += D.b_val[e] * pwl_value(D, D.b_col[e], t);
-      xs[i] = (bu - csr_row_dot(D.g_rowptr, D.g_col, D.g_val, D.xk, i)) - D.Ik[i];
-    }
-    __syncthreads();
-    solve_lds<BS>(D, xs);
-    for (int i = threadIdx.x; i < n; i += BS) D.w[i] = xs[i];
-    // ---- p = G^{-1} B s ----
+    // ---- the three right-hand sides, one solve each (one loop, one copy of
+    // the solve code):  w = G^{-1} r with r = B u(t) - G_lin x_k - I_dev(x_k);
+    // p = G^{-1} B s;  z = G^{-1} C p, leaving v = w - z in tmp ----
     const double tm = t + 0.5 * h_try;
-    for (int i = threadIdx.x; i < n; i += BS) {
-      double bs = 0.0;
-      for (int e = D.b_rowptr[i]; e < D.b_rowptr[i + 1]; ++e) bs += D.b_val[e] * pwl_slope(D, D.b_col[e], tm);
-      xs[i] = bs;
+#pragma nounroll
+    for (int rhs = 0; rhs < 3; ++rhs) {
+      for (int i = tid(); i < n; i += BS) {
+        double b = 0.0;
+        if (rhs == 0) {
+          for (int e = gbl(D.b_rowptr)[i]; e < gbl(D.b_rowptr)[i + 1]; ++e) b += gbl(D.b_val)[e] * pwl_value(D, gbl(D.b_col)[e], t);
+          b = (b - csr_row_dot(D.g_rowptr, D.g_col, D.g_val, D.xk, i)) - gbl(D.Ik)[i];
+        } else if (rhs == 1) {
+          for (int e = gbl(D.b_rowptr)[i]; e < gbl(D.b_rowptr)[i + 1]; ++e) b += gbl(D.b_val)[e] * pwl_slope(D, gbl(D.b_col)[e], tm);
+        } else {
+          b = c_row(D, D.p, i);
+        }
+        xs[i] = b;
+      }
+      __syncthreads();
+      solve_lds<BS>(D, xs);
+      GMEM double *dst = rhs == 0 ? gbl(D.w) : rhs == 1 ? gbl(D.p) : gbl(D.tmp);
+      for (int i = tid(); i < n; i += BS) dst[i] = rhs == 2 ? gbl(D.w)[i] - xs[i] : xs[i];
+      __syncthreads();
     }
-    __syncthreads();
-    solve_lds<BS>(D, xs);
-    for (int i = threadIdx.x; i < n; i += BS) D.p[i] = xs[i];
-    __syncthreads();
-    // ---- z = G^{-1} C p ;  v = w - z ----
-    for (int i = threadIdx.x; i < n; i += BS) xs[i] = c_row(D, D.p, i);
-    __syncthreads();
-    solve_lds<BS>(D, xs);
-    for (int i = threadIdx.x; i < n; i += BS) D.tmp[i] = D.w[i] - xs[i];
-    __syncthreads();
     Basis Bm;
     basis_start<BS>(D, L, D.tmp, D.V, Bm);
     pf.mark(1);
@@ -1088,12 +980,16 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
       wk.comb += Bm.m;
       // x_{k+1} = x_k + h p + beta V_m d
       double bad = 0.0;
-      for (int i = threadIdx.x; i < n; i += BS) {
-        double acc = 0.0;
-        for (int j = 0; j < Bm.m; ++j) acc += D.V[(int64_t)j * D.ldv + i] * L.dmain[j];
-        const double v = (D.xk[i] + h * D.p[i]) + Bm.beta * acc;
-        D.x1[i] = v;
-        if (!isfinite(v)) bad = 1.0;
+      {
+        const GMEM double *Vg = gbl(D.V), *xk = gbl(D.xk), *pp = gbl(D.p);
+        GMEM double *x1 = gbl(D.x1);
+        for (int i = tid(); i < n; i += BS) {
+          double acc = 0.0;
+          for (int j = 0; j < Bm.m; ++j) acc += Vg[(int64_t)j * D.ldv + i] * L.dmain[j];
+          const double v = (xk[i] + h * pp[i]) + Bm.beta * acc;
+          x1[i] = v;
+          if (!isfinite(v)) bad = 1.0;
+        }
       }
       if (wg_max(L, bad) != 0.0) { status = kENONFINITE; break; }
       err = 0.0;
@@ -1102,16 +998,16 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
         stamp_devices<BS>(D, D.x1, D.devI1, nullptr);
         __syncthreads();
         // dF = J_dev(x_k)(x_{k+1} - x_k) - (I_dev(x_{k+1}) - I_dev(x_k))
-        for (int i = threadIdx.x; i < n; i += BS) {
+        for (int i = tid(); i < n; i += BS) {
           double s = 0.0;
-          for (int c = D.node_ptr[i]; c < D.node_ptr[i + 1]; ++c) {
-            const int code = D.node_code[c], k = code >> 1;
+          for (int c = gbl(D.node_ptr)[i]; c < gbl(D.node_ptr)[i + 1]; ++c) {
+            const int code = gbl(D.node_code)[c], k = code >> 1;
             double lin = 0.0;
             for (int v = 0; v < 3; ++v) {
-              const int nd = D.dev_node[3 * k + v];
-              if (nd >= 0) lin += D.devD[3 * k + v] * (D.x1[nd] - D.xk[nd]);
+              const int nd = gbl(D.dev_node)[3 * k + v];
+              if (nd >= 0) lin += gbl(D.devD)[3 * k + v] * (D.x1[nd] - gbl(D.xk)[nd]);
             }
-            const double df = lin - (D.devI1[k] - D.devI[k]);
+            const double df = lin - (D.devI1[k] - gbl(D.devI)[k]);
             s += (code & 1) ? -df : df;
           }
           xs[i] = s;
@@ -1127,9 +1023,10 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
         m_err = Be.m;
         wk.comb += Be.m;
         double emax = 0.0;
-        for (int i = threadIdx.x; i < n; i += BS) {
+        const GMEM double *Veg = gbl(D.Ve);
+        for (int i = tid(); i < n; i += BS) {
           double acc = 0.0;
-          for (int j = 0; j < Be.m; ++j) acc += D.Ve[(int64_t)j * D.ldv + i] * L.derr[j];
+          for (int j = 0; j < Be.m; ++j) acc += Veg[(int64_t)j * D.ldv + i] * L.derr[j];
           emax = nmax(emax, fabs(Be.beta * acc));
         }
         err = wg_max(L, emax);
@@ -1143,23 +1040,23 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     if (status != kOK) break;
     // ---- accept ----
     const double t_new = (land && rej == 0) ? t_land : t + h;
-    for (int i = threadIdx.x; i < n; i += BS) D.xk[i] = D.x1[i];
-    double *r = D.trace + (int64_t)(steps - steps0) * rec;
-    if (threadIdx.x == 0) {
+    for (int i = tid(); i < n; i += BS) gbl(D.xk)[i] = gbl(D.x1)[i];
+    GMEM double *r = gbl(D.trace) + (int64_t)(steps - steps0) * rec;
+    if (tid() == 0) {
       r[0] = t_new; r[1] = h; r[2] = h_try; r[3] = Bm.m;
       r[4] = m_err; r[5] = rej; r[6] = err; r[7] = rho;
     }
-    for (int q = threadIdx.x; q < D.n_probe; q += BS) r[kRecFixed + q] = D.x1[D.probe[q]];
+    for (int q = tid(); q < D.n_probe; q += BS) r[kRecFixed + q] = gbl(D.x1)[gbl(D.probe)[q]];
     __syncthreads();
     const double grow = rej < o.grow_if_rejects_lt ? o.beta : 1.0;
     h_prop = fmin(D.h_max, grow * (rej == 0 ? h_prop : h));
     t = t_new;
     if (!replay)
-      while (bp_idx < D.n_bp - 1 && D.bp[bp_idx] <= t) ++bp_idx;
+      while (bp_idx < D.n_bp - 1 && gbl(D.bp)[bp_idx] <= t) ++bp_idx;
     rej_total += rej;
     ++steps;
   }
-  if (threadIdx.x == 0) {
+  if (tid() == 0) {
     S.t = t;
     S.h_prop = h_prop;
     S.bp_idx = bp_idx;
@@ -1186,10 +1083,10 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
 // then full Newton (uniformly damped to vclip) until max|dx| <= 1e-12 V.
 template <int BS>
 __global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, Opts o, double t0, int max_it,
-                                           int R) {
+                                           int R, int NX) {
   const InstDesc &D = descs[blockIdx.x];
   InstState &S = *D.state;
-  Lds<BS> L = lds_setup<BS>(R);
+  Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
   const int n = D.n;
   const double vclip = 0.3;
@@ -1205,21 +1102,21 @@ __global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, Opts o, double
       assemble<BS>(D, block);
       __syncthreads();
       if (!refactor<BS>(D, L, o.piv_tol)) { status = kESINGULAR; break; }
-      for (int i = threadIdx.x; i < n; i += BS) {
+      for (int i = tid(); i < n; i += BS) {
         double bu = 0.0;
-        for (int e = D.b_rowptr[i]; e < D.b_rowptr[i + 1]; ++e) bu += D.b_val[e] * pwl_value(D, D.b_col[e], t0);
-        xs[i] = (bu - csr_row_dot(D.g_rowptr, D.g_col, D.g_val, D.xk, i)) - D.Ik[i];
+        for (int e = gbl(D.b_rowptr)[i]; e < gbl(D.b_rowptr)[i + 1]; ++e) bu += gbl(D.b_val)[e] * pwl_value(D, gbl(D.b_col)[e], t0);
+        xs[i] = (bu - csr_row_dot(D.g_rowptr, D.g_col, D.g_val, D.xk, i)) - gbl(D.Ik)[i];
       }
       __syncthreads();
       solve_lds<BS>(D, xs);
       double big = 0.0;
-      for (int i = threadIdx.x; i < n; i += BS) big = nmax(big, fabs(xs[i]));
+      for (int i = tid(); i < n; i += BS) big = nmax(big, fabs(xs[i]));
       big = wg_max(L, big);
       if (!isfinite(big)) { status = kENONFINITE; break; }
       const double sc = (!block && big > vclip) ? vclip / big : 1.0;
-      for (int i = threadIdx.x; i < n; i += BS) {
+      for (int i = tid(); i < n; i += BS) {
         const double dx = xs[i];
-        D.xk[i] += block ? fmin(fmax(dx, -vclip), vclip) : sc * dx;
+        gbl(D.xk)[i] += block ? fmin(fmax(dx, -vclip), vclip) : sc * dx;
       }
       __syncthreads();
       if (big <= tol) { conv = true; break; }
@@ -1230,7 +1127,7 @@ __global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, Opts o, double
       break;
     }
   }
-  if (threadIdx.x == 0) {
+  if (tid() == 0) {
     S.status = status;
     S.steps = its;
   }
@@ -1240,37 +1137,37 @@ __global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, Opts o, double
 
 // stamp + assemble + refactor at x_k
 template <int BS>
-__global__ void __launch_bounds__(BS) k_factor(const InstDesc *descs, Opts o, int R) {
+__global__ void __launch_bounds__(BS) k_factor(const InstDesc *descs, Opts o, int R, int NX) {
   const InstDesc &D = descs[blockIdx.x];
-  Lds<BS> L = lds_setup<BS>(R);
+  Lds<BS> L = lds_setup<BS>(R, NX);
   stamp_devices<BS>(D, D.xk, D.devI, D.devD);
   __syncthreads();
   assemble<BS>(D, false);
   __syncthreads();
   const bool ok = refactor<BS>(D, L, o.piv_tol);
-  if (threadIdx.x == 0) D.state->status = ok ? kOK : kESINGULAR;
+  if (tid() == 0) D.state->status = ok ? kOK : kESINGULAR;
 }
 
 // y = G_k^{-1} b with the current factors (caller numbering in and out)
 template <int BS>
 __global__ void __launch_bounds__(BS) k_solve(const InstDesc *descs, const double *const *bin,
-                                              double *const *yout, int R) {
+                                              double *const *yout, int R, int NX) {
   const InstDesc &D = descs[blockIdx.x];
-  Lds<BS> L = lds_setup<BS>(R);
+  Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
-  for (int i = threadIdx.x; i < D.n; i += BS) xs[i] = bin[blockIdx.x][D.perm[i]];
+  for (int i = tid(); i < D.n; i += BS) xs[i] = bin[blockIdx.x][gbl(D.perm)[i]];
   __syncthreads();
   solve_lds<BS>(D, xs);
-  for (int i = threadIdx.x; i < D.n; i += BS) yout[blockIdx.x][D.perm[i]] = xs[i];
+  for (int i = tid(); i < D.n; i += BS) yout[blockIdx.x][gbl(D.perm)[i]] = xs[i];
 }
 
 // out = (I - e^{hJ}) v by MEVP_IKS with the current factors; reports m, rho
 template <int BS>
 __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, const double *const *vin,
-                                             double *const *out, double h, double eps, int R) {
+                                             double *const *out, double h, double eps, int R, int NX) {
   const InstDesc &D = descs[blockIdx.x];
-  Lds<BS> L = lds_setup<BS>(R);
-  for (int i = threadIdx.x; i < D.n; i += BS) D.tmp[i] = vin[blockIdx.x][D.perm[i]];
+  Lds<BS> L = lds_setup<BS>(R, NX);
+  for (int i = tid(); i < D.n; i += BS) gbl(D.tmp)[i] = vin[blockIdx.x][gbl(D.perm)[i]];
   __syncthreads();
   Basis B;
   basis_start<BS>(D, L, D.tmp, D.V, B);
@@ -1281,12 +1178,12 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
   Work wk{0, 0, 0};
   __syncthreads();
   const int st = mevp_converge<BS>(D, L, o, D.V, D.H, B, h, eps, L.dmain, rho, iters, pf, wk);
-  for (int i = threadIdx.x; i < D.n; i += BS) {
+  for (int i = tid(); i < D.n; i += BS) {
     double acc = 0.0;
-    for (int j = 0; j < B.m; ++j) acc += D.V[(int64_t)j * D.ldv + i] * L.dmain[j];
-    out[blockIdx.x][D.perm[i]] = B.beta * acc;
+    for (int j = 0; j < B.m; ++j) acc += gbl(D.V)[(int64_t)j * D.ldv + i] * L.dmain[j];
+    out[blockIdx.x][gbl(D.perm)[i]] = B.beta * acc;
   }
-  if (threadIdx.x == 0) {
+  if (tid() == 0) {
     D.state->status = st;
     D.state->arnoldi = B.m;
     D.state->t = rho;
@@ -1330,79 +1227,57 @@ hipError_t set_lds_limits(size_t bytes) {
 // 5 level loop with barriers only, 6 MGS step against 9 basis vectors).
 // Writes wall-clock ticks to out[0].
 template <int BS>
-__global__ void __launch_bounds__(BS) k_diag(const InstDesc *descs, int what, int reps, long long *out,
-                                             int R) {
+__global__ void __launch_bounds__(BS) k_diag(const InstDesc *descs, int what, int reps, int arg,
+                                             long long *out, int R, int NX) {
   const InstDesc &D = descs[0];
-  Lds<BS> L = lds_setup<BS>(R);
+  Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
   const int n = D.n;
-  for (int i = threadIdx.x; i < n; i += BS) xs[i] = D.p[i];
+  // finite data in the vector area, the first arg + 2 basis columns and a
+  // synthetic Hessenberg (diagonally dominant, entries of the size a circuit
+  // gives: time constants of 0.1 ps and up)
+  for (int i = tid(); i < n; i += BS) xs[i] = 1.0 / (1.0 + i);
+  for (int c = 0; c < arg + 2 && c <= kMaxKrylov; ++c)
+    for (int i = tid(); i < n; i += BS) gbl(D.V)[(int64_t)c * D.ldv + i] = (((i * 7 + c * 3) % 11) - 5) * 0.01;
+  for (int idx = tid(); idx < kHLd * kMaxKrylov; idx += BS) {
+    const int r = idx % kHLd, c = idx / kHLd;
+    double v = 0.0;
+    if (r == c) v = -1e-13 * (1.0 + 0.5 * r);
+    else if (r == c + 1) v = 3e-14;
+    else if (r < c) v = 1e-14 / (1 + c - r);
+    gbl(D.He)[idx] = v;
+  }
   __syncthreads();
+  Prof pf;
+  pf.start(L.prof);
   double acc = 0.0;
   const long long t0 = wall_clock64();
   for (int r = 0; r < reps; ++r) {
-    if (what == 0) {
-      solve_lds<BS>(D, xs);
-    } else if (what == 1 || what == 2) {
-      InstDesc E = D;
-      if (what == 1) E.n_usched = 0; else E.n_lsched = 0;
-      solve_lds<BS>(E, xs);
+    if (what <= 2) {
+      solve_lds<BS>(D, xs, what != 2, what != 1);
     } else if (what == 3) {
-      for (int i = threadIdx.x; i < n; i += BS) xs[i] = c_row(D, D.p, i);
-      __syncthreads();
+      Basis B{arg, 0, 1.0, 0.0};
+      arnoldi_step<BS>(D, L, D.V, D.H, B, 0.0, pf);
     } else if (what == 4) {
       acc += wg_sum(L, acc + 1.0);
     } else if (what == 5) {
-      for (int l = 0; l < D.n_lsched + D.n_usched; ++l) __syncthreads();
+      for (int l = 0; l < D.n_lpass + D.n_upass; ++l) __syncthreads();
     } else if (what == 6) {
-      for (int i = 0; i < 9; ++i) {
-        const double *vi = D.V + (int64_t)i * D.ldv;
-        double part = 0.0;
-        for (int t = threadIdx.x; t < n; t += BS) part += xs[t] * vi[t];
-        const double hij = wg_sum(L, part) * 1e-300;
-        for (int t = threadIdx.x; t < n; t += BS) xs[t] -= hij * vi[t];
-      }
-    } else if (what == 7 || what == 8 || what == 9) {
-      // 7: register MGS as in arnoldi_step; 8: its loads and dots without the
-      // reduction; 9: its reductions without loads
-      constexpr int E = (4608 + BS - 1) / BS;
-      const int t0 = threadIdx.x;
-      const double *V = D.V;
-      const int64_t ldv = D.ldv;
-      double cur[E], nxt[E];
-#pragma unroll
-      for (int e = 0; e < E; ++e) cur[e] = (what != 9 && t0 + e * BS < n) ? V[t0 + e * BS] : 0.0;
-      for (int i = 0; i < 9; ++i) {
-        double part = 0.0;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (t0 + e * BS < n) part += xs[t0 + e * BS] * cur[e];
-        if (what != 9 && i < 8) {
-          const double *vn = V + (int64_t)(i + 1) * ldv;
-#pragma unroll
-          for (int e = 0; e < E; ++e) nxt[e] = (t0 + e * BS < n) ? vn[t0 + e * BS] : 0.0;
-        }
-        const double hij = (what != 8 ? wg_sum(L, part) : part) * 1e-300;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (t0 + e * BS < n) xs[t0 + e * BS] -= hij * cur[e];
-        if (what != 9)
-#pragma unroll
-          for (int e = 0; e < E; ++e) cur[e] = nxt[e];
-      }
+      acc += hess_phi<BS>(D, L, D.He, arg, 2e-12, 1.0, 1e-14, L.derr);
     }
   }
   const long long t1 = wall_clock64();
-  if (threadIdx.x == 0) { out[0] = t1 - t0; out[1] = (long long)acc; }
+  if (tid() == 0) { out[0] = t1 - t0; out[1] = (long long)acc; }
 }
 
-hipError_t launch_diag(const InstDesc *d, int what, int reps, long long *out, int bs, int R, hipStream_t s) {
+hipError_t launch_diag(const InstDesc *d, int what, int reps, int arg, long long *out, int bs, int R, int NX,
+                       hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
   EXPRI_DISPATCH(bs, {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_diag<BS>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag<BS>, dim3(1), dim3(BS), sh, s, d, what, reps, out, R);
+    hipLaunchKernelGGL(k_diag<BS>, dim3(1), dim3(BS), sh, s, d, what, reps, arg, out, R, NX);
   });
   return hipGetLastError();
 }
@@ -1419,37 +1294,37 @@ hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStr
 }
 
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
-                      int replay, int bs, int R, hipStream_t s) {
+                      int replay, int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
   EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_run<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, o, max_steps,
-                                        replay, R));
+                                        replay, R, NX));
   return hipGetLastError();
 }
 
-hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R,
+hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R, int NX,
                      hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_dc<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, t0, max_it, R));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_dc<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, t0, max_it, R, NX));
   return hipGetLastError();
 }
 
-hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, hipStream_t s) {
+hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_factor<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, R));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_factor<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, R, NX));
   return hipGetLastError();
 }
 
 hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, double *const *y, int bs,
-                        int R, hipStream_t s) {
+                        int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_solve<BS>, dim3(n_inst), dim3(BS), sh, s, d, b, y, R));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_solve<BS>, dim3(n_inst), dim3(BS), sh, s, d, b, y, R, NX));
   return hipGetLastError();
 }
 
 hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
-                       double *const *out, double h, double eps, int bs, int R, hipStream_t s) {
+                       double *const *out, double h, double eps, int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_mevp<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, v, out, h, eps, R));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_mevp<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, v, out, h, eps, R, NX));
   return hipGetLastError();
 }
 

@@ -26,15 +26,16 @@ hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin,
                         hipStream_t s);
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
-                      int replay, int bs, int R, hipStream_t s);
-hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R,
+                      int replay, int bs, int R, int NX, hipStream_t s);
+hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R, int NX,
                      hipStream_t s);
-hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, hipStream_t s);
+hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, int NX, hipStream_t s);
 hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, double *const *y, int bs,
-                        int R, hipStream_t s);
+                        int R, int NX, hipStream_t s);
 hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
-                       double *const *out, double h, double eps, int bs, int R, hipStream_t s);
-hipError_t launch_diag(const InstDesc *d, int what, int reps, long long *out, int bs, int R, hipStream_t s);
+                       double *const *out, double h, double eps, int bs, int R, int NX, hipStream_t s);
+hipError_t launch_diag(const InstDesc *d, int what, int reps, int arg, long long *out, int bs, int R, int NX,
+                       hipStream_t s);
 }  // namespace expri
 
 using namespace expri;
@@ -64,9 +65,9 @@ struct PatternDev {
   Symbolic sym;
   // flattened solve schedules and C ELL pattern (depend on the block size)
   std::vector<SolveLevel> lsched, usched;
-  std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col;
-  int32_t c_ell_k = 0;
-  size_t o_lsched, o_usched, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col;
+  std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code;
+  int32_t c_ell_k = 0, n_lpass = 0, n_upass = 0, pl = 1, pu = 1, u_slot_base = 0, u_row_base = 0;
+  size_t o_pass_code, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col;
   size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
       grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
       g_rowptr, g_col, c_rowptr, c_col, b_rowptr, b_col, dev_node, perm;
@@ -78,7 +79,7 @@ struct Inst {
   double vdd = 1.0, T = 0.0, h_max = 0.0;
   size_t g_val, c_val, b_val, c_ell_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
   // workspace offsets
-  size_t xk, x1, w, p, z, tmp, e, Ik, devI, devD, devI1, lu, V, Ve, H, He, mat, state, trace;
+  size_t xk, x1, w, p, z, tmp, e, Ik, devI, devD, devI1, lu, sval, rdv, V, Ve, H, He, mat, state, trace;
   int64_t ldv = 0;
   std::vector<double> trace_host;
   expri_run_info info{};
@@ -101,7 +102,7 @@ struct expri_ctx {
   void **d_ptrs = nullptr;  // 4 * n_inst device pointers
   int *d_order = nullptr;   // launch order of the transient kernel (largest first)
   int variant = 0;          // EXPRI_VARIANT: code-path selection for A/B measurements
-  int bs = 512, R = 8192;
+  int bs = 512, R = 8192, NX = 0;
   double wall_hz = 1e8;  // GPU wall-clock counter rate
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double run_kernel_s = 0.0;  // summed duration of the k_run launches of the last call
@@ -209,6 +210,8 @@ size_t layout_workspace(expri_ctx *c) {
     I.z = take(8 * n); I.tmp = take(8 * n); I.e = take(8 * n); I.Ik = take(8 * n);
     I.devI = take(8 * nd); I.devD = take(24 * nd); I.devI1 = take(8 * nd);
     I.lu = take(8 * (size_t)S.lu_rowptr[n]);
+    I.sval = take(8 * c->pats[I.pat].slot_pos.size());
+    I.rdv = take(8 * c->pats[I.pat].row_of.size());
     I.V = take(8 * (size_t)I.ldv * (mm + 1));
     I.Ve = take(8 * (size_t)I.ldv * (mm + 1));
     I.H = take(8 * (size_t)kHLd * kMaxKrylov);
@@ -254,10 +257,10 @@ void fill_descs(expri_ctx *c) {
     d.c_rowptr = ci(P.c_rowptr); d.c_col = ci(P.c_col);
     d.b_rowptr = ci(P.b_rowptr); d.b_col = ci(P.b_col);
     d.dev_node = ci(P.dev_node); d.perm = ci(P.perm);
-    d.lsched = reinterpret_cast<const SolveLevel *>(c->d_const + P.o_lsched);
-    d.usched = reinterpret_cast<const SolveLevel *>(c->d_const + P.o_usched);
-    d.n_lsched = (int32_t)P.lsched.size();
-    d.n_usched = (int32_t)P.usched.size();
+    d.pass_code = ci(P.o_pass_code);
+    d.n_lpass = P.n_lpass; d.n_upass = P.n_upass; d.pl = P.pl; d.pu = P.pu;
+    d.u_slot_base = P.u_slot_base; d.u_row_base = P.u_row_base;
+    d.n_slots = (int32_t)P.slot_pos.size(); d.n_srows = (int32_t)P.row_of.size();
     d.slot_pos = ci(P.o_slot_pos); d.slot_col = ci(P.o_slot_col); d.row_of = ci(P.o_row_of);
     d.c_ell_col = ci(P.o_c_ell_col); d.c_ell_k = P.c_ell_k;
     d.c_ell_val = cd(I.c_ell_val);
@@ -267,7 +270,8 @@ void fill_descs(expri_ctx *c) {
     d.src_v = cd(I.src_v); d.bp = cd(I.bp);
     d.xk = wd(I.xk); d.x1 = wd(I.x1); d.w = wd(I.w); d.p = wd(I.p); d.z = wd(I.z);
     d.tmp = wd(I.tmp); d.e = wd(I.e); d.devI = wd(I.devI); d.devD = wd(I.devD);
-    d.devI1 = wd(I.devI1); d.Ik = wd(I.Ik); d.lu = wd(I.lu); d.V = wd(I.V); d.Ve = wd(I.Ve);
+    d.devI1 = wd(I.devI1); d.Ik = wd(I.Ik); d.lu = wd(I.lu); d.sval = wd(I.sval); d.rdv = wd(I.rdv);
+    d.V = wd(I.V); d.Ve = wd(I.Ve);
     d.H = wd(I.H); d.He = wd(I.He); d.mat = wd(I.mat);
     d.ldv = I.ldv;
     d.state = reinterpret_cast<InstState *>(c->d_ws + I.state);
@@ -350,7 +354,7 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
     if (launches >= max_launches)
       return fail(c, EXPRI_ESTEPMIN, "step budget of " + std::to_string(kMaxRunSteps) + " accepted steps exhausted");
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_run(c->d_desc, c->d_order, n, ko, max_steps, replay, c->bs, c->R, c->stream));
+    HIPCHK(c, launch_run(c->d_desc, c->d_order, n, ko, max_steps, replay, c->bs, c->R, c->NX, c->stream));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     if ((s = read_states(c, st)) != EXPRI_OK) return s;
     float ms = 0.0f;
@@ -493,22 +497,41 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   int wall_khz = 0;
   if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
     c->wall_hz = 1e3 * wall_khz;
-  // 1024-thread blocks spill registers in the transient kernel; 512 covers the
-  // LDS-resident sizes this engine targets
-  c->bs = op.block_size ? op.block_size : (n_max <= 2048 ? 256 : 512);
+  // a thread keeps at most 9 rows of a vector in registers (n <= 9 bs)
+  c->bs = op.block_size ? op.block_size : (n_max <= 2048 ? 256 : n_max <= 9 * 512 ? 512 : 1024);
+  if (n_max > 9 * c->bs) {
+    *out = c.release();
+    (*out)->err = "block size " + std::to_string((*out)->bs) + " too small for n = " + std::to_string(n_max);
+    return EXPRI_EINVAL;
+  }
   const size_t limit = prop.sharedMemPerBlock;
   const size_t extras = lds_bytes(c->bs, 0);
-  size_t R = std::max<size_t>(n_max, 8192);
-  if (8 * R + extras > limit) R = std::max<size_t>(n_max, (limit - extras) / 8);
-  if (8 * R + extras > limit) {
+  // LDS: the vector area (solve vector / current Arnoldi basis vector, NX
+  // doubles) and behind it the small dense matrices of the Hessenberg
+  // exponential: five 32 x 33 matrices cover m <= 31 (larger m use global
+  // scratch)
+  const size_t NX = ((size_t)n_max + 63) / 64 * 64;
+  size_t RD = std::max<size_t>(5 * 32 * 33, NX < 8192 ? 8192 - NX : 0);
+  if (8 * (NX + RD) + extras > limit && 8 * NX + extras < limit) RD = (limit - extras) / 8 - NX;
+  if (8 * (NX + RD) + extras > limit || RD < 5 * 16 * 17) {
     *out = c.release();
     (*out)->err = "circuit too large for the one-workgroup engine (n = " + std::to_string(n_max) + ")";
     return EXPRI_EINVAL;
   }
+  const size_t R = NX + RD;
   // flattened solve schedules and the C ELL pattern for this block size
   for (auto &P : c->pats) {
     build_solve_schedule(P.sym, c->bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of);
+    P.u_slot_base = (int32_t)P.slot_pos.size();
+    P.u_row_base = (int32_t)P.row_of.size();
     build_solve_schedule(P.sym, c->bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of);
+    P.pass_code = pass_codes(P.lsched);
+    P.n_lpass = (int32_t)P.pass_code.size();
+    const std::vector<int32_t> up = pass_codes(P.usched);
+    P.n_upass = (int32_t)up.size();
+    P.pass_code.insert(P.pass_code.end(), up.begin(), up.end());
+    P.pl = P.lsched.empty() ? 1 : P.lsched[0].P;
+    P.pu = P.usched.empty() ? 1 : P.usched[0].P;
     P.c_ell_k = build_c_ell(P.sym, P.c_ell_col);
   }
   // ---- pack constant data ----
@@ -526,7 +549,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.c_rowptr = pk.add(S.c_rowptr); P.c_col = pk.add(S.c_col);
     P.b_rowptr = pk.add(S.b_rowptr); P.b_col = pk.add(S.b_col);
     P.dev_node = pk.add(S.dev_node); P.perm = pk.add(S.perm);
-    P.o_lsched = pk.add(P.lsched); P.o_usched = pk.add(P.usched);
+    P.o_pass_code = pk.add(P.pass_code);
     P.o_slot_pos = pk.add(P.slot_pos); P.o_slot_col = pk.add(P.slot_col); P.o_row_of = pk.add(P.row_of);
     P.o_c_ell_col = pk.add(P.c_ell_col);
   }
@@ -597,6 +620,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "setup upload"); }
 
   c->R = (int)R;
+  c->NX = (int)NX;
   e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "event create"); }
@@ -632,7 +656,7 @@ expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {
   if ((s = upload_descs(c)) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
   HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t0, c->opts.h_init, c->stream));
-  HIPCHK(c, launch_dc(c->d_desc, n, kernel_opts(c->opts), t0, 20000, c->bs, c->R, c->stream));
+  HIPCHK(c, launch_dc(c->d_desc, n, kernel_opts(c->opts), t0, 20000, c->bs, c->R, c->NX, c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   // write back only instances that converged (x keeps its input otherwise)
@@ -654,7 +678,7 @@ expri_status expri_factor(expri_ctx *c, const double *const *x) {
   if ((s = upload_descs(c)) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
   HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), 0.0, c->opts.h_init, c->stream));
-  HIPCHK(c, launch_factor(c->d_desc, n, kernel_opts(c->opts), c->bs, c->R, c->stream));
+  HIPCHK(c, launch_factor(c->d_desc, n, kernel_opts(c->opts), c->bs, c->R, c->NX, c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   return first_error(c, st, "factor");
@@ -668,7 +692,7 @@ expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y)
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(b))) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(y))) != EXPRI_OK) return s;
   HIPCHK(c, launch_solve(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs),
-                         reinterpret_cast<double *const *>(c->d_ptrs + n), c->bs, c->R, c->stream));
+                         reinterpret_cast<double *const *>(c->d_ptrs + n), c->bs, c->R, c->NX, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return EXPRI_OK;
 }
@@ -682,7 +706,7 @@ expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(v))) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(out))) != EXPRI_OK) return s;
   HIPCHK(c, launch_mevp(c->d_desc, n, kernel_opts(c->opts), reinterpret_cast<const double *const *>(c->d_ptrs),
-                        reinterpret_cast<double *const *>(c->d_ptrs + n), h, eps, c->bs, c->R, c->stream));
+                        reinterpret_cast<double *const *>(c->d_ptrs + n), h, eps, c->bs, c->R, c->NX, c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   for (int k = 0; k < n; ++k) {
@@ -798,13 +822,14 @@ expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
   return EXPRI_OK;
 }
 
-expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, double *seconds) {
-  if (!c || !seconds || what < 0 || what > 9 || reps < 1) return EXPRI_EINVAL;
+expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, int32_t arg, double *seconds) {
+  if (!c || !seconds || what < 0 || what > 6 || reps < 1) return EXPRI_EINVAL;
+  if (arg < 0 || arg > c->opts.m_max - 1 || (what == 6 && arg < 1)) return EXPRI_EINVAL;
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   long long *d = nullptr;
   HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&d), 2 * sizeof(long long)));
-  hipError_t e = launch_diag(c->d_desc, what, reps, d, c->bs, c->R, c->stream);
+  hipError_t e = launch_diag(c->d_desc, what, reps, arg, d, c->bs, c->R, c->NX, c->stream);
   long long h[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

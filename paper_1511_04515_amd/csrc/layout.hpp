@@ -51,13 +51,15 @@ struct InstState {
 };
 
 // One level of a flattened triangular-solve schedule: rows of the level are
-// handled by groups of G lanes (G a power of two), each lane multiplying up
-// to P stored entries; the level's rows need `passes` sweeps of the block.
+// handled by groups of G lanes (G a power of two), each lane multiplying P
+// stored entries (P is the same for every level of one direction); the
+// level's rows need `passes` sweeps of the block.
 struct SolveLevel {
   int32_t G, P, passes, pad;
   int32_t slot_base;  // into slot_pos / slot_col: index (q * P + j) * BS + t
-  int32_t row_base;   // into row_of: index q * (BS / G) + t / G
+  int32_t row_base;   // into row_of: index q * BS + t / G
 };
+constexpr int kPassSync = 1;  // pass code flag: last pass of its level
 
 struct InstDesc {
   int32_t n, n_dev, n_src, n_bp;
@@ -72,10 +74,15 @@ struct InstDesc {
   const int32_t *lu_gidx, *jac_ptr, *jac_code, *node_ptr, *node_code;
   const int32_t *g_rowptr, *g_col, *c_rowptr, *c_col, *b_rowptr, *b_col;
   const int32_t *dev_node;      // 3 per device
-  // flattened solve schedules (built for the launch block size)
-  const SolveLevel *lsched, *usched;
+  // flattened solve schedules (built for the launch block size): the L
+  // passes then the U passes, one code each ((log2 G << 8) | kPassSync); pass q of
+  // a direction reads slots base + (q * P + j) * BS + t and row slots
+  // base + q * BS + t / G
+  const int32_t *pass_code;
   const int32_t *slot_pos, *slot_col, *row_of;
-  int32_t n_lsched, n_usched;
+  int32_t n_lpass, n_upass, pl, pu;   // passes and slots per lane of L and U
+  int32_t u_slot_base, u_row_base;    // where the U passes start
+  int32_t n_slots, n_srows;           // sizes of slot_pos / row_of
   // C in ELL layout: entry k of row i at k * n + i (column -1 = padding)
   const int32_t *c_ell_col;
   int32_t c_ell_k, pad4;
@@ -95,6 +102,8 @@ struct InstDesc {
   double *devI, *devD, *devI1;  // per device: I(x_k), dI/d(d,g,s)(x_k), I(x_{k+1})
   double *Ik;                   // node currents at x_k
   double *lu;                   // L\U values
+  double *sval;                 // L\U values in solve-slot order (0 on padding)
+  double *rdv;                  // u_ii per row slot (1 where the slot has no row)
   double *V, *Ve;               // Krylov bases, n x (m_max + 1), column j at j * ldv
   double *H, *He;               // Hessenbergs, kHLd x kMaxKrylov column-major
   double *mat;                  // small dense matrices when they do not fit in LDS

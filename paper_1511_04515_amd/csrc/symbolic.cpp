@@ -496,31 +496,55 @@ bool analyse(const PatternInput &in, Symbolic &sym) {
   return true;
 }
 
-constexpr int kSlotMax = 8;  // entries per lane and level before more lanes share a row
+constexpr int kSlotMax = 8;  // entries per lane and pass (the kernel's register budget)
 
-// Flattened schedule of one triangular solve: for every level choose the
-// smallest power-of-two group of lanes per row that keeps each lane at
-// <= kSlotMax entries, and lay the entries out so that lane t of the block
-// reads slot (q * P + j) * bs + t (coalesced).
+// Flattened schedule of one triangular solve.  Every pass of one direction
+// gives each lane the same number P of slots (P in {1, 2, 4, 8}), so that the
+// kernel's loads per pass are a fixed set it can issue one pass ahead.  A
+// level's rows are handled by groups of G lanes (the smallest power of two
+// with ceil(K / G) <= P for the level's longest row K); lane t of pass q of
+// the direction reads slots (q * P + j) * bs + t, j < P (coalesced), and group
+// t / G owns row row_of[q * bs + t / G].  P is chosen per direction to
+// minimise passes * (1 + P / 8): a pass costs a dependent load round trip and
+// a barrier, its padding only bandwidth.
 void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
                           std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
                           std::vector<int32_t> &row_of) {
   const auto &ptr = lower ? S.lev_ptr : S.ulev_ptr;
   const auto &rows = lower ? S.lev_rows : S.ulev_rows;
   const int nlev = (int)ptr.size() - 1;
+  auto row_len = [&](int i) {
+    return lower ? S.lu_diag[i] - S.lu_rowptr[i] : S.lu_rowptr[i + 1] - S.lu_diag[i] - 1;
+  };
+  std::vector<int> Kl(nlev, 0);
+  for (int l = 0; l < nlev; ++l)
+    for (int q = ptr[l]; q < ptr[l + 1]; ++q) Kl[l] = std::max(Kl[l], row_len(rows[q]));
+  auto group = [](int K, int P) {
+    int G = 1;
+    while (G < 64 && (K + G - 1) / G > P) G *= 2;
+    return G;
+  };
+  int bestP = 1;
+  double best = 1e300;
+  for (int P = 1; P <= kSlotMax; P *= 2) {
+    bool fits = true;
+    long passes = 0;
+    for (int l = 0; l < nlev; ++l) {
+      if (lower && Kl[l] == 0) continue;
+      const int G = group(Kl[l], P);
+      if ((Kl[l] + G - 1) / G > P) fits = false;
+      const int nr = ptr[l + 1] - ptr[l];
+      passes += (nr + bs / G - 1) / (bs / G);
+    }
+    const double cost = fits ? passes * (1.0 + P / 8.0) : 1e300;
+    if (cost < best) { best = cost; bestP = P; }
+  }
+  const int P = bestP;
   sched.clear();
   for (int l = 0; l < nlev; ++l) {
     const int r0 = ptr[l], r1 = ptr[l + 1], nr = r1 - r0;
-    int K = 0;
-    for (int q = r0; q < r1; ++q) {
-      const int i = rows[q];
-      const int k = lower ? S.lu_diag[i] - S.lu_rowptr[i] : S.lu_rowptr[i + 1] - S.lu_diag[i] - 1;
-      K = std::max(K, k);
-    }
-    if (lower && K == 0) continue;  // unit diagonal: nothing to do on this level
-    int G = 1;
-    while (G < 64 && (K + G - 1) / G > kSlotMax) G *= 2;
-    const int P = std::max(1, (K + G - 1) / G);
+    if (lower && Kl[l] == 0) continue;  // unit diagonal: nothing to do on this level
+    const int G = group(Kl[l], P);
     const int per_pass = bs / G;
     const int passes = (nr + per_pass - 1) / per_pass;
     SolveLevel L{};
@@ -531,11 +555,11 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
     L.row_base = (int32_t)row_of.size();
     slot_pos.resize(slot_pos.size() + (size_t)passes * P * bs, -1);
     slot_col.resize(slot_col.size() + (size_t)passes * P * bs, 0);
-    row_of.resize(row_of.size() + (size_t)passes * per_pass, -1);
+    row_of.resize(row_of.size() + (size_t)passes * bs, -1);
     for (int idx = 0; idx < nr; ++idx) {
       const int i = rows[r0 + idx];
       const int q = idx / per_pass, g = idx % per_pass;
-      row_of[L.row_base + q * per_pass + g] = i;
+      row_of[L.row_base + q * bs + g] = i;
       const int b = lower ? S.lu_rowptr[i] : S.lu_diag[i] + 1;
       const int e = lower ? S.lu_diag[i] : S.lu_rowptr[i + 1];
       for (int k = 0; k < e - b; ++k) {
@@ -548,6 +572,17 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
     }
     sched.push_back(L);
   }
+}
+
+std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched) {
+  std::vector<int32_t> out;
+  for (const auto &L : sched)
+    for (int q = 0; q < L.passes; ++q) {
+      int lg = 0;
+      while ((1 << lg) < L.G) ++lg;
+      out.push_back((lg << 8) | (q == L.passes - 1 ? kPassSync : 0));
+    }
+  return out;
 }
 
 // ELL layout of C's pattern: entry k of row i at k * n + i; returns K.

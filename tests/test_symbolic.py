@@ -158,11 +158,13 @@ def test_node_current_gather_matches_oracle():
 
 def emulate_flat_solve(S, lu, b, bs):
     """The kernel's flattened level schedule: lane t of pass q reads slots
-    (q P + j) bs + t; groups of G lanes sum their partial products."""
+    (q P + j) bs + t; groups of G lanes sum their partial products; group g of
+    pass q owns row slot q bs + g.  P is one value per direction."""
     x = b.copy()
     n = b.size
     nnz = lu.size
     for lower, sched in ((True, S["lsched"].reshape(-1, 6)), (False, S["usched"].reshape(-1, 6))):
+        assert len(set(sched[:, 1].tolist())) <= 1 and set(sched[:, 1].tolist()) <= {1, 2, 4, 8}
         for G, P, passes, _, sb, rb in sched:
             assert G in (1, 2, 4, 8, 16, 32, 64) and P >= 1 and passes >= 1
             for q in range(passes):
@@ -173,7 +175,7 @@ def emulate_flat_solve(S, lu, b, bs):
                 assert pos.max() < nnz and col.min() >= 0 and col.max() < n
                 prod = np.where(pos >= 0, lu[np.maximum(pos, 0)] * x[col], 0.0)
                 acc = prod.sum(0).reshape(bs // G, G).sum(1)
-                ridx = rb + q * (bs // G) + np.arange(bs // G)
+                ridx = rb + q * bs + np.arange(bs // G)
                 assert ridx.max() < S["row_of"].size
                 rows = S["row_of"][ridx]
                 ok = rows >= 0
@@ -206,7 +208,7 @@ def test_flattened_solve_schedule_matches_row_solve(make, bs):
     def rows_of(sched):
         out = []
         for G, P, passes, _, sb, rb in sched:
-            r = S["row_of"][rb: rb + passes * (bs // G)]
+            r = S["row_of"][rb: rb + passes * bs]
             out.extend(r[r >= 0].tolist())
         return out
     ur = rows_of(us)
