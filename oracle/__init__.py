@@ -14,6 +14,8 @@ Modules
   sources -- piecewise-linear source values, slopes, breakpoints
   mevp    -- Algorithm 1 (MEVP_IKS) and the small Hessenberg exponential
   er      -- Algorithm 2 (ER step, error estimate, step control), DC point
+  mlp     -- the learned step controller's network: forward, gradient, Adam,
+             bfloat16 inference (not part of the paper; its plain definition)
 
 Every function is pinned by tests/test_oracle_*.py against closed forms,
 brute force or invariants fixed by the paper and the mathematics.
@@ -22,3 +24,4 @@ from .mosfet import mosfet_eval, device_currents
 from .sources import source_values, source_slopes, breakpoints
 from .mevp import InvertKrylov, hessenberg_phi
 from .er import Options, Oracle, Trace
+from . import mlp
