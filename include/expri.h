@@ -257,6 +257,52 @@ const char *expri_last_error(const expri_ctx *ctx);
 /* Release everything the context owns (not a bound workspace). */
 void expri_destroy(expri_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Learned step controller (not part of the paper; an addition to Algorithm
+ * 2's step control, whose error test stays the judge).  A multilayer
+ * perceptron 8 -> 64 -> 64 -> 2 with ReLU hidden layers maps eight features
+ * of the step to (m, log10 h).  Parameters are EXPRI_MLP_PARAMS floats in the
+ * order W1 (64 x 8, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64),
+ * b3 (2).  Inputs and targets are standardised with EXPRI_MLP_NORM floats:
+ * input mean (8), input std (8), target mean (2), target std (2).  The loss
+ * is half the mean squared error over a minibatch.
+ *
+ * Samples: X is n x 8 and T (targets) n x 2 float32, row-major, device
+ * pointers owned by the caller.  Work runs on the stream given at creation;
+ * calls that return host results synchronise it.
+ * ------------------------------------------------------------------------- */
+#define EXPRI_MLP_PARAMS 4866
+#define EXPRI_MLP_NORM 20
+
+typedef struct expri_mlp expri_mlp;
+
+/* Training state on the device: float32 parameters (copied from the host
+ * array params), zero Adam moments, unit standardisation.  EINVAL for NULL
+ * arguments, EHIP/ENOMEM when device memory cannot be had. */
+expri_status expri_mlp_create(expri_mlp **m, const float *params, void *hip_stream);
+/* Standardisation from the host (EXPRI_MLP_NORM floats; EINVAL unless every
+ * std is > 0), or fitted on the device to the population mean and standard
+ * deviation of n samples (a constant column gets std 1). */
+expri_status expri_mlp_set_norm(expri_mlp *m, const float *norm);
+expri_status expri_mlp_fit_norm(expri_mlp *m, const float *X, const float *T, int32_t n);
+/* Copy the parameters and/or the standardisation to host arrays (either may
+ * be NULL, not both). */
+expri_status expri_mlp_get(const expri_mlp *m, float *params, float *norm);
+/* Loss and gradient (float32 forward and backward passes on the device,
+ * workgroup partial sums added in a fixed order) over n >= 1 samples; loss
+ * and grad (EXPRI_MLP_PARAMS floats) are host outputs, either may be NULL. */
+expri_status expri_mlp_grad(expri_mlp *m, const float *X, const float *T, int32_t n, float *loss, float *grad);
+/* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected) with learning rate lr > 0 on the minibatch; the loss before the
+ * update goes to *loss when loss is not NULL. */
+expri_status expri_mlp_adam_step(expri_mlp *m, const float *X, const float *T, int32_t n, float lr, float *loss);
+/* Inference: Y (device, n x 2, de-standardised) = net(X) with float32
+ * weights (bf16 = 0) or with bfloat16 weights, inputs and hidden
+ * activations and float32 sums (bf16 = 1), one wavefront per sample. */
+expri_status expri_mlp_forward(expri_mlp *m, const float *X, float *Y, int32_t n, int32_t bf16);
+const char *expri_mlp_last_error(const expri_mlp *m);
+void expri_mlp_destroy(expri_mlp *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,19 @@ def adam(theta, g, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def standardize_stats(X, T):
+    """Mean and standard deviation (population) of every input feature and
+    target over the samples; a constant column gets standard deviation 1.
+    The network sees (x - mean) / std and predicts (t - mean) / std."""
+    out = []
+    for A in (np.asarray(X, np.float64), np.asarray(T, np.float64)):
+        mu = A.mean(0)
+        sd = np.sqrt(((A - mu) ** 2).mean(0))
+        sd[sd == 0.0] = 1.0
+        out += [mu, sd]
+    return tuple(out)  # (x_mean, x_std, t_mean, t_std)
+
+
 def to_bf16(a):
     """Round float32 values to bfloat16 (nearest, ties to even), returned as
     float32."""

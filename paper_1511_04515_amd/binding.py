@@ -28,10 +28,14 @@ ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_workspace_size", "ex
                 "expri_run_schedule", "expri_step", "expri_trace", "expri_get_run_info",
                 "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_block_size", "expri_diag_time", "expri_symbolic_create",
                 "expri_symbolic_array",
-                "expri_symbolic_destroy", "expri_last_error", "expri_destroy")
+                "expri_symbolic_destroy", "expri_last_error", "expri_destroy",
+                "expri_mlp_create", "expri_mlp_set_norm", "expri_mlp_fit_norm", "expri_mlp_get",
+                "expri_mlp_grad", "expri_mlp_adam_step", "expri_mlp_forward", "expri_mlp_last_error",
+                "expri_mlp_destroy")
 
 _p = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
+_f32p = C.POINTER(C.c_float)
 _f64p = C.POINTER(C.c_double)
 
 
@@ -117,6 +121,15 @@ def load_library(path: str = LIB_PATH):
         "expri_symbolic_destroy": ([_p], None),
         "expri_last_error": ([_p], C.c_char_p),
         "expri_destroy": ([_p], None),
+        "expri_mlp_create": ([C.POINTER(_p), _f32p, _p], C.c_int),
+        "expri_mlp_set_norm": ([_p, _f32p], C.c_int),
+        "expri_mlp_fit_norm": ([_p, _p, _p, C.c_int32], C.c_int),
+        "expri_mlp_get": ([_p, _f32p, _f32p], C.c_int),
+        "expri_mlp_grad": ([_p, _p, _p, C.c_int32, _f32p, _f32p], C.c_int),
+        "expri_mlp_adam_step": ([_p, _p, _p, C.c_int32, C.c_float, _f32p], C.c_int),
+        "expri_mlp_forward": ([_p, _p, _p, C.c_int32, C.c_int32], C.c_int),
+        "expri_mlp_last_error": ([_p], C.c_char_p),
+        "expri_mlp_destroy": ([_p], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -428,3 +441,93 @@ def symbolic_analysis(net, block_size: int | None = None) -> dict:
     finally:
         lib.expri_symbolic_destroy(h)
     return out
+
+
+MLP_PARAMS = 4866
+MLP_NORM = 20
+
+
+class Mlp:
+    """The learned step controller's network on the current GPU (training in
+    float32, inference in float32 or bfloat16).  X (n x 8) and T (n x 2) are
+    float32 CUDA tensors; params is a float array of MLP_PARAMS values."""
+
+    def __init__(self, params):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("expri needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.lib = load_library()
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters, got {p.size}")
+        self.stream = torch.cuda.current_stream()
+        self.h = C.c_void_p()
+        self._check(self.lib.expri_mlp_create(C.byref(self.h), _ptr(p, C.c_float),
+                                              C.c_void_p(self.stream.cuda_stream)))
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.expri_mlp_last_error(self.h).decode() if self.h else ""
+            raise ExpriError(st, msg)
+
+    def _samples(self, X, T=None):
+        for A, w in ((X, 8), (T, 2)):
+            if A is not None and (A.dtype != self.torch.float32 or A.dim() != 2 or A.shape[1] != w
+                                  or not A.is_cuda or not A.is_contiguous()):
+                raise ValueError(f"expected a contiguous float32 CUDA tensor of shape (n, {w})")
+        if T is not None and T.shape[0] != X.shape[0]:
+            raise ValueError("X and T differ in length")
+        return X.shape[0]
+
+    def set_norm(self, norm):
+        a = np.ascontiguousarray(norm, np.float32)
+        self._check(self.lib.expri_mlp_set_norm(self.h, _ptr(a, C.c_float)))
+
+    def fit_norm(self, X, T):
+        n = self._samples(X, T)
+        self._check(self.lib.expri_mlp_fit_norm(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n))
+
+    def params(self):
+        out = np.zeros(MLP_PARAMS, np.float32)
+        self._check(self.lib.expri_mlp_get(self.h, _ptr(out, C.c_float), None))
+        return out
+
+    def norm(self):
+        out = np.zeros(MLP_NORM, np.float32)
+        self._check(self.lib.expri_mlp_get(self.h, None, _ptr(out, C.c_float)))
+        return out
+
+    def grad(self, X, T):
+        n = self._samples(X, T)
+        loss = np.zeros(1, np.float32)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        self._check(self.lib.expri_mlp_grad(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+                                            _ptr(loss, C.c_float), _ptr(g, C.c_float)))
+        return float(loss[0]), g
+
+    def adam_step(self, X, T, lr: float = 1e-3, want_loss: bool = False):
+        n = self._samples(X, T)
+        loss = np.zeros(1, np.float32)
+        self._check(self.lib.expri_mlp_adam_step(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+                                                 C.c_float(lr), _ptr(loss, C.c_float) if want_loss else None))
+        return float(loss[0]) if want_loss else None
+
+    def forward(self, X, bf16: bool = True):
+        n = self._samples(X)
+        Y = self.torch.empty((n, 2), dtype=self.torch.float32, device=X.device)
+        self._check(self.lib.expri_mlp_forward(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), n,
+                                               1 if bf16 else 0))
+        return Y
+
+    def close(self):
+        if self.h:
+            self.torch.cuda.synchronize()
+            self.lib.expri_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,7 +24,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
-SOURCES = [("engine.hip", "hip"), ("expri_api.cpp", "hip"), ("symbolic.cpp", "cxx"),
+SOURCES = [("engine.hip", "hip"), ("controller.hip", "hip"), ("expri_api.cpp", "hip"), ("symbolic.cpp", "cxx"),
            ("symbolic_capi.cpp", "cxx")]
 
 
