@@ -5,15 +5,18 @@ Workload (default "batch"): 256 variants of a 200-stage CMOS inverter chain
 input delay U(0, 0.5 ns)) plus 64 chains of U{50..400} stages, 4 ns
 transients at E_rr = 1e-6 V, every instance stepped by the GPU library in
 one launch.  A bench step is one whole transient of the batch from its DC
-point (computed on the GPU, untimed) to T.  value = accepted ER steps summed
-over instances per second of wall time.
+point (computed on the GPU, untimed) to T, with the learned step controller
+(trained first, untimed, on traces of disjoint circuits).  value = accepted
+ER steps summed over instances per second of wall time.
 
-Also reported: the same library on the single 200-stage chain ("plain", one
-instance), the roofline figures of the transient kernel (algorithmic bytes
-per launch / its HIP-event duration), and the oracle's CPU throughput on a
-bounded sample.
+Also reported: the same batch under the paper's step control (time to
+solution of both), the library on the single 200-stage chain ("plain", one
+instance, the paper's control), the roofline figures of the transient kernel
+(algorithmic bytes per launch / its HIP-event duration), and the oracle's CPU
+throughput on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--workload batch|chain|mesh]
+                    [--controller learned|plain]
 """
 from __future__ import annotations
 
@@ -89,15 +92,57 @@ def cpu_baseline(budget_s=15.0):
                       f"from its DC point ({el:.1f} s), NumPy/SciPy FP64 on one thread"}
 
 
+def controller_training_set():
+    """Circuits for the learned controller's training traces, disjoint from
+    every benchmarked circuit (seeds 7000+): 16 variants of a 100-stage chain
+    and 8 chains of 50-200 stages."""
+    import numpy as np
+    import netgen
+    base = netgen.inverter_chain(seed=7000, n_stages=100).meta["values"]
+    nets = [netgen.inverter_chain(seed=7000, n_stages=100, base=base, variation=dict(seed=7100 + i))
+            for i in range(16)]
+    rng = np.random.default_rng(7200)
+    nets += [netgen.inverter_chain(seed=7300 + j, n_stages=int(L)) for j, L in enumerate(rng.integers(50, 201, 8))]
+    return nets
+
+
+def train_controller(log):
+    """Plain runs of the training set -> step traces -> GPU training."""
+    import numpy as np
+    import torch
+    import paper_1511_04515_amd as E
+    from paper_1511_04515_amd import control
+    nets = controller_training_set()
+    t0 = time.perf_counter()
+    s = E.Solver(nets, probes=[np.zeros(0, np.int32)] * len(nets), trace_cap=8192)
+    x = s.zeros()
+    s.dc(x)
+    s.run(x, max_steps_per_launch=8192)
+    X, T = control.samples_from_traces([s.trace(i) for i in range(len(nets))])
+    s.close()
+    t1 = time.perf_counter()
+    params, norm, losses = control.train(X, T, epochs=40, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"controller: {len(X)} samples from {len(nets)} training circuits ({t1 - t0:.1f} s), "
+        f"trained in {t2 - t1:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    return params, norm, {"train_samples": int(len(X)), "train_circuits": len(nets),
+                          "trace_seconds": t1 - t0, "train_seconds": t2 - t1,
+                          "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch")
+    ap.add_argument("--controller", default="learned", choices=("learned", "plain"))
+    ap.add_argument("--safety", type=float, default=1.0)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain-control run of the same batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is not sharded "
@@ -108,6 +153,9 @@ def main():
     import torch
     import paper_1511_04515_amd as E
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
     nets, desc = workload(args.workload)
     syms = {}
@@ -115,6 +163,10 @@ def main():
         key = (net.n, net.G.nnz, net.n_dev)
         if key not in syms:
             syms[key] = E.symbolic_analysis(net)
+    ctrl, ctrl_info = None, None
+    if args.controller == "learned":
+        params, norm, ctrl_info = train_controller(log)
+        ctrl = (params, norm)
     s = E.Solver(nets, probes=[np.zeros(0, np.int32)] * len(nets), trace_cap=8192,
                  block_size=args.block_size)
     x0 = s.zeros()
@@ -130,10 +182,11 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t, info, s.kernel_time()
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    log(f"{args.workload}: {len(nets)} instances, {sum(n.n for n in nets)} nodes, block size {s.bs}")
+    mode = "learned" if ctrl else "plain"
+    if ctrl:
+        s.load_controller(*ctrl, safety=args.safety)
+    log(f"{args.workload}: {len(nets)} instances, {sum(n.n for n in nets)} nodes, block size {s.bs}, "
+        f"{mode} step control")
     for w in range(args.warmup):
         el, _, _ = one_run()
         log(f"warmup {w}: {el:.2f} s")
@@ -175,11 +228,27 @@ def main():
                    "accepted_steps_per_run": int(sum(i["steps"] for i in info)),
                    "rejected_trials_per_run": int(sum(i["rejects"] for i in info)),
                    "arnoldi_iterations_per_run": int(sum(i["arnoldi"] for i in info)),
-                   "controller": "plain (paper's alpha/beta rule)",
+                   "controller": (f"learned: MLP 8-64-64-2, bfloat16 inference in the transient kernel, "
+                                  f"trained on the GPU (float32) from traces of disjoint circuits, "
+                                  f"safety {args.safety}") if ctrl else "plain (the paper's alpha/beta rule)",
                    "block_size": s.bs},
+        "time_to_solution_s": elapsed / args.steps,
         "roofline": roof,
         "phase_share": {k: v / max(sum(phases.values()), 1e-30) for k, v in phases.items()},
     }
+    if ctrl_info:
+        out["controller_training"] = ctrl_info
+    if ctrl_info and not args.no_compare:
+        # the same batch under the paper's step control, for the learned-vs-plain comparison
+        s.load_controller(None)
+        el, inf_p, _ = one_run()
+        steps_p = sum(i["steps"] for i in inf_p)
+        out["plain_control_batch"] = {"value": steps_p / el, "unit": "instance-steps/s", "seconds": el,
+                                      "accepted_steps": int(steps_p),
+                                      "rejected_trials": int(sum(i["rejects"] for i in inf_p)),
+                                      "arnoldi_iterations": int(sum(i["arnoldi"] for i in inf_p))}
+        out["learned_vs_plain_time_to_solution"] = el / (elapsed / args.steps)
+        log(f"plain step control on the same batch: {el:.2f} s, {steps_p} accepted ER steps")
     s.close()
     if args.workload == "batch" and not args.no_plain:
         nets1, _ = workload("chain")
@@ -192,8 +261,8 @@ def main():
         inf1 = s1.run(y, max_steps_per_launch=8192)
         torch.cuda.synchronize()
         el1 = time.perf_counter() - t
-        out["plain"] = {"workload": "one 200-stage chain, same library", "value": inf1[0]["steps"] / el1,
-                        "unit": "steps/s", "seconds": el1}
+        out["plain"] = {"workload": "one 200-stage chain, same library, the paper's step control",
+                        "value": inf1[0]["steps"] / el1, "unit": "steps/s", "seconds": el1}
         out["batched_vs_plain"] = value / out["plain"]["value"]
         s1.close()
     if not args.no_cpu_baseline:

@@ -129,9 +129,17 @@ typedef struct {
   int64_t comb_terms; /* Krylov basis columns combined into x_{k+1} and e_rr */
 } expri_run_info;
 
-/* Trace record layout (doubles): t, h, h_try, m, m_err, rejects, err_inf,
- * krylov_residual, then the n_probe probed voltages at t. */
-#define EXPRI_REC_FIXED 8
+/* Trace record layout (doubles): t, h, h_try (the first trial before
+ * clipping to a source corner or T), m, m_err, rejects, err_inf,
+ * krylov_residual, the eight step features (below), then the n_probe probed
+ * voltages at t.  The features of step k are computed before its step size
+ * is chosen: log10 ||r_k||_inf (A), m_{k-1} / 60, log10 h_{k-1} (the
+ * nominal size of step k-1: its h_try when it landed on a corner at the
+ * first try, else its h),
+ * log10 rho_{k-1}, log10(1 + max |du/dt| * 1 ns), log10 ||F_k(x_k)||_inf
+ * (F_k(x) = J_dev(x_k) x - I_dev(x), A), log10(err_{k-1} / E_rr) and the
+ * rejections of step k-1 (logarithms of values below 1e-30 are clamped). */
+#define EXPRI_REC_FIXED 16
 
 /* Fill o with the defaults listed above. */
 expri_status expri_default_opts(expri_opts *o);
@@ -302,6 +310,23 @@ expri_status expri_mlp_adam_step(expri_mlp *m, const float *X, const float *T, i
 expri_status expri_mlp_forward(expri_mlp *m, const float *X, float *Y, int32_t n, int32_t bf16);
 const char *expri_mlp_last_error(const expri_mlp *m);
 void expri_mlp_destroy(expri_mlp *m);
+
+/* Use a trained network (host arrays: EXPRI_MLP_PARAMS parameters and
+ * EXPRI_MLP_NORM standardisation floats) as the step controller of expri_run
+ * on ctx; params = NULL restores the paper's alpha/beta rule.  The
+ * parameters are rounded to bfloat16 and evaluated in the transient kernel
+ * (bfloat16 inference, float32 sums) on the step features.  For each step
+ * the network's h, times safety (0 < safety <= 1), bounded to
+ * [alpha, beta] x the previous step's nominal size and to h_max, is the
+ * first trial; it lands on the next source corner (or T) when that is within
+ * 1.25 h and takes half the gap when the gap is shorter than 2 h; the residual test of the first MEVP
+ * starts at the predicted m minus one.  The error estimate still accepts or
+ * rejects every trial, and rejections halve h as in Algorithm 2.  When a
+ * learned trial's MEVP does not converge within m_max, the step restarts
+ * once from the paper's own proposal (keeping the basis).  Replays
+ * (expri_run_schedule, expri_step) ignore the controller.  EINVAL for a
+ * non-finite parameter, a std <= 0 or safety outside (0, 1]. */
+expri_status expri_controller_load(expri_ctx *ctx, const float *params, const float *norm, double safety);
 
 #ifdef __cplusplus
 }

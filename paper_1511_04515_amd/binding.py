@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libexpri.so")
 
 GND, VDD = -1, -2
-REC_FIXED = 8
+REC_FIXED = 16
 REC_FIELDS = ("t", "h", "h_try", "m", "m_err", "rejects", "err", "rho")
+N_FEAT = 8  # step features after the fixed fields (see EXPRI_REC_FIXED in expri.h)
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -5: "ESTEPMIN",
           -6: "ENONFINITE", -7: "EHIP", -8: "EPATTERN", -9: "ENOCONV"}
@@ -31,7 +32,7 @@ ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_workspace_size", "ex
                 "expri_symbolic_destroy", "expri_last_error", "expri_destroy",
                 "expri_mlp_create", "expri_mlp_set_norm", "expri_mlp_fit_norm", "expri_mlp_get",
                 "expri_mlp_grad", "expri_mlp_adam_step", "expri_mlp_forward", "expri_mlp_last_error",
-                "expri_mlp_destroy")
+                "expri_mlp_destroy", "expri_controller_load")
 
 _p = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "expri_mlp_forward": ([_p, _p, _p, C.c_int32, C.c_int32], C.c_int),
         "expri_mlp_last_error": ([_p], C.c_char_p),
         "expri_mlp_destroy": ([_p], None),
+        "expri_controller_load": ([_p, _f32p, _f32p, C.c_double], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -350,6 +352,7 @@ class Solver:
         self._check(self.lib.expri_trace(self.ctx, inst, _ptr(buf, C.c_double), n.value, C.byref(n)))
         buf = buf[: n.value]
         out = {k: buf[:, i] for i, k in enumerate(REC_FIELDS)}
+        out["feat"] = buf[:, len(REC_FIELDS):len(REC_FIELDS) + N_FEAT]
         out["x"] = buf[:, REC_FIXED:]
         return out
 
@@ -389,6 +392,19 @@ class Solver:
         out = np.zeros(nnz)
         self._check(self.lib.expri_lu_values(self.ctx, inst, _ptr(out, C.c_double)))
         return out
+
+    def load_controller(self, params=None, norm=None, safety: float = 1.0):
+        """Use a trained network as the step controller of run() (None: the
+        paper's alpha/beta rule)."""
+        if params is None:
+            self._check(self.lib.expri_controller_load(self.ctx, None, None, 1.0))
+            return
+        p = np.ascontiguousarray(params, np.float32)
+        q = np.ascontiguousarray(norm, np.float32)
+        if p.size != MLP_PARAMS or q.size != MLP_NORM:
+            raise ValueError("expected MLP_PARAMS parameters and MLP_NORM standardisation values")
+        self._check(self.lib.expri_controller_load(self.ctx, _ptr(p, C.c_float), _ptr(q, C.c_float),
+                                                   C.c_double(safety)))
 
     def close(self):
         if self.ctx:

@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "layout.hpp"
+#include "mlp.hpp"
 
 namespace expri {
 
@@ -802,25 +803,27 @@ __device__ __forceinline__ void basis_start(const InstDesc &D, Lds<BS> &L, const
 template <int BS>
 __device__ __forceinline__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, double *V, double *H,
                              Basis &B, double h, double eps, double *dout, double &rho,
-                             int &iters, Prof &pf, Work &wk) {
+                             int &iters, Prof &pf, Work &wk, int m_first = 1) {
   if (B.beta == 0.0) {
     rho = 0.0;
     return kOK;
   }
   // one call site each for the residual test and the Arnoldi step (the code
-  // is inlined: a second copy would only cost instruction cache)
+  // is inlined: a second copy would only cost instruction cache).  The
+  // residual is tested from m_first on (every j when m_first = 1, as in
+  // Algorithm 1), and always once the basis is complete.
   for (int it = 0;; ++it) {
-    if (B.m > 0) {
+    if (B.m > 0 && (B.m >= m_first || B.exact)) {
       rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : gbl(H)[B.m + (B.m - 1) * kHLd], dout);
       pf.mark(4);
       if (rho <= eps) return kOK;
       if (B.exact) return kEKRYLOV;
-      if (it == 0) {
-        // a reused basis continues from v_m; the LDS vector area has been reused
-        const GMEM double *vm = gbl(V) + (int64_t)B.m * D.ldv;
-        for (int t = tid(); t < D.n; t += BS) L.region[t] = vm[t];
-        __syncthreads();
-      }
+    }
+    if (it == 0 && B.m > 0) {
+      // a reused basis continues from v_m; the LDS vector area has been reused
+      const GMEM double *vm = gbl(V) + (int64_t)B.m * D.ldv;
+      for (int t = tid(); t < D.n; t += BS) L.region[t] = vm[t];
+      __syncthreads();
     }
     if (B.m >= o.m_max) return kEKRYLOV;
     arnoldi_step<BS>(D, L, V, H, B, o.breakdown, pf);
@@ -872,6 +875,11 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
     S.mgs_terms = 0;
     S.comb_terms = 0;
     for (int i = 0; i < kPhases; ++i) S.ph[i] = 0.0;
+    S.h_prev = S.h_prop;
+    S.rho_prev = 0.0;
+    S.err_prev = 0.0;
+    S.m_prev = 0;
+    S.rej_prev = 0;
     int b = 0;
     while (b < D.n_bp - 1 && gbl(D.bp)[b] <= t0) ++b;
     S.bp_idx = b;
@@ -902,6 +910,9 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
   int bp_idx = S.bp_idx, steps = S.steps, status = kOK;
   int lu_count = S.lu_count, rej_total = S.rejects, iters = S.arnoldi;
   int lu_valid = S.lu_valid;
+  double h_prev = S.h_prev, rho_prev = S.rho_prev, err_prev = S.err_prev;
+  int m_prev = S.m_prev, rej_prev = S.rej_prev;
+  const bool learned = o.controller && !replay;
   const int steps0 = steps;
   const int rec = kRecFixed + D.n_probe;
   Prof pf;
@@ -918,13 +929,14 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     // ---- step size: clip to the next source corner / T ----
     double h_try, t_land;
     bool land;
+    double h_unc;  // the first trial before clipping to a source corner or T
     if (replay) {
       t_land = gbl(D.bp)[steps];
-      h_try = t_land - t;
+      h_try = h_unc = t_land - t;
       land = true;
     } else {
       t_land = gbl(D.bp)[bp_idx];
-      h_try = fmin(h_prop, D.h_max);
+      h_try = h_unc = fmin(h_prop, D.h_max);
       land = false;
       if (t + h_try * (1.0 + 1e-3) >= t_land) {
         h_try = t_land - t;
@@ -946,14 +958,81 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     // ---- the three right-hand sides, one solve each (one loop, one copy of
     // the solve code):  w = G^{-1} r with r = B u(t) - G_lin x_k - I_dev(x_k);
     // p = G^{-1} B s;  z = G^{-1} C p, leaving v = w - z in tmp ----
-    const double tm = t + 0.5 * h_try;
+    // step features (used by the learned controller, recorded in every mode)
+    double feat[kFeat];
+    double rmax = 0.0, fkmax = 0.0;
+    int m_first = 1;  // first Krylov size at which the residual is tested
 #pragma nounroll
     for (int rhs = 0; rhs < 3; ++rhs) {
+      if (rhs == 1) {
+        // source slopes inside the current PWL segment
+        const double ts = t + 0.5 * (learned ? gbl(D.bp)[bp_idx] - t : h_try);
+        double smax = 0.0;
+        for (int q = tid(); q < D.n_src; q += BS) smax = nmax(smax, fabs(pwl_slope(D, q, ts)));
+        const double r_inf = wg_max(L, rmax), f_inf = wg_max(L, fkmax), s_inf = wg_max(L, smax);
+        feat[0] = log10(fmax(r_inf, 1e-30));
+        feat[1] = m_prev / 60.0;
+        feat[2] = log10(h_prev);
+        feat[3] = log10(fmax(rho_prev, 1e-30));
+        feat[4] = log10(1.0 + s_inf * 1e-9);
+        feat[5] = log10(fmax(f_inf, 1e-30));
+        feat[6] = log10(fmax(err_prev / o.E_rr, 1e-30));
+        feat[7] = rej_prev;
+        if (learned) {
+          // the network proposes (m, log10 h); the step stays within a
+          // factor alpha..beta of the previous accepted one and the error
+          // test below still judges it (rejections halve as before)
+          if (tid() < 64) {
+            float ff[kFeat], out[2];
+#pragma unroll
+            for (int i = 0; i < kFeat; ++i) ff[i] = (float)feat[i];
+            mlp_infer_wave(o.ctrl_w, o.ctrl_norm, ff, out);
+            if (tid() == 0) {
+              L.hcol[0] = out[0];
+              L.hcol[1] = out[1];
+            }
+          }
+          __syncthreads();
+          const double m_hat = L.hcol[0], lh = L.hcol[1];
+          __syncthreads();
+          m_first = (int)fmin(fmax(rint(m_hat) - 1.0, 1.0), (double)o.m_max);
+          double hl = o.ctrl_safety * exp10(lh);
+          if (!(hl == hl)) hl = h_prev;
+          hl = fmin(fmax(hl, o.alpha * h_prev), o.beta * h_prev);
+          // corners: stretch by up to 25 % to land on one, and split a gap
+          // shorter than two steps into two equal halves, so that no tiny
+          // remainder step is left (the invert-Krylov basis needed at small
+          // h grows, up to the m_max limit)
+          t_land = gbl(D.bp)[bp_idx];
+          h_try = h_unc = fmin(hl, D.h_max);
+          land = false;
+          if (t + h_try * 1.25 >= t_land) {
+            h_try = t_land - t;
+            land = true;
+          } else if (t + 2.0 * h_try > t_land) {
+            h_try = 0.5 * (t_land - t);
+          }
+        }
+      }
+      const double tm = t + 0.5 * h_try;
       for (int i = tid(); i < n; i += BS) {
         double b = 0.0;
         if (rhs == 0) {
           for (int e = gbl(D.b_rowptr)[i]; e < gbl(D.b_rowptr)[i + 1]; ++e) b += gbl(D.b_val)[e] * pwl_value(D, gbl(D.b_col)[e], t);
           b = (b - csr_row_dot(D.g_rowptr, D.g_col, D.g_val, D.xk, i)) - gbl(D.Ik)[i];
+          rmax = nmax(rmax, fabs(b));
+          // F_k(x_k) = J_dev(x_k) x_k - I_dev(x_k) at node i
+          double lin = 0.0;
+          for (int c = gbl(D.node_ptr)[i]; c < gbl(D.node_ptr)[i + 1]; ++c) {
+            const int code = gbl(D.node_code)[c], k = code >> 1;
+            double dv = 0.0;
+            for (int v = 0; v < 3; ++v) {
+              const int nd = gbl(D.dev_node)[3 * k + v];
+              if (nd >= 0) dv += gbl(D.devD)[3 * k + v] * gbl(D.xk)[nd];
+            }
+            lin += (code & 1) ? -dv : dv;
+          }
+          fkmax = nmax(fkmax, fabs(lin - gbl(D.Ik)[i]));
         } else if (rhs == 1) {
           for (int e = gbl(D.b_rowptr)[i]; e < gbl(D.b_rowptr)[i + 1]; ++e) b += gbl(D.b_val)[e] * pwl_slope(D, gbl(D.b_col)[e], tm);
         } else {
@@ -973,9 +1052,29 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     // ---- trial loop ----
     double h = h_try, rho = 0.0, err = 0.0;
     int rej = 0, m_err = 0;
+    bool fell_back = false;
     for (;;) {
       ++wk.trials;
-      status = mevp_converge<BS>(D, L, o, D.V, D.H, Bm, h, o.eps_K, L.dmain, rho, iters, pf, wk);
+      status = mevp_converge<BS>(D, L, o, D.V, D.H, Bm, h, o.eps_K, L.dmain, rho, iters, pf, wk,
+                                 rej == 0 ? m_first : 1);
+      // a learned proposal whose MEVP does not converge within m_max (the
+      // invert-Krylov residual grows as h shrinks, so halving would not help)
+      // falls back to the paper's proposal for this step; the basis is kept
+      if (status == kEKRYLOV && learned && !fell_back) {
+        fell_back = true;
+        double hp = fmin(h_prop, D.h_max);
+        h_unc = hp;
+        t_land = gbl(D.bp)[bp_idx];
+        land = false;
+        if (t + hp * (1.0 + 1e-3) >= t_land) {
+          hp = t_land - t;
+          land = true;
+        }
+        h = h_try = hp;
+        rej = 0;
+        status = kOK;
+        continue;
+      }
       if (status != kOK) break;
       wk.comb += Bm.m;
       // x_{k+1} = x_k + h p + beta V_m d
@@ -1019,6 +1118,21 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
         pf.mark(5);
         double rho_e;
         status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk);
+        if (status == kEKRYLOV && learned && !fell_back) {
+          fell_back = true;
+          double hp = fmin(h_prop, D.h_max);
+          h_unc = hp;
+          t_land = gbl(D.bp)[bp_idx];
+          land = false;
+          if (t + hp * (1.0 + 1e-3) >= t_land) {
+            hp = t_land - t;
+            land = true;
+          }
+          h = h_try = hp;
+          rej = 0;
+          status = kOK;
+          continue;
+        }
         if (status != kOK) break;
         m_err = Be.m;
         wk.comb += Be.m;
@@ -1043,8 +1157,10 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     for (int i = tid(); i < n; i += BS) gbl(D.xk)[i] = gbl(D.x1)[i];
     GMEM double *r = gbl(D.trace) + (int64_t)(steps - steps0) * rec;
     if (tid() == 0) {
-      r[0] = t_new; r[1] = h; r[2] = h_try; r[3] = Bm.m;
+      r[0] = t_new; r[1] = h; r[2] = h_unc; r[3] = Bm.m;
       r[4] = m_err; r[5] = rej; r[6] = err; r[7] = rho;
+#pragma unroll
+      for (int i = 0; i < kFeat; ++i) r[8 + i] = feat[i];
     }
     for (int q = tid(); q < D.n_probe; q += BS) r[kRecFixed + q] = gbl(D.x1)[gbl(D.probe)[q]];
     __syncthreads();
@@ -1055,6 +1171,13 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
       while (bp_idx < D.n_bp - 1 && gbl(D.bp)[bp_idx] <= t) ++bp_idx;
     rej_total += rej;
     ++steps;
+    // the nominal size of this step: a first-try step clipped to a corner
+    // counts with its unclipped size (as the paper's h_prop does)
+    h_prev = (land && rej == 0) ? h_unc : h;
+    rho_prev = rho;
+    err_prev = err;
+    m_prev = Bm.m;
+    rej_prev = rej;
   }
   if (tid() == 0) {
     S.t = t;
@@ -1065,6 +1188,11 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     S.rejects = rej_total;
     S.arnoldi = iters;
     S.lu_valid = lu_valid;
+    S.h_prev = h_prev;
+    S.rho_prev = rho_prev;
+    S.err_prev = err_prev;
+    S.m_prev = m_prev;
+    S.rej_prev = rej_prev;
     S.trials += wk.trials;
     S.mgs_terms += wk.mgs;
     S.comb_terms += wk.comb;

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "layout.hpp"
+#include "mlp.hpp"
 #include "symbolic.hpp"
 
 namespace expri {
@@ -34,6 +35,7 @@ hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, d
                         int R, int NX, hipStream_t s);
 hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
                        double *const *out, double h, double eps, int bs, int R, int NX, hipStream_t s);
+hipError_t launch_mlp_pack(const float *p, void *out, bool bf16, hipStream_t s);
 hipError_t launch_diag(const InstDesc *d, int what, int reps, int arg, long long *out, int bs, int R, int NX,
                        hipStream_t s);
 }  // namespace expri
@@ -101,7 +103,11 @@ struct expri_ctx {
   std::vector<InstDesc> h_desc;
   void **d_ptrs = nullptr;  // 4 * n_inst device pointers
   int *d_order = nullptr;   // launch order of the transient kernel (largest first)
-  int variant = 0;          // EXPRI_VARIANT: code-path selection for A/B measurements
+  uint16_t *d_ctrl_w = nullptr;  // learned controller: bfloat16 parameters (inference layout)
+  float *d_ctrl_norm = nullptr;   // and its standardisation; null = the paper's step control
+  float *d_ctrl_tmp = nullptr;    // float32 staging for the conversion
+  double ctrl_safety = 1.0;
+  bool ctrl_on = false;
   int bs = 512, R = 8192, NX = 0;
   double wall_hz = 1e8;  // GPU wall-clock counter rate
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -242,7 +248,6 @@ void fill_descs(expri_ctx *c) {
     d.n_ulev = (int32_t)S.ulev_ptr.size() - 1;
     d.n_probe = I.n_probe;
     d.has_dev = I.n_dev > 0;
-    d.variant = c->variant;
     d.vdd = I.vdd;
     d.T = I.T;
     d.h_max = I.h_max;
@@ -341,7 +346,13 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
   expri_status s;
   if ((s = upload_descs(c)) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
-  const Opts ko = kernel_opts(c->opts);
+  Opts ko = kernel_opts(c->opts);
+  if (c->ctrl_on && !replay) {
+    ko.controller = 1;
+    ko.ctrl_w = c->d_ctrl_w;
+    ko.ctrl_norm = c->d_ctrl_norm;
+    ko.ctrl_safety = c->ctrl_safety;
+  }
   HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t0, c->opts.h_init,
                          c->stream));
   for (auto &I : c->inst) I.trace_host.clear();
@@ -426,7 +437,6 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   if (!c) return EXPRI_ENOMEM;
   if (!ckt || n_inst <= 0) return EXPRI_EINVAL;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  if (const char *v = std::getenv("EXPRI_VARIANT")) c->variant = std::atoi(v);
   if (o) c->opts = *o; else expri_default_opts(&c->opts);
   const expri_opts &op = c->opts;
   if (!(op.E_rr > 0) || !(op.eps_krylov > 0) || !(op.alpha > 0 && op.alpha < 1) || !(op.beta >= 1) ||
@@ -854,8 +864,38 @@ expri_status expri_kernel_time(const expri_ctx *c, double *seconds, int32_t *lau
 
 const char *expri_last_error(const expri_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+expri_status expri_controller_load(expri_ctx *c, const float *params, const float *norm, double safety) {
+  if (!c) return EXPRI_EINVAL;
+  if (!params) {
+    c->ctrl_on = false;
+    return EXPRI_OK;
+  }
+  if (!norm || !(safety > 0.0 && safety <= 1.0)) return fail(c, EXPRI_EINVAL, "controller: norm missing or safety not in (0, 1]");
+  for (int i = 0; i < kMlpIn; ++i)
+    if (!(norm[kMlpIn + i] > 0.0f)) return fail(c, EXPRI_EINVAL, "controller: input std must be > 0");
+  for (int o = 0; o < kMlpOut; ++o)
+    if (!(norm[2 * kMlpIn + kMlpOut + o] > 0.0f)) return fail(c, EXPRI_EINVAL, "controller: target std must be > 0");
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(params[i])) return fail(c, EXPRI_EINVAL, "controller: non-finite parameter");
+  if (!c->d_ctrl_w) {
+    HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&c->d_ctrl_w), sizeof(uint16_t) * kMlpParams));
+    HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&c->d_ctrl_norm), sizeof(float) * kMlpNorm));
+    HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&c->d_ctrl_tmp), sizeof(float) * kMlpParams));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_ctrl_tmp, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_ctrl_norm, norm, sizeof(float) * kMlpNorm, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_mlp_pack(c->d_ctrl_tmp, c->d_ctrl_w, true, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ctrl_on = true;
+  c->ctrl_safety = safety;
+  return EXPRI_OK;
+}
+
 void expri_destroy(expri_ctx *c) {
   if (!c) return;
+  if (c->d_ctrl_w) (void)hipFree(c->d_ctrl_w);
+  if (c->d_ctrl_norm) (void)hipFree(c->d_ctrl_norm);
+  if (c->d_ctrl_tmp) (void)hipFree(c->d_ctrl_tmp);
   if (c->d_ws && c->ws_owned) (void)hipFree(c->d_ws);
   if (c->d_const) (void)hipFree(c->d_const);
   if (c->d_desc) (void)hipFree(c->d_desc);

@@ -10,7 +10,8 @@ namespace expri {
 
 constexpr int kMaxKrylov = 60;        // hard upper bound on m
 constexpr int kHLd = kMaxKrylov + 1;  // leading dimension of stored Hessenbergs
-constexpr int kRecFixed = 8;          // fixed doubles per trace record
+constexpr int kRecFixed = 16;         // fixed doubles per trace record (8 + 8 step features)
+constexpr int kFeat = 8;              // step features seen by the learned controller
 constexpr int kPhases = 6;            // profiled phases of a step
 // status codes (mirror expri_status of the public header)
 constexpr int kOK = 0, kEINVAL = -1, kENOMEM = -2, kESINGULAR = -3, kEKRYLOV = -4,
@@ -26,8 +27,11 @@ struct Opts {
   double piv_tol;     // small-pivot threshold, relative to the row's max |G_k|
   int32_t grow_if_rejects_lt;
   int32_t m_max;
-  int32_t variant;    // code-path selection for A/B measurements (0 = default)
+  int32_t controller; // 1: the learned controller proposes h and the first residual test
   int32_t pad;
+  double ctrl_safety;         // factor on the predicted step
+  const uint16_t *ctrl_w;     // bfloat16 network parameters (inference layout)
+  const float *ctrl_norm;     // input / output standardisation
 };
 
 // Run state of one instance; lives in device memory between launches.
@@ -48,6 +52,9 @@ struct InstState {
   int64_t comb_terms; // basis columns combined into x_{k+1} and e_rr
   // wall-clock ticks per phase: factor, rhs, arnoldi solve, mgs, phi, trial
   double ph[kPhases];
+  // the previous accepted step, as seen by the step features
+  double h_prev, rho_prev, err_prev;
+  int32_t m_prev, rej_prev;
 };
 
 // One level of a flattened triangular-solve schedule: rows of the level are
@@ -64,7 +71,7 @@ constexpr int kPassSync = 1;  // pass code flag: last pass of its level
 struct InstDesc {
   int32_t n, n_dev, n_src, n_bp;
   int32_t nnz_lu, n_lev, n_ulev, n_probe;
-  int32_t has_dev, variant, pad1, pad2;
+  int32_t has_dev, pad0, pad1, pad2;
   double vdd, T, h_max;
 
   // symbolic (shared by instances of one pattern)
