@@ -28,6 +28,11 @@ Step control (Algorithm 2): accept when ||e_rr||_inf <= E_rr, otherwise
 h <- alpha h and retry with the same LU and Krylov basis; after an accepted
 step with i rejections grow by beta when i < 5.
 
+ER-C (the modified correction term, Algorithm 2 with O_pt_c): after the error
+estimate, x_{k+1} <- x_{k+1} - gamma h phi_2(hJ) C^{-1} dF, evaluated on the
+error MEVP's basis (hessenberg_phi2); the step is accepted on the estimate of
+the uncorrected x_{k+1}.
+
 Readings where the paper is silent (each listed in the design notes):
  * steps are clipped to source corners and to T; a clipped step that is
    accepted at its first try lands exactly on the corner;
@@ -73,6 +78,8 @@ class Options:
     m_max: int = 60
     mode: str = "combined"            # or "literal"
     breakdown: float = 1e-13
+    erc: bool = False                 # ER-C: subtract gamma h phi_2(hJ) C^{-1} dF
+    gamma: float = 0.1
     max_steps: int = 10_000_000
 
 
@@ -242,6 +249,10 @@ class Oracle:
                 err = float(np.max(np.abs(e))) if e.size else 0.0
                 m_err = ke.m
                 self.trace.arnoldi_iters += ke.iterations
+                if o.erc:
+                    # the ER-C correction (section on the modified correction
+                    # term): D = gamma h phi_2(hJ) C^{-1} dF on the error basis
+                    x1 = x1 - o.gamma * ke.combine(ke.phi2(h))
             if forced or err <= self.E_rr:
                 info = dict(m=max(k.m for _, k in kry), m_err=m_err, rejects=i, err=err, rho=rho,
                             h_try=h_try)

@@ -56,6 +56,26 @@ def hessenberg_phi(Hm: np.ndarray, h_next: float, beta: float, h: float):
     return d, rho
 
 
+def hessenberg_phi2(Hm: np.ndarray, h: float) -> np.ndarray:
+    """Small-matrix part of h phi_2(hJ) on the invert Krylov space: with
+    M = h H_m^{-1}, returns d2 = -M phi_2(M) e_1 (phi_2(z) = (e^z - 1 - z)/z^2),
+    read from the exponential of the augmented matrix
+    [[M, e_1, 0], [0, 0, 1], [0, 0, 0]], whose last column holds phi_2(M) e_1.
+    With y = G^{-1} b and its basis (beta, V_m, H_m),
+        h phi_2(hJ) C^{-1} b ~ beta V_m d2
+    (from J^{-1} = -G^{-1} C: h phi_2(hJ) C^{-1} b = y - (1/h)(e^{hJ} - I) A y
+    with A = -G^{-1} C, and A y ~ beta V_m H_m e_1)."""
+    m = Hm.shape[0]
+    with np.errstate(all="ignore"):
+        M = h * np.linalg.inv(Hm)
+        aug = np.zeros((m + 2, m + 2))
+        aug[:m, :m] = M
+        aug[0, m] = 1.0
+        aug[m, m + 1] = 1.0
+        E = scipy.linalg.expm(aug)
+        return -(M @ E[:m, m + 1])
+
+
 class InvertKrylov:
     """Arnoldi state for one start vector v (Algorithm 1).
 
@@ -118,6 +138,13 @@ class InvertKrylov:
                 return d, rho
             if self.exact:
                 raise KrylovError("invariant subspace with non-finite exponential")
+
+    def phi2(self, h: float) -> np.ndarray:
+        """d2 of hessenberg_phi2 on the current basis (beta V_m d2 ~ h phi_2(hJ) C^{-1} b)."""
+        m = self.m
+        if self.beta == 0.0 or m == 0:
+            return np.zeros(m)
+        return hessenberg_phi2(self.H[:m, :m], h)
 
     def combine(self, d: np.ndarray) -> np.ndarray:
         """beta V_m d"""

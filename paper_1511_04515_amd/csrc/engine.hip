@@ -366,7 +366,7 @@ struct PassRegs {
   double dv;
 };
 
-template <int BS, int P>
+template <int BS, int P, bool UPPER>
 __device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__restrict__ sv,
                                            const GMEM int *__restrict__ scol, const GMEM int *__restrict__ rowof,
                                            const GMEM double *__restrict__ rdv, int sbase, int rbase, int lg,
@@ -377,7 +377,7 @@ __device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__
     o.c[j] = scol[sbase + j * BS + t];
   }
   o.row = rowof[rbase + (t >> lg)];
-  o.dv = rdv[rbase + (t >> lg)];
+  o.dv = UPPER ? rdv[rbase + (t >> lg)] : 1.0;  // the pivot only divides in the U solve
 }
 
 template <int P, bool UPPER>
@@ -407,18 +407,18 @@ __device__ __forceinline__ void solve_dir(const InstDesc &D, double *xs, const G
   const int t = tid();
   PassRegs<P> A, B;
   int ca = code[0], cb;
-  pass_fetch<BS, P>(A, sv, scol, rowof, rdv, sbase, rbase, ca >> 8, t);
+  pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase, rbase, ca >> 8, t);
   for (int q = 0; q < np; q += 2) {
     // the pass after q (the last pass again past the end: in range, unused)
     const int q1 = q + 1 < np ? q + 1 : np - 1;
     cb = code[q1];
-    pass_fetch<BS, P>(B, sv, scol, rowof, rdv, sbase + q1 * P * BS, rbase + q1 * BS, cb >> 8, t);
+    pass_fetch<BS, P, UPPER>(B, sv, scol, rowof, rdv, sbase + q1 * P * BS, rbase + q1 * BS, cb >> 8, t);
     pass_apply<P, UPPER>(A, xs, ca >> 8, t);
     if (ca & kPassSync) __syncthreads();
     if (q + 1 >= np) break;
     const int q2 = q + 2 < np ? q + 2 : np - 1;
     ca = code[q2];
-    pass_fetch<BS, P>(A, sv, scol, rowof, rdv, sbase + q2 * P * BS, rbase + q2 * BS, ca >> 8, t);
+    pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase + q2 * P * BS, rbase + q2 * BS, ca >> 8, t);
     pass_apply<P, UPPER>(B, xs, cb >> 8, t);
     if (cb & kPassSync) __syncthreads();
   }

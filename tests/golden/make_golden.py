@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import netgen  # noqa: E402
-from oracle import Oracle  # noqa: E402
+from oracle import Oracle, Options  # noqa: E402
 
 WORKLOADS = {
     # RC mesh 32x32, 1,024 nodes, linear, pulse loads, 5 ns
@@ -32,17 +32,21 @@ WORKLOADS = {
     "chain": lambda: netgen.config(2),
     # a short chain that switches fully inside its window (edge-case coverage)
     "chain12": lambda: netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9, t_ramp=0.2e-9),
+    # the same chain with the ER-C correction (gamma = 0.1)
+    "chain12_erc": lambda: netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9, t_ramp=0.2e-9),
 }
+OPTIONS = {"chain12_erc": lambda: Options(erc=True, gamma=0.1)}
 
 
 def make(name: str):
     net = WORKLOADS[name]()
+    opts = OPTIONS.get(name, Options)()
     t0 = time.time()
-    o = Oracle(net)
+    o = Oracle(net, opts)
     x0 = o.dc()
     run = o.run(x0, keep=net.probes)
     t_run = time.time() - t0
-    rep = Oracle(net).replay(x0, run.t, keep="all")
+    rep = Oracle(net, OPTIONS.get(name, Options)()).replay(x0, run.t, keep="all")
     X = np.array(rep.x)
     out = dict(
         x0=x0, t=np.array(run.t), h=np.array(run.h), h_try=np.array(run.h_try),

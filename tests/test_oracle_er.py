@@ -145,3 +145,17 @@ def test_replay_of_own_grid_agrees_and_is_deterministic():
     assert np.max(np.abs(np.array(a.x) - np.array(b.x))) < 10 * 0.1 * net.tol
     c = Oracle(net).replay(x0, a.t)
     assert np.array_equal(np.array(b.x), np.array(c.x))
+
+
+def test_erc_with_zero_gamma_is_er_and_correction_is_small():
+    # ER-C subtracts gamma h phi_2(hJ) C^{-1} dF: gamma = 0 reproduces ER exactly,
+    # and on a switching chain the correction stays of the order of the error budget
+    net = netgen.inverter_chain(seed=77, n_stages=6, T=0.5e-9, t_ramp=0.2e-9)
+    x0 = Oracle(net).dc()
+    ts = Oracle(net).run(x0, keep=None).t
+    er = Oracle(net).replay(x0, ts, keep="all")
+    erc0 = Oracle(net, Options(erc=True, gamma=0.0)).replay(x0, ts, keep="all")
+    assert np.array_equal(np.array(er.x), np.array(erc0.x))
+    erc = Oracle(net, Options(erc=True, gamma=0.1)).replay(x0, ts, keep="all")
+    diff = np.max(np.abs(np.array(erc.x) - np.array(er.x)))
+    assert 0.0 < diff <= 20 * net.tol

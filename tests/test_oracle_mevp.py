@@ -3,6 +3,7 @@ Hessenberg exponential, against closed forms, dense linear algebra and the
 paper's own residual identity."""
 import numpy as np
 import pytest
+import scipy.linalg
 import scipy.sparse.linalg as spla
 
 import netgen
@@ -133,3 +134,45 @@ def test_zero_vector_is_trivial():
     k = InvertKrylov(A, np.zeros(net.n), 10)
     d, rho = k.converge(1e-12, 1e-9)
     assert rho == 0.0 and np.all(k.combine(d) == 0)
+
+
+def _phi2_scalar(z):
+    return (np.exp(z) - 1.0 - z) / z ** 2
+
+
+def test_phi2_scalar_closed_form():
+    # one node: J = -g/c, h phi_2(hJ) C^{-1} b = (h b / c) phi_2(-h g / c)
+    from oracle.mevp import InvertKrylov
+    g, c, b = 2.0e-3, 5e-15, 1.3e-4
+    A = lambda q: -(c * q) / g
+    for h in (1e-13, 2.5e-12, 1e-11):
+        k = InvertKrylov(A, np.array([b / g]), 4)
+        k.iterate()
+        got = k.combine(k.phi2(h))[0]
+        ref = h * b / c * _phi2_scalar(-h * g / c)
+        assert got == pytest.approx(ref, rel=1e-12)
+
+
+def test_phi2_matches_dense_exponential_on_a_complete_space():
+    # h phi_2(hJ) C^{-1} b from the dense augmented exponential, J = -C^{-1} G
+    from oracle.mevp import InvertKrylov
+    rng = np.random.default_rng(11)
+    n = 7
+    G = rng.uniform(-1, 1, (n, n)) * 1e-3 + np.eye(n) * 5e-3
+    Q = rng.standard_normal((n, n))
+    C = (Q @ Q.T + n * np.eye(n)) * 1e-15
+    b = rng.standard_normal(n) * 1e-4
+    J = -np.linalg.solve(C, G)
+    A = lambda q: -np.linalg.solve(G, C @ q)
+    for h in (1e-14, 1e-12, 3e-11):
+        aug = np.zeros((n + 2, n + 2))
+        aug[:n, :n] = h * J
+        aug[:n, n] = np.linalg.solve(C, b)
+        aug[n, n + 1] = 1.0
+        ref = h * scipy.linalg.expm(aug)[:n, n + 1]
+        k = InvertKrylov(A, np.linalg.solve(G, b), n)
+        for _ in range(n):
+            if not k.exact:
+                k.iterate()
+        got = k.combine(k.phi2(h))
+        assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
