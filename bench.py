@@ -307,6 +307,18 @@ def main():
                         "value": inf1[0]["steps"] / el1, "unit": "steps/s", "seconds": el1}
         out["batched_vs_plain"] = value / out["plain"]["value"]
         s1.close()
+        # the paper's ER-C variant on the same chain (correction gamma = 0.1)
+        s2 = E.Solver(nets1, probes=[np.zeros(0, np.int32)], trace_cap=8192, erc=1, gamma=0.1)
+        z = [y0[0].clone()]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        inf2 = s2.run(z, max_steps_per_launch=8192)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t
+        out["plain_erc"] = {"workload": "the same chain with the ER-C correction (gamma 0.1)",
+                            "value": inf2[0]["steps"] / el2, "unit": "steps/s", "seconds": el2,
+                            "accepted_steps": inf2[0]["steps"], "rejected_trials": inf2[0]["rejects"]}
+        s2.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

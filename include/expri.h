@@ -109,6 +109,12 @@ typedef struct {
 typedef struct {
   double E_rr, eps_krylov, alpha, beta, h_init, h_min, h_max, breakdown, piv_tol;
   int32_t grow_if_rejects_lt, m_max, block_size, trace_cap;
+  /* ER-C (the modified correction term, Algorithm 2 with O_pt_c): when erc is
+   * 1, every trial's x_{k+1} is corrected by -gamma h phi_2(hJ) C^{-1} dF,
+   * evaluated on the error estimate's Krylov basis; acceptance uses the
+   * estimate of the uncorrected x_{k+1}.  Default erc = 0, gamma = 0.1. */
+  int32_t erc, pad_erc;
+  double gamma;
 } expri_opts;
 
 /* Counters of the last transient or DC call of one instance. */

@@ -118,6 +118,7 @@ struct Lds {
   int *ipiv;   // 4 ints of pivot exchange
   double *bc;  // 1 double of broadcast from wave 0
   double *hcol; // kHLd doubles: current Hessenberg column
+  double *derr2;  // kHLd doubles: ER-C coefficients on the error basis
   long long *prof;  // kPhases phase counters
   int R;   // region + dense, doubles
   int RD;  // dense, doubles
@@ -582,7 +583,7 @@ __device__ __forceinline__ void hess_inverse(const GMEM double *H, int m, double
 
 template <int BS, int NP, bool IN_LDS, class PT>
 __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM double *H, int m, double h,
-                                              double beta, double h_next, double *dout) {
+                                              double beta, double h_next, double *dout, double *dout2) {
   constexpr int ld = NP + 1;
   PT P1 = base, P2 = base + NP * ld, P3 = base + 2 * NP * ld, Ta = base + 3 * NP * ld, Tb = base + 4 * NP * ld;
   // ---- M = h H^{-1} into P3 (P2 holds the triangular factor) ----
@@ -591,10 +592,14 @@ __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM do
   for (int i = tid(); i < m * m; i += BS)
     if (!isfinite(P3[(i / m) * ld + i % m])) mbad = 1.0;
   if (wg_max(L, mbad) != 0.0) return INFINITY;  // H_m singular: not converged
-  // ---- A = [[M, e_1], [0, 0]] padded to NP x NP, in P1 ----
+  // ---- A = [[M, e_1], [0, 0]] padded to NP x NP, in P1; with the phi_2
+  // column it is [[M, e_1, 0], [0, 0, 1], [0, 0, 0]] ----
+  const bool two = dout2 != nullptr;
   for (int i = tid(); i < NP * NP; i += BS) {
     const int r = i / NP, c = i % NP;
-    P1[r * ld + c] = (r < m && c < m) ? P3[r * ld + c] : (r == 0 && c == m ? 1.0 : 0.0);
+    double v = (r < m && c < m) ? P3[r * ld + c] : (r == 0 && c == m ? 1.0 : 0.0);
+    if (two && r == m && c == m + 1) v = 1.0;
+    P1[r * ld + c] = v;
   }
   __syncthreads();
   double cs = 0.0;
@@ -637,13 +642,19 @@ __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM do
     E = Y;
     Y = tmp;
   }
-  // ---- d = -M f and (M y)_{m-1};  M = 2^s A[:m, :m] exactly ----
+  // ---- d = -M f and (M y)_{m-1};  M = 2^s A[:m, :m] exactly; with the
+  // phi_2 column also d2 = -M phi_2(M) e_1 ----
   double bad = 0.0;
   for (int r = tid(); r < m; r += BS) {
-    double acc = 0.0;
-    for (int c = 0; c < m; ++c) acc += ldexp(P1[r * ld + c], s) * E[c * ld + m];
+    double acc = 0.0, acc2 = 0.0;
+    for (int c = 0; c < m; ++c) {
+      const double mrc = ldexp(P1[r * ld + c], s);
+      acc += mrc * E[c * ld + m];
+      if (two) acc2 += mrc * E[c * ld + m + 1];
+    }
     dout[r] = -acc;
-    if (!isfinite(acc)) bad = 1.0;
+    if (two) dout2[r] = -acc2;
+    if (!isfinite(acc) || !isfinite(acc2)) bad = 1.0;
   }
   double part = 0.0;
   for (int c = tid(); c < m; c += BS) part += ldexp(P1[(m - 1) * ld + c], s) * E[c * ld];
@@ -654,16 +665,17 @@ __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM do
   return rho;
 }
 
-// d -> dout (LDS, m doubles); returns rho (inf if anything is not finite)
+// d -> dout (LDS, m doubles), and -M phi_2(M) e_1 -> dout2 when it is not
+// null; returns rho (inf if anything is not finite)
 template <int BS>
 __device__ __forceinline__ double hess_phi(const InstDesc &D, Lds<BS> &L, const double *H, int m, double h,
-                                           double beta, double h_next, double *dout) {
-  const int n1 = m + 1;
+                                           double beta, double h_next, double *dout, double *dout2 = nullptr) {
+  const int n1 = m + (dout2 ? 2 : 1);
   if (n1 <= 16 && 5 * 16 * 17 <= L.RD)
-    return hess_phi_np<BS, 16, true>(L, L.dense, gbl(H), m, h, beta, h_next, dout);
+    return hess_phi_np<BS, 16, true>(L, L.dense, gbl(H), m, h, beta, h_next, dout, dout2);
   if (n1 <= 32 && 5 * 32 * 33 <= L.RD)
-    return hess_phi_np<BS, 32, true>(L, L.dense, gbl(H), m, h, beta, h_next, dout);
-  return hess_phi_np<BS, 64, false>(L, gbl(D.mat), gbl(H), m, h, beta, h_next, dout);
+    return hess_phi_np<BS, 32, true>(L, L.dense, gbl(H), m, h, beta, h_next, dout, dout2);
+  return hess_phi_np<BS, 64, false>(L, gbl(D.mat), gbl(H), m, h, beta, h_next, dout, dout2);
 }
 
 // ---------------------------------------------------------------------------
@@ -803,7 +815,7 @@ __device__ __forceinline__ void basis_start(const InstDesc &D, Lds<BS> &L, const
 template <int BS>
 __device__ __forceinline__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, double *V, double *H,
                              Basis &B, double h, double eps, double *dout, double &rho,
-                             int &iters, Prof &pf, Work &wk, int m_first = 1) {
+                             int &iters, Prof &pf, Work &wk, int m_first = 1, double *dout2 = nullptr) {
   if (B.beta == 0.0) {
     rho = 0.0;
     return kOK;
@@ -814,7 +826,7 @@ __device__ __forceinline__ int mevp_converge(const InstDesc &D, Lds<BS> &L, cons
   // Algorithm 1), and always once the basis is complete.
   for (int it = 0;; ++it) {
     if (B.m > 0 && (B.m >= m_first || B.exact)) {
-      rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : gbl(H)[B.m + (B.m - 1) * kHLd], dout);
+      rho = hess_phi<BS>(D, L, H, B.m, h, B.beta, B.exact ? 0.0 : gbl(H)[B.m + (B.m - 1) * kHLd], dout, dout2);
       pf.mark(4);
       if (rho <= eps) return kOK;
       if (B.exact) return kEKRYLOV;
@@ -849,6 +861,7 @@ __device__ Lds<BS> lds_setup(int R, int NX) {
   L.bc = L.derr + kHLd + 2;
   L.prof = reinterpret_cast<long long *>(L.derr + kHLd + 4);
   L.hcol = L.derr + kHLd + 4 + kPhases;
+  L.derr2 = L.hcol + kHLd;
   L.R = R;
   L.RD = R - NX;
   L.par = 0;
@@ -1117,7 +1130,8 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
         basis_start<BS>(D, L, xs, D.Ve, Be);
         pf.mark(5);
         double rho_e;
-        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk);
+        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk, 1,
+                                   o.erc ? L.derr2 : nullptr);
         if (status == kEKRYLOV && learned && !fell_back) {
           fell_back = true;
           double hp = fmin(h_prop, D.h_max);
@@ -1138,11 +1152,19 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
         wk.comb += Be.m;
         double emax = 0.0;
         const GMEM double *Veg = gbl(D.Ve);
+        GMEM double *x1g = gbl(D.x1);
         for (int i = tid(); i < n; i += BS) {
-          double acc = 0.0;
-          for (int j = 0; j < Be.m; ++j) acc += Veg[(int64_t)j * D.ldv + i] * L.derr[j];
+          double acc = 0.0, acc2 = 0.0;
+          for (int j = 0; j < Be.m; ++j) {
+            const double vji = Veg[(int64_t)j * D.ldv + i];
+            acc += vji * L.derr[j];
+            if (o.erc) acc2 += vji * L.derr2[j];
+          }
           emax = nmax(emax, fabs(Be.beta * acc));
+          // ER-C: x_{k+1} -= gamma h phi_2(hJ) C^{-1} dF = gamma beta_e V_e d2
+          if (o.erc) x1g[i] -= o.gamma * (Be.beta * acc2);
         }
+        if (o.erc) wk.comb += Be.m;
         err = wg_max(L, emax);
       }
       pf.mark(5);
@@ -1331,9 +1353,9 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
   }
 
 size_t lds_bytes(int bs, int R) {
-  // region, reduction slots, dmain, derr, then 4 doubles (pivot ints,
-  // broadcast) and kPhases profile counters
-  return sizeof(double) * ((size_t)R + 2 * (bs / 64) + 3 * kHLd + 4 + kPhases);
+  // region, reduction slots, dmain, derr, 4 doubles (pivot ints,
+  // broadcast), kPhases profile counters, hcol, derr2
+  return sizeof(double) * ((size_t)R + 2 * (bs / 64) + 4 * kHLd + 4 + kPhases);
 }
 
 hipError_t set_lds_limits(size_t bytes) {

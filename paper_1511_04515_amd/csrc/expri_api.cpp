@@ -146,6 +146,8 @@ Opts kernel_opts(const expri_opts &o) {
   k.piv_tol = o.piv_tol;
   k.grow_if_rejects_lt = o.grow_if_rejects_lt;
   k.m_max = o.m_max;
+  k.erc = o.erc;
+  k.gamma = o.gamma;
   return k;
 }
 
@@ -426,6 +428,9 @@ expri_status expri_default_opts(expri_opts *o) {
   o->m_max = 60;
   o->block_size = 0;
   o->trace_cap = 4096;
+  o->erc = 0;
+  o->pad_erc = 0;
+  o->gamma = 0.1;
   return EXPRI_OK;
 }
 
@@ -442,6 +447,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   if (!(op.E_rr > 0) || !(op.eps_krylov > 0) || !(op.alpha > 0 && op.alpha < 1) || !(op.beta >= 1) ||
       !(op.h_init > 0) || !(op.h_min > 0) || !(op.h_max >= 0) || !(op.breakdown >= 0) ||
       !(op.piv_tol >= 0) || op.m_max < 1 || op.m_max > kMaxKrylov || op.trace_cap < 1 ||
+      (op.erc != 0 && op.erc != 1) || !std::isfinite(op.gamma) ||
       (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
     *out = c.release();
     (*out)->err = "invalid options";

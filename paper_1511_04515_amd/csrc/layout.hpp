@@ -28,7 +28,8 @@ struct Opts {
   int32_t grow_if_rejects_lt;
   int32_t m_max;
   int32_t controller; // 1: the learned controller proposes h and the first residual test
-  int32_t pad;
+  int32_t erc;        // 1: ER-C correction of x_{k+1}
+  double gamma;       // ER-C factor
   double ctrl_safety;         // factor on the predicted step
   const uint16_t *ctrl_w;     // bfloat16 network parameters (inference layout)
   const float *ctrl_norm;     // input / output standardisation

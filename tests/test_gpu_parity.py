@@ -111,12 +111,13 @@ def _golden(name):
     return np.load(path, allow_pickle=False)
 
 
-@pytest.mark.parametrize("name,cfg", [("mesh", 1), ("chain", 2), ("chain12", None)])
-def test_replay_parity_full_run(name, cfg):
+@pytest.mark.parametrize("name,cfg,kw", [("mesh", 1, {}), ("chain", 2, {}), ("chain12", None, {}),
+                                         ("chain12_erc", None, dict(erc=1, gamma=0.1))])
+def test_replay_parity_full_run(name, cfg, kw):
     g = _golden(name)
     net = netgen.config(cfg) if cfg else netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9,
                                                                t_ramp=0.2e-9)
-    s = Solver(net, trace_cap=4096)
+    s = Solver(net, trace_cap=4096, **kw)
     xs = s.to_device([g["x0"]])
     info = s.run_schedule(xs, [g["t"]])
     assert info[0]["status"] == 0 and info[0]["steps"] == len(g["t"])
