@@ -113,7 +113,10 @@ typedef struct {
    * 1, every trial's x_{k+1} is corrected by -gamma h phi_2(hJ) C^{-1} dF,
    * evaluated on the error estimate's Krylov basis; acceptance uses the
    * estimate of the uncorrected x_{k+1}.  Default erc = 0, gamma = 0.1. */
-  int32_t erc, pad_erc;
+  int32_t erc;
+  /* slots per lane of the flattened triangular-solve passes (1, 2, 4 or 8;
+   * 0 = chosen per direction from the pass count and the padding) */
+  int32_t solve_slots;
   double gamma;
 } expri_opts;
 
@@ -222,7 +225,8 @@ expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *l
  * what = 0 full G_k solve, 1 L solve, 2 U solve, 3 one Arnoldi step
  * j = arg (C SpMV, solve, Gram-Schmidt against arg + 1 vectors), 4 workgroup
  * reduction, 5 one barrier per solve pass and nothing else, 6 the Hessenberg
- * exponential and residual for m = arg on a synthetic H.  It overwrites
+ * exponential and residual for m = arg on a synthetic H, 7 assembly and
+ * refactor of G_k (with the slot repacking) at the last stamp.  It overwrites
  * instance 0's basis, Hessenbergs and solve vector with synthetic data.
  * EXPRI_EINVAL unless 0 <= arg < m_max (and arg >= 1 for what = 6). */
 expri_status expri_diag_time(expri_ctx *ctx, int32_t what, int32_t reps, int32_t arg, double *seconds);

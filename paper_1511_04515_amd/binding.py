@@ -66,7 +66,7 @@ class Opts(C.Structure):
                 ("h_max", C.c_double), ("breakdown", C.c_double), ("piv_tol", C.c_double),
                 ("grow_if_rejects_lt", C.c_int32), ("m_max", C.c_int32),
                 ("block_size", C.c_int32), ("trace_cap", C.c_int32),
-                ("erc", C.c_int32), ("pad_erc", C.c_int32), ("gamma", C.c_double)]
+                ("erc", C.c_int32), ("solve_slots", C.c_int32), ("gamma", C.c_double)]
 
 
 class RunInfo(C.Structure):

@@ -48,6 +48,9 @@ __device__ __forceinline__ int tid() {
   return t;
 }
 
+// orders a wave's own LDS traffic (its LDS operations complete in order)
+__device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 // Wave-wide reductions on the DPP network: a butterfly inside each 16-lane
 // row (pairs of lanes 1 and 2 apart, then the 8- and 16-lane mirrors), then
 // the four row results read out in a fixed order.  Every lane ends with the
@@ -272,19 +275,35 @@ __device__ __forceinline__ void stamp_devices(const InstDesc &D, const double *x
 }
 
 // lu <- G_lin + J_dev (drop the derivative couplings between DC blocks when
-// dc_block is set) ;  Ik <- I_dev(x) per node
+// dc_block is set) ;  Ik <- I_dev(x) per node.  G_lin comes pre-scattered to
+// the L\U positions (a coalesced copy); the few positions with device terms
+// are then rewritten with their sums.
 template <int BS>
 __device__ __forceinline__ void assemble(const InstDesc &D, bool dc_block) {
-  for (int p = tid(); p < D.nnz_lu; p += BS) {
-    const int gi = gbl(D.lu_gidx)[p];
-    double v = gi >= 0 ? gbl(D.g_val)[gi] : 0.0;
-    for (int c = gbl(D.jac_ptr)[p]; c < gbl(D.jac_ptr)[p + 1]; ++c) {
-      const int code = gbl(D.jac_code)[c];
+  const GMEM double *__restrict__ glu = gbl(D.g_lu);
+  GMEM double *__restrict__ lu = gbl(D.lu);
+  const int nz = D.nnz_lu;
+  for (int p0 = tid(); p0 < nz; p0 += 8 * BS) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p0 + u * BS < nz ? glu[p0 + u * BS] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (p0 + u * BS < nz) lu[p0 + u * BS] = v[u];
+  }
+  __syncthreads();
+  const GMEM int *__restrict__ jpos = gbl(D.jpos), *__restrict__ jptr = gbl(D.jac_ptr), *__restrict__ jcode = gbl(D.jac_code);
+  const GMEM double *__restrict__ devD = gbl(D.devD);
+  for (int q = tid(); q < D.n_jpos; q += BS) {
+    const int p = jpos[q];
+    double v = glu[p];
+    for (int c = jptr[p]; c < jptr[p + 1]; ++c) {
+      const int code = jcode[c];
       if (dc_block && ((code >> 3) & 1)) continue;
-      const double dv = gbl(D.devD)[3 * (code >> 4) + (code & 3)];
+      const double dv = devD[3 * (code >> 4) + (code & 3)];
       v += ((code >> 2) & 1) ? -dv : dv;
     }
-    gbl(D.lu)[p] = v;
+    lu[p] = v;
   }
   for (int i = tid(); i < D.n; i += BS) {
     double s = 0.0;
@@ -299,35 +318,101 @@ __device__ __forceinline__ void assemble(const InstDesc &D, bool dc_block) {
 
 // Slot-ordered copy of the factors for the solves: sval[k] is the L\U value
 // of slot k of the flattened schedules (0 on padding) and rdv[r] the pivot
-// u_ii of the row in row slot r (1 where the slot holds no row).  A solve pass
-// then reads its operands with coalesced loads that depend on nothing the
-// solve computes, so they can be issued a pass ahead.
+// u_ii of the row in row slot r of the U passes (1 where the slot holds no
+// row).  A solve pass then reads its operands with coalesced loads that
+// depend on nothing the solve computes, so they can be issued a pass ahead.
 template <int BS>
 __device__ __forceinline__ void pack_slots(const InstDesc &D) {
   const GMEM double *__restrict__ a = gbl(D.lu);
   const GMEM int *__restrict__ spos = gbl(D.slot_pos);
   GMEM double *__restrict__ sv = gbl(D.sval);
-  const GMEM int *__restrict__ rowof = gbl(D.row_of);
-  const GMEM int *__restrict__ diag = gbl(D.lu_diag);
+  const GMEM int *__restrict__ dpos = gbl(D.rdv_pos);
   GMEM double *__restrict__ rdv = gbl(D.rdv);
   const int ns = D.n_slots;
-  for (int k0 = tid(); k0 < ns; k0 += 4 * BS) {
-    int p[4];
+  for (int k0 = tid(); k0 < ns; k0 += 8 * BS) {
+    int p[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) p[u] = k0 + u * BS < ns ? spos[k0 + u * BS] : -1;
+    for (int u = 0; u < 8; ++u) p[u] = k0 + u * BS < ns ? spos[k0 + u * BS] : -1;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (k0 + u * BS < ns) sv[k0 + u * BS] = p[u] >= 0 ? a[p[u]] : 0.0;
   }
-  for (int r = tid(); r < D.n_srows; r += BS) {
-    const int i = rowof[r];
-    rdv[r] = i >= 0 ? a[diag[i]] : 1.0;
+  const int r1 = D.n_srows;
+  for (int r0 = D.u_row_base + tid(); r0 < r1; r0 += 8 * BS) {
+    int p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u] = r0 + u * BS < r1 ? dpos[r0 + u * BS] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r0 + u * BS < r1) rdv[r0 + u * BS] = p[u] >= 0 ? a[p[u]] : 1.0;
   }
   __syncthreads();
 }
 
 // numeric refactor of the L\U storage (row-wise Doolittle, static pivots).
 // Returns false when a pivot is small: |u_ii| <= piv_tol * max_j |G_k(i, j)|.
+// Row i of a level takes its pivot groups in order: l_ik = a_ik / u_kk, then
+// a_ij -= l_ik u_kj over the group's update pairs.  Wide levels run one row
+// per thread.  Narrow levels (the separators at the top of the ordering,
+// where the rows are long and the group chains deep) run one row per wave:
+// the row is staged in LDS, the pivots u_kk and the u_kj of up to 64 pairs
+// are loaded by the lanes at once (rows k are final), and only the chain
+// over the groups is sequential, in LDS.  The update order of every entry is
+// the same in both forms.
+template <int BS>
+__device__ __forceinline__ void refactor_row_wave(GMEM double *a, const GMEM int *rowptr, const GMEM int *row_grp,
+                                                  const GMEM int *grp_pos, const GMEM int *grp_diag,
+                                                  const GMEM int *grp_ptr, const GMEM int *pair_dst,
+                                                  const GMEM int *pair_src, int i, int diag_i, double *rb,
+                                                  double piv_tol, int lane, int &bad) {
+  const int rs = rowptr[i], len = rowptr[i + 1] - rs;
+  double rmx = 0.0;
+  for (int q = lane; q < len; q += 64) {
+    const double v = a[rs + q];
+    rb[q] = v;
+    rmx = fmax(rmx, fabs(v));
+  }
+  rmx = wave_max(rmx);
+  const int g0 = row_grp[i], ng = row_grp[i + 1] - g0;
+  const int p0 = grp_ptr[g0], np = grp_ptr[g0 + ng] - p0;
+  wfence();
+  if (ng <= 64 && np <= 64) {
+    int goff = 0, glo = 0, ghi = 0, pd = 0;
+    double gdg = 1.0, ps = 0.0;
+    if (lane < ng) {
+      goff = grp_pos[g0 + lane] - rs;
+      gdg = a[grp_diag[g0 + lane]];
+      glo = grp_ptr[g0 + lane] - p0;
+      ghi = grp_ptr[g0 + lane + 1] - p0;
+    }
+    if (lane < np) {
+      pd = pair_dst[p0 + lane] - rs;
+      ps = a[pair_src[p0 + lane]];
+    }
+    for (int g = 0; g < ng; ++g) {
+      const int off = __builtin_amdgcn_readlane(goff, g);
+      const int lo = __builtin_amdgcn_readlane(glo, g), hi = __builtin_amdgcn_readlane(ghi, g);
+      const double l = rb[off] / readlane_d(gdg, g);
+      wfence();
+      if (lane == 0) rb[off] = l;
+      if (lane >= lo && lane < hi) rb[pd] -= l * ps;
+      wfence();
+    }
+  } else {
+    for (int g = 0; g < ng; ++g) {
+      const int off = grp_pos[g0 + g] - rs;
+      const double l = rb[off] / a[grp_diag[g0 + g]];
+      wfence();
+      if (lane == 0) rb[off] = l;
+      for (int u = grp_ptr[g0 + g] + lane; u < grp_ptr[g0 + g + 1]; u += 64)
+        rb[pair_dst[u] - rs] -= l * a[pair_src[u]];
+      wfence();
+    }
+  }
+  for (int q = lane; q < len; q += 64) a[rs + q] = rb[q];
+  if (lane == 0 && !(fabs(rb[diag_i - rs]) > piv_tol * rmx)) bad = 1;
+}
+
 template <int BS>
 __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
   GMEM double *a = gbl(D.lu);
@@ -335,20 +420,33 @@ __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double p
   const GMEM int *row_grp = gbl(D.row_grp), *grp_pos = gbl(D.grp_pos), *grp_diag = gbl(D.grp_diag);
   const GMEM int *grp_ptr = gbl(D.grp_ptr), *pair_dst = gbl(D.pair_dst), *pair_src = gbl(D.pair_src);
   const GMEM int *diag = gbl(D.lu_diag);
+  constexpr int NW = BS / 64;
+  const int t = tid(), lane = t & 63, wave = t >> 6;
+  // per-wave row buffers in the LDS vector area (free while G_k is refactored)
+  const bool wave_rows_fit = NW * D.max_row <= L.R;
   int bad = 0;
   for (int lv = 0; lv < D.n_lev; ++lv) {
-    for (int q = lev_ptr[lv] + tid(); q < lev_ptr[lv + 1]; q += BS) {
-      const int i = lev_rows[q];
-      double rmax = 0.0;
-      for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) rmax = fmax(rmax, fabs(a[p]));
-      for (int g = row_grp[i]; g < row_grp[i + 1]; ++g) {
-        const int pik = grp_pos[g];
-        const double l = a[pik] / a[grp_diag[g]];
-        a[pik] = l;
-        for (int u = grp_ptr[g]; u < grp_ptr[g + 1]; ++u) a[pair_dst[u]] -= l * a[pair_src[u]];
+    const int q0 = lev_ptr[lv], q1 = lev_ptr[lv + 1];
+    if (wave_rows_fit && q1 - q0 <= 4 * NW) {
+      for (int q = q0 + wave; q < q1; q += NW) {
+        const int i = lev_rows[q];
+        refactor_row_wave<BS>(a, rowptr, row_grp, grp_pos, grp_diag, grp_ptr, pair_dst, pair_src, i, diag[i],
+                              L.region + wave * D.max_row, piv_tol, lane, bad);
       }
-      const double dii = a[diag[i]];
-      if (!(fabs(dii) > piv_tol * rmax)) bad = 1;
+    } else {
+      for (int q = q0 + t; q < q1; q += BS) {
+        const int i = lev_rows[q];
+        double rmax = 0.0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) rmax = fmax(rmax, fabs(a[p]));
+        for (int g = row_grp[i]; g < row_grp[i + 1]; ++g) {
+          const int pik = grp_pos[g];
+          const double l = a[pik] / a[grp_diag[g]];
+          a[pik] = l;
+          for (int u = grp_ptr[g]; u < grp_ptr[g + 1]; ++u) a[pair_dst[u]] -= l * a[pair_src[u]];
+        }
+        const double dii = a[diag[i]];
+        if (!(fabs(dii) > piv_tol * rmax)) bad = 1;
+      }
     }
     __syncthreads();
   }
@@ -484,7 +582,6 @@ __device__ __forceinline__ double csr_row_dot(const int *rp, const int *ci, cons
 //    MFMA 16x16x4 tiles, one output tile per wave.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -1414,6 +1511,10 @@ __global__ void __launch_bounds__(BS) k_diag(const InstDesc *descs, int what, in
       for (int l = 0; l < D.n_lpass + D.n_upass; ++l) __syncthreads();
     } else if (what == 6) {
       acc += hess_phi<BS>(D, L, D.He, arg, 2e-12, 1.0, 1e-14, L.derr);
+    } else if (what == 7) {
+      assemble<BS>(D, false);
+      __syncthreads();
+      acc += refactor<BS>(D, L, 0.0) ? 1.0 : 0.0;
     }
   }
   const long long t1 = wall_clock64();

@@ -67,9 +67,9 @@ struct PatternDev {
   Symbolic sym;
   // flattened solve schedules and C ELL pattern (depend on the block size)
   std::vector<SolveLevel> lsched, usched;
-  std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code;
+  std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code, rdv_pos, jpos;
   int32_t c_ell_k = 0, n_lpass = 0, n_upass = 0, pl = 1, pu = 1, u_slot_base = 0, u_row_base = 0;
-  size_t o_pass_code, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col;
+  size_t o_pass_code, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col, o_rdv_pos, o_jpos;
   size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
       grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
       g_rowptr, g_col, c_rowptr, c_col, b_rowptr, b_col, dev_node, perm;
@@ -79,7 +79,7 @@ struct Inst {
   int pat = 0;
   int32_t n = 0, n_dev = 0, n_src = 0, n_probe = 0, n_bp = 0;
   double vdd = 1.0, T = 0.0, h_max = 0.0;
-  size_t g_val, c_val, b_val, c_ell_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
+  size_t g_val, g_lu, c_val, b_val, c_ell_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
   // workspace offsets
   size_t xk, x1, w, p, z, tmp, e, Ik, devI, devD, devI1, lu, sval, rdv, V, Ve, H, He, mat, state, trace;
   int64_t ldv = 0;
@@ -250,6 +250,7 @@ void fill_descs(expri_ctx *c) {
     d.n_ulev = (int32_t)S.ulev_ptr.size() - 1;
     d.n_probe = I.n_probe;
     d.has_dev = I.n_dev > 0;
+    d.max_row = S.max_row;
     d.vdd = I.vdd;
     d.T = I.T;
     d.h_max = I.h_max;
@@ -272,7 +273,8 @@ void fill_descs(expri_ctx *c) {
     d.c_ell_col = ci(P.o_c_ell_col); d.c_ell_k = P.c_ell_k;
     d.c_ell_val = cd(I.c_ell_val);
     d.probe = ci(I.probe);
-    d.g_val = cd(I.g_val); d.c_val = cd(I.c_val); d.b_val = cd(I.b_val);
+    d.g_val = cd(I.g_val); d.c_val = cd(I.c_val); d.b_val = cd(I.b_val); d.g_lu = cd(I.g_lu);
+    d.rdv_pos = ci(P.o_rdv_pos); d.jpos = ci(P.o_jpos); d.n_jpos = (int32_t)P.jpos.size();
     d.dev_par = cd(I.dev_par); d.src_ptr = ci(I.src_ptr); d.src_t = cd(I.src_t);
     d.src_v = cd(I.src_v); d.bp = cd(I.bp);
     d.xk = wd(I.xk); d.x1 = wd(I.x1); d.w = wd(I.w); d.p = wd(I.p); d.z = wd(I.z);
@@ -429,7 +431,7 @@ expri_status expri_default_opts(expri_opts *o) {
   o->block_size = 0;
   o->trace_cap = 4096;
   o->erc = 0;
-  o->pad_erc = 0;
+  o->solve_slots = 0;
   o->gamma = 0.1;
   return EXPRI_OK;
 }
@@ -448,6 +450,8 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       !(op.h_init > 0) || !(op.h_min > 0) || !(op.h_max >= 0) || !(op.breakdown >= 0) ||
       !(op.piv_tol >= 0) || op.m_max < 1 || op.m_max > kMaxKrylov || op.trace_cap < 1 ||
       (op.erc != 0 && op.erc != 1) || !std::isfinite(op.gamma) ||
+      (op.solve_slots != 0 && op.solve_slots != 1 && op.solve_slots != 2 && op.solve_slots != 4 &&
+       op.solve_slots != 8) ||
       (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
     *out = c.release();
     (*out)->err = "invalid options";
@@ -537,10 +541,10 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   const size_t R = NX + RD;
   // flattened solve schedules and the C ELL pattern for this block size
   for (auto &P : c->pats) {
-    build_solve_schedule(P.sym, c->bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of);
+    build_solve_schedule(P.sym, c->bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots);
     P.u_slot_base = (int32_t)P.slot_pos.size();
     P.u_row_base = (int32_t)P.row_of.size();
-    build_solve_schedule(P.sym, c->bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of);
+    build_solve_schedule(P.sym, c->bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots);
     P.pass_code = pass_codes(P.lsched);
     P.n_lpass = (int32_t)P.pass_code.size();
     const std::vector<int32_t> up = pass_codes(P.usched);
@@ -549,6 +553,13 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.pl = P.lsched.empty() ? 1 : P.lsched[0].P;
     P.pu = P.usched.empty() ? 1 : P.usched[0].P;
     P.c_ell_k = build_c_ell(P.sym, P.c_ell_col);
+    // pivot positions for the U passes' row slots; positions with device terms
+    P.rdv_pos.assign(P.row_of.size(), -1);
+    for (size_t r = (size_t)P.u_row_base; r < P.row_of.size(); ++r)
+      if (P.row_of[r] >= 0) P.rdv_pos[r] = P.sym.lu_diag[P.row_of[r]];
+    P.jpos.clear();
+    for (size_t p = 0; p + 1 < P.sym.jac_ptr.size(); ++p)
+      if (P.sym.jac_ptr[p + 1] > P.sym.jac_ptr[p]) P.jpos.push_back((int32_t)p);
   }
   // ---- pack constant data ----
   Packer pk;
@@ -566,6 +577,8 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.b_rowptr = pk.add(S.b_rowptr); P.b_col = pk.add(S.b_col);
     P.dev_node = pk.add(S.dev_node); P.perm = pk.add(S.perm);
     P.o_pass_code = pk.add(P.pass_code);
+    P.o_rdv_pos = pk.add(P.rdv_pos);
+    P.o_jpos = pk.add(P.jpos);
     P.o_slot_pos = pk.add(P.slot_pos); P.o_slot_col = pk.add(P.slot_col); P.o_row_of = pk.add(P.row_of);
     P.o_c_ell_col = pk.add(P.c_ell_col);
   }
@@ -574,6 +587,13 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     Inst &I = c->inst[k];
     const Symbolic &S = c->pats[I.pat].sym;
     I.g_val = pk.add(gather(K.G.val, S.g_src));
+    {
+      const std::vector<double> gperm = gather(K.G.val, S.g_src);
+      std::vector<double> glu(S.lu_gidx.size(), 0.0);
+      for (size_t p = 0; p < glu.size(); ++p)
+        if (S.lu_gidx[p] >= 0) glu[p] = gperm[S.lu_gidx[p]];
+      I.g_lu = pk.add(glu);
+    }
     const std::vector<double> cperm = gather(K.C.val, S.c_src);
     I.c_val = pk.add(cperm);
     {
@@ -839,7 +859,7 @@ expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
 }
 
 expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, int32_t arg, double *seconds) {
-  if (!c || !seconds || what < 0 || what > 6 || reps < 1) return EXPRI_EINVAL;
+  if (!c || !seconds || what < 0 || what > 7 || reps < 1) return EXPRI_EINVAL;
   if (arg < 0 || arg > c->opts.m_max - 1 || (what == 6 && arg < 1)) return EXPRI_EINVAL;
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;

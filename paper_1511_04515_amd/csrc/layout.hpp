@@ -72,7 +72,7 @@ constexpr int kPassSync = 1;  // pass code flag: last pass of its level
 struct InstDesc {
   int32_t n, n_dev, n_src, n_bp;
   int32_t nnz_lu, n_lev, n_ulev, n_probe;
-  int32_t has_dev, pad0, pad1, pad2;
+  int32_t has_dev, max_row, pad1, pad2;  // max_row: longest row of L\U
   double vdd, T, h_max;
 
   // symbolic (shared by instances of one pattern)
@@ -88,6 +88,9 @@ struct InstDesc {
   // base + q * BS + t / G
   const int32_t *pass_code;
   const int32_t *slot_pos, *slot_col, *row_of;
+  const int32_t *rdv_pos;             // per row slot of the U passes: position of u_ii (-1: none)
+  const int32_t *jpos;                // L\U positions that receive device derivatives
+  int32_t n_jpos, pad5;
   int32_t n_lpass, n_upass, pl, pu;   // passes and slots per lane of L and U
   int32_t u_slot_base, u_row_base;    // where the U passes start
   int32_t n_slots, n_srows;           // sizes of slot_pos / row_of
@@ -99,6 +102,7 @@ struct InstDesc {
 
   // values (per instance, permuted to the internal numbering)
   const double *g_val, *c_val, *b_val;
+  const double *g_lu;           // G_lin scattered to the L\U positions (0 elsewhere)
   const double *c_ell_val;
   const double *dev_par;        // 4 per device: type (+1/-1), K = k' W/L, V_th, lambda
   const int32_t *src_ptr;       // n_src + 1

@@ -509,7 +509,7 @@ constexpr int kSlotMax = 8;  // entries per lane and pass (the kernel's register
 // a barrier, its padding only bandwidth.
 void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
                           std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
-                          std::vector<int32_t> &row_of) {
+                          std::vector<int32_t> &row_of, int force_p) {
   const auto &ptr = lower ? S.lev_ptr : S.ulev_ptr;
   const auto &rows = lower ? S.lev_rows : S.ulev_rows;
   const int nlev = (int)ptr.size() - 1;
@@ -539,7 +539,7 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
     const double cost = fits ? passes * (1.0 + P / 8.0) : 1e300;
     if (cost < best) { best = cost; bestP = P; }
   }
-  const int P = bestP;
+  const int P = force_p > 0 ? force_p : bestP;
   sched.clear();
   for (int l = 0; l < nlev; ++l) {
     const int r0 = ptr[l], r1 = ptr[l + 1], nr = r1 - r0;

@@ -81,7 +81,7 @@ uint64_t pattern_hash(const PatternInput &in);
 // direction share one slot count P per lane.
 void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
                           std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
-                          std::vector<int32_t> &row_of);
+                          std::vector<int32_t> &row_of, int force_p = 0);
 
 // The passes of a schedule in execution order, one code each:
 // (log2(G) << 8) | kPassSync on the last pass of a level.
