@@ -22,7 +22,11 @@
  *     on return.  Arguments documented as "device" are device pointers that the
  *     caller owns (e.g. PyTorch tensors) and that must stay valid for the call.
  *   - Work is queued on the HIP stream given to expri_setup; every entry point
- *     that produces results synchronises that stream before returning.
+ *     that produces results synchronises that stream before returning.  A
+ *     batch whose instances need different block sizes (see expri_setup)
+ *     runs its transient kernel as one launch per block size, concurrently:
+ *     the first on that stream, the others on streams the context creates
+ *     (default priority), forked from and joined back to it with events.
  *   - Every call returns an expri_status; nothing throws, aborts or prints.
  *     expri_last_error() gives a message for the last failure.  After an error
  *     in a transient call the caller's state vectors hold the last accepted
@@ -115,7 +119,9 @@ typedef struct {
    * estimate of the uncorrected x_{k+1}.  Default erc = 0, gamma = 0.1. */
   int32_t erc;
   /* slots per lane of the flattened triangular-solve passes (1, 2, 4 or 8;
-   * 0 = chosen per direction from the pass count and the padding) */
+   * 0 = chosen per direction from the pass count and the padding; a value
+   * that the longest row of a level does not fit in 64 lanes falls back to
+   * the automatic choice) */
   int32_t solve_slots;
   double gamma;
 } expri_opts;
@@ -156,6 +162,10 @@ expri_status expri_default_opts(expri_opts *o);
 /* Analyse and upload n_inst circuits (host data, copied).  Builds the
  * symbolic analysis of G_k's pattern (fill-reducing order, L\U pattern, level
  * schedules, refactor update lists, stamp maps) once per distinct pattern.
+ * Each instance runs in one workgroup whose block size is the smallest of
+ * 256 / 512 / 1024 with n <= 2048 / 4608 / 9216 (or opts.block_size, which
+ * must then satisfy n <= 9 block_size for every instance); instances of one
+ * block size form a launch class.
  * hip_stream: the hipStream_t all work is queued on (NULL = default stream).
  * EINVAL for malformed input; ENOMEM / EHIP on allocation failure. */
 expri_status expri_setup(expri_ctx **ctx, const expri_circuit *ckt, int32_t n_inst,
@@ -215,10 +225,20 @@ expri_status expri_step(expri_ctx *ctx, double *const *x, double t, double h,
  * cap * (EXPRI_REC_FIXED + n_probe) doubles); *n_rec = records available. */
 expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_t cap, int64_t *n_rec);
 
-/* Summed device duration (HIP events on the context's stream) of the
- * transient-kernel launches of the last expri_run / expri_run_schedule /
- * expri_step call, and their number. */
+/* Summed device duration (HIP events on the context's stream, around the
+ * concurrent launches of all launch classes) of the transient-kernel launches
+ * of the last expri_run / expri_run_schedule / expri_step call, and their
+ * number. */
 expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *launches);
+
+/* The launch classes, block size descending: *n_classes receives their
+ * number; for the first min(cap, n) classes block_size[q], n_inst[q] and
+ * kernel_s[q] (the summed duration of that class's transient-kernel launches
+ * in the last transient call, HIP events on the stream it runs on) are
+ * written where the array is not NULL, and inst_class (host, n_inst
+ * entries, may be NULL) receives the class of every instance. */
+expri_status expri_launch_classes(const expri_ctx *ctx, int32_t cap, int32_t *block_size, int32_t *n_inst,
+                                  double *kernel_s, int32_t *inst_class, int32_t *n_classes);
 
 /* Diagnostic: device time (seconds per repetition, GPU wall clock) of one
  * building block of the step on instance 0's current factors:
@@ -231,8 +251,8 @@ expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *l
  * EXPRI_EINVAL unless 0 <= arg < m_max (and arg >= 1 for what = 6). */
 expri_status expri_diag_time(expri_ctx *ctx, int32_t what, int32_t reps, int32_t arg, double *seconds);
 
-/* Threads per workgroup the kernels are launched with (one workgroup per
- * instance). */
+/* Threads per workgroup of the first launch class (the largest block size
+ * in the batch; one workgroup per instance). */
 expri_status expri_block_size(const expri_ctx *ctx, int32_t *bs);
 
 /* Counters of the last transient / DC call of instance inst. */
@@ -260,11 +280,16 @@ expri_status expri_lu_values(const expri_ctx *ctx, int32_t inst, double *out);
  * full length.  EINVAL for an unknown name. */
 typedef struct expri_symbolic expri_symbolic;
 expri_status expri_symbolic_create(expri_symbolic **sym, const expri_circuit *ckt);
-/* Build the flattened solve schedules for block size bs (256, 512, 1024),
- * exposed as arrays "lsched" / "usched" (6 ints per level: G, P, passes, 0,
- * slot_base, row_base), "slot_pos", "slot_col", "row_of" and "c_ell_col"
- * (ELL pattern of C, followed by its width). */
-expri_status expri_symbolic_schedule(expri_symbolic *sym, int32_t bs);
+/* Build the flattened solve schedules for block size bs (256, 512, 1024)
+ * and slots per lane solve_slots (as expri_opts.solve_slots; a value that a
+ * row does not fit falls back to the automatic choice), exposed as arrays
+ * "lsched" / "usched" (6 ints per level: G, P, passes, rows, slot_base,
+ * row_base), "slot_pos", "slot_col", "row_of", "pass_code" (one per pass, L
+ * then U: (active << 16) | (log2 G << 8) | 1 on a level's last pass, lanes
+ * t >= active holding no row) and "c_ell_col" (ELL pattern of C, followed by
+ * its width).  EXPRI_EINVAL for a bad bs or solve_slots, or
+ * when a row of L or U has more than 512 off-diagonal entries. */
+expri_status expri_symbolic_schedule(expri_symbolic *sym, int32_t bs, int32_t solve_slots);
 expri_status expri_symbolic_array(const expri_symbolic *sym, const char *name, int32_t *out, int64_t cap,
                                   int64_t *len);
 void expri_symbolic_destroy(expri_symbolic *sym);

@@ -27,7 +27,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -
 ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_workspace_size", "expri_bind_workspace",
                 "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run",
                 "expri_run_schedule", "expri_step", "expri_trace", "expri_get_run_info",
-                "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_block_size", "expri_diag_time", "expri_symbolic_create",
+                "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_launch_classes",
+                "expri_block_size", "expri_diag_time", "expri_symbolic_create",
                 "expri_symbolic_array",
                 "expri_symbolic_destroy", "expri_last_error", "expri_destroy",
                 "expri_mlp_create", "expri_mlp_set_norm", "expri_mlp_fit_norm", "expri_mlp_get",
@@ -115,11 +116,12 @@ def load_library(path: str = LIB_PATH):
                               C.POINTER(C.c_int64)], C.c_int),
         "expri_lu_values": ([_p, C.c_int32, _f64p], C.c_int),
         "expri_kernel_time": ([_p, _f64p, _i32p], C.c_int),
+        "expri_launch_classes": ([_p, C.c_int32, _i32p, _i32p, _f64p, _i32p, _i32p], C.c_int),
         "expri_block_size": ([_p, _i32p], C.c_int),
         "expri_diag_time": ([_p, C.c_int32, C.c_int32, C.c_int32, _f64p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
         "expri_symbolic_array": ([_p, C.c_char_p, _i32p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
-        "expri_symbolic_schedule": ([_p, C.c_int32], C.c_int),
+        "expri_symbolic_schedule": ([_p, C.c_int32, C.c_int32], C.c_int),
         "expri_symbolic_destroy": ([_p], None),
         "expri_last_error": ([_p], C.c_char_p),
         "expri_destroy": ([_p], None),
@@ -364,6 +366,20 @@ class Solver:
         self._check(self.lib.expri_diag_time(self.ctx, what, reps, arg, C.byref(sec)))
         return sec.value
 
+    def classes(self):
+        """(classes, inst_class): the launch classes of the batch as
+        [{"block_size", "n_inst", "kernel_s"}], block size descending
+        (kernel_s: the last transient call's summed duration of that class's
+        launches), and the class index of every instance."""
+        n = C.c_int32()
+        self._check(self.lib.expri_launch_classes(self.ctx, 0, None, None, None, None, C.byref(n)))
+        bs = (C.c_int32 * n.value)()
+        cnt = (C.c_int32 * n.value)()
+        ks = (C.c_double * n.value)()
+        ic = np.zeros(self.n_inst, np.int32)
+        self._check(self.lib.expri_launch_classes(self.ctx, n.value, bs, cnt, ks, _ptr(ic, C.c_int32), C.byref(n)))
+        return [{"block_size": bs[q], "n_inst": cnt[q], "kernel_s": ks[q]} for q in range(n.value)], ic
+
     def kernel_time(self):
         """(seconds, launches) of the transient kernel in the last run call."""
         sec = C.c_double()
@@ -427,13 +443,14 @@ SYMBOLIC_ARRAYS = ("perm", "lu_rowptr", "lu_col", "lu_diag", "lev_ptr", "lev_row
                    "block_of")
 
 
-SCHEDULE_ARRAYS = ("lsched", "usched", "slot_pos", "slot_col", "row_of", "c_ell_col")
+SCHEDULE_ARRAYS = ("lsched", "usched", "slot_pos", "slot_col", "row_of", "pass_code", "c_ell_col")
 
 
-def symbolic_analysis(net, block_size: int | None = None) -> dict:
+def symbolic_analysis(net, block_size: int | None = None, solve_slots: int = 0) -> dict:
     """Host-only symbolic analysis of one netlist (no GPU): every integer
     array the kernels are driven by, by name; with block_size also the
-    flattened solve schedules built for that launch block size."""
+    flattened solve schedules built for that launch block size (and
+    solve_slots slots per lane, 0 = automatic)."""
     lib = load_library()
     m = _Marshal()
     k = m.circuit(net)
@@ -445,7 +462,7 @@ def symbolic_analysis(net, block_size: int | None = None) -> dict:
     try:
         names = SYMBOLIC_ARRAYS
         if block_size is not None:
-            st = lib.expri_symbolic_schedule(h, int(block_size))
+            st = lib.expri_symbolic_schedule(h, int(block_size), int(solve_slots))
             if st != 0:
                 raise ExpriError(st, "schedule build failed")
             names = SYMBOLIC_ARRAYS + SCHEDULE_ARRAYS

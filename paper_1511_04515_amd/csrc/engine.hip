@@ -456,7 +456,8 @@ __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double p
 }
 
 // Operands of one solve pass held by one lane: P slot values and columns,
-// the row its group owns and that row's pivot.
+// the row its group owns and that row's pivot.  Lanes at or past the pass's
+// active count (code >> 16) own no row and load nothing.
 template <int P>
 struct PassRegs {
   double v[P];
@@ -468,19 +469,31 @@ struct PassRegs {
 template <int BS, int P, bool UPPER>
 __device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__restrict__ sv,
                                            const GMEM int *__restrict__ scol, const GMEM int *__restrict__ rowof,
-                                           const GMEM double *__restrict__ rdv, int sbase, int rbase, int lg,
+                                           const GMEM double *__restrict__ rdv, int sbase, int rbase, int code,
                                            int t) {
+  const int lg = (code >> 8) & 15;
+  if (t < (code >> 16)) {
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    o.v[j] = sv[sbase + j * BS + t];
-    o.c[j] = scol[sbase + j * BS + t];
+    for (int j = 0; j < P; ++j) {
+      o.v[j] = sv[sbase + j * BS + t];
+      o.c[j] = scol[sbase + j * BS + t];
+    }
+    o.row = rowof[rbase + (t >> lg)];
+    o.dv = UPPER ? rdv[rbase + (t >> lg)] : 1.0;  // the pivot only divides in the U solve
+  } else {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      o.v[j] = 0.0;
+      o.c[j] = 0;
+    }
+    o.row = -1;
+    o.dv = 1.0;
   }
-  o.row = rowof[rbase + (t >> lg)];
-  o.dv = UPPER ? rdv[rbase + (t >> lg)] : 1.0;  // the pivot only divides in the U solve
 }
 
 template <int P, bool UPPER>
-__device__ __forceinline__ void pass_apply(const PassRegs<P> &o, double *xs, int lg, int t) {
+__device__ __forceinline__ void pass_apply(const PassRegs<P> &o, double *xs, int code, int t) {
+  const int lg = (code >> 8) & 15;
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < P; ++j) acc += o.v[j] * xs[o.c[j]];
@@ -506,19 +519,19 @@ __device__ __forceinline__ void solve_dir(const InstDesc &D, double *xs, const G
   const int t = tid();
   PassRegs<P> A, B;
   int ca = code[0], cb;
-  pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase, rbase, ca >> 8, t);
+  pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase, rbase, ca, t);
   for (int q = 0; q < np; q += 2) {
     // the pass after q (the last pass again past the end: in range, unused)
     const int q1 = q + 1 < np ? q + 1 : np - 1;
     cb = code[q1];
-    pass_fetch<BS, P, UPPER>(B, sv, scol, rowof, rdv, sbase + q1 * P * BS, rbase + q1 * BS, cb >> 8, t);
-    pass_apply<P, UPPER>(A, xs, ca >> 8, t);
+    pass_fetch<BS, P, UPPER>(B, sv, scol, rowof, rdv, sbase + q1 * P * BS, rbase + q1 * BS, cb, t);
+    pass_apply<P, UPPER>(A, xs, ca, t);
     if (ca & kPassSync) __syncthreads();
     if (q + 1 >= np) break;
     const int q2 = q + 2 < np ? q + 2 : np - 1;
     ca = code[q2];
-    pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase + q2 * P * BS, rbase + q2 * BS, ca >> 8, t);
-    pass_apply<P, UPPER>(B, xs, cb >> 8, t);
+    pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase + q2 * P * BS, rbase + q2 * BS, ca, t);
+    pass_apply<P, UPPER>(B, xs, cb, t);
     if (cb & kPassSync) __syncthreads();
   }
 }
@@ -1329,9 +1342,9 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
 // #levels sweeps), updates clipped per node to vclip, until max|dx| <= 1e-9 V;
 // then full Newton (uniformly damped to vclip) until max|dx| <= 1e-12 V.
 template <int BS>
-__global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, Opts o, double t0, int max_it,
-                                           int R, int NX) {
-  const InstDesc &D = descs[blockIdx.x];
+__global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, const int *order, Opts o, double t0,
+                                           int max_it, int R, int NX) {
+  const InstDesc &D = descs[order[blockIdx.x]];
   InstState &S = *D.state;
   Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
@@ -1384,8 +1397,9 @@ __global__ void __launch_bounds__(BS) k_dc(const InstDesc *descs, Opts o, double
 
 // stamp + assemble + refactor at x_k
 template <int BS>
-__global__ void __launch_bounds__(BS) k_factor(const InstDesc *descs, Opts o, int R, int NX) {
-  const InstDesc &D = descs[blockIdx.x];
+__global__ void __launch_bounds__(BS) k_factor(const InstDesc *descs, const int *order, Opts o, int R,
+                                               int NX) {
+  const InstDesc &D = descs[order[blockIdx.x]];
   Lds<BS> L = lds_setup<BS>(R, NX);
   stamp_devices<BS>(D, D.xk, D.devI, D.devD);
   __syncthreads();
@@ -1397,24 +1411,27 @@ __global__ void __launch_bounds__(BS) k_factor(const InstDesc *descs, Opts o, in
 
 // y = G_k^{-1} b with the current factors (caller numbering in and out)
 template <int BS>
-__global__ void __launch_bounds__(BS) k_solve(const InstDesc *descs, const double *const *bin,
+__global__ void __launch_bounds__(BS) k_solve(const InstDesc *descs, const int *order, const double *const *bin,
                                               double *const *yout, int R, int NX) {
-  const InstDesc &D = descs[blockIdx.x];
+  const int k = order[blockIdx.x];
+  const InstDesc &D = descs[k];
   Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
-  for (int i = tid(); i < D.n; i += BS) xs[i] = bin[blockIdx.x][gbl(D.perm)[i]];
+  for (int i = tid(); i < D.n; i += BS) xs[i] = bin[k][gbl(D.perm)[i]];
   __syncthreads();
   solve_lds<BS>(D, xs);
-  for (int i = tid(); i < D.n; i += BS) yout[blockIdx.x][gbl(D.perm)[i]] = xs[i];
+  for (int i = tid(); i < D.n; i += BS) yout[k][gbl(D.perm)[i]] = xs[i];
 }
 
 // out = (I - e^{hJ}) v by MEVP_IKS with the current factors; reports m, rho
 template <int BS>
-__global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, const double *const *vin,
-                                             double *const *out, double h, double eps, int R, int NX) {
-  const InstDesc &D = descs[blockIdx.x];
+__global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, const int *order, Opts o,
+                                             const double *const *vin, double *const *out, double h, double eps,
+                                             int R, int NX) {
+  const int k = order[blockIdx.x];
+  const InstDesc &D = descs[k];
   Lds<BS> L = lds_setup<BS>(R, NX);
-  for (int i = tid(); i < D.n; i += BS) gbl(D.tmp)[i] = vin[blockIdx.x][gbl(D.perm)[i]];
+  for (int i = tid(); i < D.n; i += BS) gbl(D.tmp)[i] = vin[k][gbl(D.perm)[i]];
   __syncthreads();
   Basis B;
   basis_start<BS>(D, L, D.tmp, D.V, B);
@@ -1428,7 +1445,7 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, Opts o, cons
   for (int i = tid(); i < D.n; i += BS) {
     double acc = 0.0;
     for (int j = 0; j < B.m; ++j) acc += gbl(D.V)[(int64_t)j * D.ldv + i] * L.dmain[j];
-    out[blockIdx.x][gbl(D.perm)[i]] = B.beta * acc;
+    out[k][gbl(D.perm)[i]] = B.beta * acc;
   }
   if (tid() == 0) {
     D.state->status = st;
@@ -1552,30 +1569,32 @@ hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opt
   return hipGetLastError();
 }
 
-hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R, int NX,
-                     hipStream_t s) {
+hipError_t launch_dc(const InstDesc *d, const int *order, int n_inst, const Opts &o, double t0, int max_it,
+                     int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_dc<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, t0, max_it, R, NX));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_dc<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, o, t0, max_it, R, NX));
   return hipGetLastError();
 }
 
-hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, int NX, hipStream_t s) {
+hipError_t launch_factor(const InstDesc *d, const int *order, int n_inst, const Opts &o, int bs, int R, int NX,
+                         hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_factor<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, R, NX));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_factor<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, o, R, NX));
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, double *const *y, int bs,
-                        int R, int NX, hipStream_t s) {
+hipError_t launch_solve(const InstDesc *d, const int *order, int n_inst, const double *const *b,
+                        double *const *y, int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_solve<BS>, dim3(n_inst), dim3(BS), sh, s, d, b, y, R, NX));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_solve<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, b, y, R, NX));
   return hipGetLastError();
 }
 
-hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
+hipError_t launch_mevp(const InstDesc *d, const int *order, int n_inst, const Opts &o, const double *const *v,
                        double *const *out, double h, double eps, int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_mevp<BS>, dim3(n_inst), dim3(BS), sh, s, d, o, v, out, h, eps, R, NX));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_mevp<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, o, v, out, h, eps,
+                                        R, NX));
   return hipGetLastError();
 }
 

@@ -28,12 +28,13 @@ hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin,
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
                       int replay, int bs, int R, int NX, hipStream_t s);
-hipError_t launch_dc(const InstDesc *d, int n_inst, const Opts &o, double t0, int max_it, int bs, int R, int NX,
-                     hipStream_t s);
-hipError_t launch_factor(const InstDesc *d, int n_inst, const Opts &o, int bs, int R, int NX, hipStream_t s);
-hipError_t launch_solve(const InstDesc *d, int n_inst, const double *const *b, double *const *y, int bs,
-                        int R, int NX, hipStream_t s);
-hipError_t launch_mevp(const InstDesc *d, int n_inst, const Opts &o, const double *const *v,
+hipError_t launch_dc(const InstDesc *d, const int *order, int n_inst, const Opts &o, double t0, int max_it,
+                     int bs, int R, int NX, hipStream_t s);
+hipError_t launch_factor(const InstDesc *d, const int *order, int n_inst, const Opts &o, int bs, int R, int NX,
+                         hipStream_t s);
+hipError_t launch_solve(const InstDesc *d, const int *order, int n_inst, const double *const *b,
+                        double *const *y, int bs, int R, int NX, hipStream_t s);
+hipError_t launch_mevp(const InstDesc *d, const int *order, int n_inst, const Opts &o, const double *const *v,
                        double *const *out, double h, double eps, int bs, int R, int NX, hipStream_t s);
 hipError_t launch_mlp_pack(const float *p, void *out, bool bf16, hipStream_t s);
 hipError_t launch_diag(const InstDesc *d, int what, int reps, int arg, long long *out, int bs, int R, int NX,
@@ -65,6 +66,7 @@ struct Packer {
 
 struct PatternDev {
   Symbolic sym;
+  int bs = 512;  // block size of its launch class
   // flattened solve schedules and C ELL pattern (depend on the block size)
   std::vector<SolveLevel> lsched, usched;
   std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code, rdv_pos, jpos;
@@ -87,6 +89,18 @@ struct Inst {
   expri_run_info info{};
 };
 
+// The instances that share one block size (and so one LDS shape): a launch
+// of the transient kernel per class, the classes concurrently on their own
+// streams (class 0 on the caller's stream), larger block sizes first.
+struct LaunchClass {
+  int bs = 512, R = 0, NX = 0;
+  int first = 0, count = 0;  // their slice of the launch order
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;  // around its k_run launch, on its stream
+  double kernel_s = 0.0;                  // summed k_run duration of the last call
+};
+
 }  // namespace
 
 struct expri_ctx {
@@ -102,13 +116,16 @@ struct expri_ctx {
   InstDesc *d_desc = nullptr;
   std::vector<InstDesc> h_desc;
   void **d_ptrs = nullptr;  // 4 * n_inst device pointers
-  int *d_order = nullptr;   // launch order of the transient kernel (largest first)
+  int *d_order = nullptr;   // instances by launch class, the largest first within a class
+  std::vector<LaunchClass> cls;
+  std::vector<int> inst_class;  // launch class of each instance
+  hipEvent_t ev_fork = nullptr;
   uint16_t *d_ctrl_w = nullptr;  // learned controller: bfloat16 parameters (inference layout)
   float *d_ctrl_norm = nullptr;   // and its standardisation; null = the paper's step control
   float *d_ctrl_tmp = nullptr;    // float32 staging for the conversion
   double ctrl_safety = 1.0;
   bool ctrl_on = false;
-  int bs = 512, R = 8192, NX = 0;
+  int bs = 512;  // block size of class 0
   double wall_hz = 1e8;  // GPU wall-clock counter rate
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double run_kernel_s = 0.0;  // summed duration of the k_run launches of the last call
@@ -342,6 +359,24 @@ expri_status first_error(expri_ctx *c, const std::vector<InstState> &st, const c
   return EXPRI_OK;
 }
 
+// one k_run launch per launch class, the classes concurrently (fork / join
+// on the caller's stream); ev0 / ev1 bracket the whole on the caller's stream
+expri_status launch_run_classes(expri_ctx *c, const Opts &ko, int max_steps, int replay) {
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+  for (auto &K : c->cls) {
+    if (K.stream != c->stream) HIPCHK(c, hipStreamWaitEvent(K.stream, c->ev_fork, 0));
+    HIPCHK(c, hipEventRecord(K.e0, K.stream));
+    HIPCHK(c, launch_run(c->d_desc, c->d_order + K.first, K.count, ko, max_steps, replay, K.bs, K.R, K.NX,
+                         K.stream));
+    HIPCHK(c, hipEventRecord(K.e1, K.stream));
+  }
+  for (auto &K : c->cls)
+    if (K.stream != c->stream) HIPCHK(c, hipStreamWaitEvent(c->stream, K.e1, 0));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  return EXPRI_OK;
+}
+
 // drive k_run until every instance is done (adaptive or replay)
 expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int replay) {
   const int n = (int)c->inst.size();
@@ -362,19 +397,22 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
   for (auto &I : c->inst) I.trace_host.clear();
   c->run_kernel_s = 0.0;
   c->run_launches = 0;
+  for (auto &K : c->cls) K.kernel_s = 0.0;
   std::vector<int32_t> prev(n, 0);
   std::vector<InstState> st;
   const int64_t max_launches = kMaxRunSteps / max_steps + 1;
   for (int64_t launches = 0;; ++launches) {
     if (launches >= max_launches)
       return fail(c, EXPRI_ESTEPMIN, "step budget of " + std::to_string(kMaxRunSteps) + " accepted steps exhausted");
-    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_run(c->d_desc, c->d_order, n, ko, max_steps, replay, c->bs, c->R, c->NX, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    if ((s = launch_run_classes(c, ko, max_steps, replay)) != EXPRI_OK) return s;
     if ((s = read_states(c, st)) != EXPRI_OK) return s;
     float ms = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->run_kernel_s += 1e-3 * ms;
+    for (auto &K : c->cls) {
+      HIPCHK(c, hipEventElapsedTime(&ms, K.e0, K.e1));
+      K.kernel_s += 1e-3 * ms;
+    }
     ++c->run_launches;
     bool all = true;
     for (int k = 0; k < n; ++k) {
@@ -517,37 +555,66 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   int wall_khz = 0;
   if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
     c->wall_hz = 1e3 * wall_khz;
-  // a thread keeps at most 9 rows of a vector in registers (n <= 9 bs)
-  c->bs = op.block_size ? op.block_size : (n_max <= 2048 ? 256 : n_max <= 9 * 512 ? 512 : 1024);
-  if (n_max > 9 * c->bs) {
-    *out = c.release();
-    (*out)->err = "block size " + std::to_string((*out)->bs) + " too small for n = " + std::to_string(n_max);
-    return EXPRI_EINVAL;
+  // ---- launch classes.  A thread keeps at most 9 rows of a vector in
+  // registers (n <= 9 bs): a pattern takes the smallest block size of 256,
+  // 512, 1024 that holds it (or the one the options force), and the
+  // instances of one block size form a launch class ----
+  (void)n_max;
+  for (auto &P : c->pats) {
+    P.bs = op.block_size ? op.block_size : (P.sym.n <= 2048 ? 256 : P.sym.n <= 9 * 512 ? 512 : 1024);
+    if (P.sym.n > 9 * P.bs) {
+      *out = c.release();
+      (*out)->err = "block size " + std::to_string(P.bs) + " too small for n = " + std::to_string(P.sym.n);
+      return EXPRI_EINVAL;
+    }
   }
   const size_t limit = prop.sharedMemPerBlock;
-  const size_t extras = lds_bytes(c->bs, 0);
-  // LDS: the vector area (solve vector / current Arnoldi basis vector, NX
-  // doubles) and behind it the small dense matrices of the Hessenberg
-  // exponential: five 32 x 33 matrices cover m <= 31 (larger m use global
-  // scratch)
-  const size_t NX = ((size_t)n_max + 63) / 64 * 64;
-  size_t RD = std::max<size_t>(5 * 32 * 33, NX < 8192 ? 8192 - NX : 0);
-  if (8 * (NX + RD) + extras > limit && 8 * NX + extras < limit) RD = (limit - extras) / 8 - NX;
-  if (8 * (NX + RD) + extras > limit || RD < 5 * 16 * 17) {
-    *out = c.release();
-    (*out)->err = "circuit too large for the one-workgroup engine (n = " + std::to_string(n_max) + ")";
-    return EXPRI_EINVAL;
+  for (int bs : {1024, 512, 256}) {
+    int nm = 0;
+    for (const auto &I : c->inst)
+      if (c->pats[I.pat].bs == bs) nm = std::max(nm, I.n);
+    if (nm == 0) continue;
+    // LDS: the vector area (solve vector / current Arnoldi basis vector, NX
+    // doubles) and behind it the small dense matrices of the Hessenberg
+    // exponential: five 32 x 33 matrices cover m <= 31 (larger m use global
+    // scratch)
+    const size_t extras = lds_bytes(bs, 0);
+    const size_t NX = ((size_t)nm + 63) / 64 * 64;
+    size_t RD = std::max<size_t>(5 * 32 * 33, NX < 8192 ? 8192 - NX : 0);
+    if (8 * (NX + RD) + extras > limit && 8 * NX + extras < limit) RD = (limit - extras) / 8 - NX;
+    if (8 * (NX + RD) + extras > limit || RD < 5 * 16 * 17) {
+      *out = c.release();
+      (*out)->err = "circuit too large for the one-workgroup engine (n = " + std::to_string(nm) + ")";
+      return EXPRI_EINVAL;
+    }
+    LaunchClass K;
+    K.bs = bs;
+    K.NX = (int)NX;
+    K.R = (int)(NX + RD);
+    c->cls.push_back(K);
   }
-  const size_t R = NX + RD;
-  // flattened solve schedules and the C ELL pattern for this block size
+  c->bs = c->cls[0].bs;
+  c->inst_class.resize(n_inst);
+  for (int k = 0; k < n_inst; ++k)
+    for (size_t q = 0; q < c->cls.size(); ++q)
+      if (c->cls[q].bs == c->pats[c->inst[k].pat].bs) c->inst_class[k] = (int)q;
+  // flattened solve schedules and the C ELL pattern for the pattern's block size
   for (auto &P : c->pats) {
-    build_solve_schedule(P.sym, c->bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots);
-    P.u_slot_base = (int32_t)P.slot_pos.size();
-    P.u_row_base = (int32_t)P.row_of.size();
-    build_solve_schedule(P.sym, c->bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots);
-    P.pass_code = pass_codes(P.lsched);
+    P.u_slot_base = -1;
+    if (build_solve_schedule(P.sym, P.bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots)) {
+      P.u_slot_base = (int32_t)P.slot_pos.size();
+      P.u_row_base = (int32_t)P.row_of.size();
+      if (!build_solve_schedule(P.sym, P.bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots))
+        P.u_slot_base = -1;
+    }
+    if (P.u_slot_base < 0) {
+      *out = c.release();
+      (*out)->err = "a row of L or U is longer than the triangular solve handles (512 entries)";
+      return EXPRI_EINVAL;
+    }
+    P.pass_code = pass_codes(P.lsched, P.bs);
     P.n_lpass = (int32_t)P.pass_code.size();
-    const std::vector<int32_t> up = pass_codes(P.usched);
+    const std::vector<int32_t> up = pass_codes(P.usched, P.bs);
     P.n_upass = (int32_t)up.size();
     P.pass_code.insert(P.pass_code.end(), up.begin(), up.end());
     P.pl = P.lsched.empty() ? 1 : P.lsched[0].P;
@@ -642,25 +709,43 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_desc), sizeof(InstDesc) * n_inst);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_ptrs), sizeof(void *) * 4 * n_inst);
   if (e == hipSuccess) {
-    // longest-processing-time-first: larger instances (more nodes, then more
-    // devices) are launched first so they do not wait for a free compute unit
+    // by launch class; within a class longest-processing-time-first: larger
+    // instances (more nodes, then more devices) are launched first so they do
+    // not wait for a free compute unit
     std::vector<int> order(n_inst);
     for (int k = 0; k < n_inst; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (c->inst_class[a] != c->inst_class[b]) return c->inst_class[a] < c->inst_class[b];
       if (ckt[a].n != ckt[b].n) return ckt[a].n > ckt[b].n;
       return ckt[a].dev.n > ckt[b].dev.n;
     });
+    for (int k = 0; k < n_inst; ++k) {
+      LaunchClass &K = c->cls[c->inst_class[order[k]]];
+      if (K.count == 0) K.first = k;
+      ++K.count;
+    }
     e = hipMalloc(reinterpret_cast<void **>(&c->d_order), sizeof(int) * n_inst);
     if (e == hipSuccess) e = hipMemcpy(c->d_order, order.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "setup upload"); }
 
-  c->R = (int)R;
-  c->NX = (int)NX;
   e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
-  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "event create"); }
-  e = set_lds_limits(lds_bytes(c->bs, c->R));
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_fork);
+  for (size_t q = 0; q < c->cls.size() && e == hipSuccess; ++q) {
+    LaunchClass &K = c->cls[q];
+    e = hipEventCreate(&K.e0);
+    if (e == hipSuccess) e = hipEventCreate(&K.e1);
+    if (e == hipSuccess && q == 0) K.stream = c->stream;
+    if (e == hipSuccess && q > 0) {
+      e = hipStreamCreateWithFlags(&K.stream, hipStreamNonBlocking);
+      K.own_stream = e == hipSuccess;
+    }
+  }
+  if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "event / stream create"); }
+  // the per-kernel LDS ceiling is process-wide: allow the device maximum and
+  // pass each launch its own size
+  e = set_lds_limits(limit);
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "LDS limit"); }
   c->ws_bytes = layout_workspace(c.get());
   *out = c.release();
@@ -692,7 +777,9 @@ expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {
   if ((s = upload_descs(c)) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
   HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t0, c->opts.h_init, c->stream));
-  HIPCHK(c, launch_dc(c->d_desc, n, kernel_opts(c->opts), t0, 20000, c->bs, c->R, c->NX, c->stream));
+  for (const auto &K : c->cls)
+    HIPCHK(c, launch_dc(c->d_desc, c->d_order + K.first, K.count, kernel_opts(c->opts), t0, 20000, K.bs, K.R, K.NX,
+                        c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   // write back only instances that converged (x keeps its input otherwise)
@@ -714,7 +801,9 @@ expri_status expri_factor(expri_ctx *c, const double *const *x) {
   if ((s = upload_descs(c)) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
   HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), 0.0, c->opts.h_init, c->stream));
-  HIPCHK(c, launch_factor(c->d_desc, n, kernel_opts(c->opts), c->bs, c->R, c->NX, c->stream));
+  for (const auto &K : c->cls)
+    HIPCHK(c, launch_factor(c->d_desc, c->d_order + K.first, K.count, kernel_opts(c->opts), K.bs, K.R, K.NX,
+                            c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   return first_error(c, st, "factor");
@@ -727,8 +816,10 @@ expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y)
   const int n = (int)c->inst.size();
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(b))) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(y))) != EXPRI_OK) return s;
-  HIPCHK(c, launch_solve(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs),
-                         reinterpret_cast<double *const *>(c->d_ptrs + n), c->bs, c->R, c->NX, c->stream));
+  for (const auto &K : c->cls)
+    HIPCHK(c, launch_solve(c->d_desc, c->d_order + K.first, K.count,
+                           reinterpret_cast<const double *const *>(c->d_ptrs),
+                           reinterpret_cast<double *const *>(c->d_ptrs + n), K.bs, K.R, K.NX, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return EXPRI_OK;
 }
@@ -741,8 +832,10 @@ expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out
   const int n = (int)c->inst.size();
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(v))) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(out))) != EXPRI_OK) return s;
-  HIPCHK(c, launch_mevp(c->d_desc, n, kernel_opts(c->opts), reinterpret_cast<const double *const *>(c->d_ptrs),
-                        reinterpret_cast<double *const *>(c->d_ptrs + n), h, eps, c->bs, c->R, c->NX, c->stream));
+  for (const auto &K : c->cls)
+    HIPCHK(c, launch_mevp(c->d_desc, c->d_order + K.first, K.count, kernel_opts(c->opts),
+                          reinterpret_cast<const double *const *>(c->d_ptrs),
+                          reinterpret_cast<double *const *>(c->d_ptrs + n), h, eps, K.bs, K.R, K.NX, c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
   for (int k = 0; k < n; ++k) {
@@ -865,7 +958,8 @@ expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, int32_t a
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   long long *d = nullptr;
   HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&d), 2 * sizeof(long long)));
-  hipError_t e = launch_diag(c->d_desc, what, reps, arg, d, c->bs, c->R, c->NX, c->stream);
+  const LaunchClass &K = c->cls[c->inst_class[0]];
+  hipError_t e = launch_diag(c->d_desc, what, reps, arg, d, K.bs, K.R, K.NX, c->stream);
   long long h[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -885,6 +979,20 @@ expri_status expri_kernel_time(const expri_ctx *c, double *seconds, int32_t *lau
   if (!c || !seconds || !launches) return EXPRI_EINVAL;
   *seconds = c->run_kernel_s;
   *launches = c->run_launches;
+  return EXPRI_OK;
+}
+
+expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *block_size, int32_t *n_inst,
+                                  double *kernel_s, int32_t *inst_class, int32_t *n_classes) {
+  if (!c || !n_classes || cap < 0) return EXPRI_EINVAL;
+  *n_classes = (int32_t)c->cls.size();
+  if (inst_class)
+    for (size_t k = 0; k < c->inst_class.size(); ++k) inst_class[k] = c->inst_class[k];
+  for (int32_t q = 0; q < std::min<int32_t>(cap, *n_classes); ++q) {
+    if (block_size) block_size[q] = c->cls[q].bs;
+    if (n_inst) n_inst[q] = c->cls[q].count;
+    if (kernel_s) kernel_s[q] = c->cls[q].kernel_s;
+  }
   return EXPRI_OK;
 }
 
@@ -929,6 +1037,12 @@ void expri_destroy(expri_ctx *c) {
   if (c->d_order) (void)hipFree(c->d_order);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  for (auto &K : c->cls) {
+    if (K.e0) (void)hipEventDestroy(K.e0);
+    if (K.e1) (void)hipEventDestroy(K.e1);
+    if (K.own_stream && K.stream) (void)hipStreamDestroy(K.stream);
+  }
   delete c;
 }
 

@@ -63,7 +63,7 @@ struct InstState {
 // stored entries (P is the same for every level of one direction); the
 // level's rows need `passes` sweeps of the block.
 struct SolveLevel {
-  int32_t G, P, passes, pad;
+  int32_t G, P, passes, rows;  // rows: rows of the level
   int32_t slot_base;  // into slot_pos / slot_col: index (q * P + j) * BS + t
   int32_t row_base;   // into row_of: index q * BS + t / G
 };
@@ -83,7 +83,8 @@ struct InstDesc {
   const int32_t *g_rowptr, *g_col, *c_rowptr, *c_col, *b_rowptr, *b_col;
   const int32_t *dev_node;      // 3 per device
   // flattened solve schedules (built for the launch block size): the L
-  // passes then the U passes, one code each ((log2 G << 8) | kPassSync); pass q of
+  // passes then the U passes, one code each ((active << 16) | (log2 G << 8) |
+  // kPassSync; lanes t >= active have no row in the pass); pass q of
   // a direction reads slots base + (q * P + j) * BS + t and row slots
   // base + q * BS + t / G
   const int32_t *pass_code;

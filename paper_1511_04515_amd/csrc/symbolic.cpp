@@ -506,8 +506,9 @@ constexpr int kSlotMax = 8;  // entries per lane and pass (the kernel's register
 // the direction reads slots (q * P + j) * bs + t, j < P (coalesced), and group
 // t / G owns row row_of[q * bs + t / G].  P is chosen per direction to
 // minimise passes * (1 + P / 8): a pass costs a dependent load round trip and
-// a barrier, its padding only bandwidth.
-void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
+// a barrier, its padding only bandwidth.  Returns false (and builds nothing)
+// when a row is longer than 64 lanes x kSlotMax slots.
+bool build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
                           std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
                           std::vector<int32_t> &row_of, int force_p) {
   const auto &ptr = lower ? S.lev_ptr : S.ulev_ptr;
@@ -526,6 +527,7 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
   };
   int bestP = 1;
   double best = 1e300;
+  bool forced_fits = false;
   for (int P = 1; P <= kSlotMax; P *= 2) {
     bool fits = true;
     long passes = 0;
@@ -538,8 +540,11 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
     }
     const double cost = fits ? passes * (1.0 + P / 8.0) : 1e300;
     if (cost < best) { best = cost; bestP = P; }
+    if (P == force_p) forced_fits = fits;
   }
-  const int P = force_p > 0 ? force_p : bestP;
+  if (!(best < 1e300)) return false;
+  // a requested P is taken only where every level's longest row fits it
+  const int P = forced_fits ? force_p : bestP;
   sched.clear();
   for (int l = 0; l < nlev; ++l) {
     const int r0 = ptr[l], r1 = ptr[l + 1], nr = r1 - r0;
@@ -551,6 +556,7 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
     L.G = G;
     L.P = P;
     L.passes = passes;
+    L.rows = nr;
     L.slot_base = (int32_t)slot_pos.size();
     L.row_base = (int32_t)row_of.size();
     slot_pos.resize(slot_pos.size() + (size_t)passes * P * bs, -1);
@@ -572,15 +578,18 @@ void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
     }
     sched.push_back(L);
   }
+  return true;
 }
 
-std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched) {
+std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched, int bs) {
   std::vector<int32_t> out;
   for (const auto &L : sched)
     for (int q = 0; q < L.passes; ++q) {
       int lg = 0;
       while ((1 << lg) < L.G) ++lg;
-      out.push_back((lg << 8) | (q == L.passes - 1 ? kPassSync : 0));
+      const int per_pass = bs / L.G;
+      const int active = std::min(per_pass, L.rows - q * per_pass) * L.G;
+      out.push_back((active << 16) | (lg << 8) | (q == L.passes - 1 ? kPassSync : 0));
     }
   return out;
 }

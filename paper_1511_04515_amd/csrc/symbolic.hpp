@@ -79,13 +79,14 @@ uint64_t pattern_hash(const PatternInput &in);
 // Flattened schedule of one triangular solve for block size bs (lower = L
 // solve, else U solve); appends to the slot / row arrays.  All levels of one
 // direction share one slot count P per lane.
-void build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
+bool build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<SolveLevel> &sched,
                           std::vector<int32_t> &slot_pos, std::vector<int32_t> &slot_col,
                           std::vector<int32_t> &row_of, int force_p = 0);
 
 // The passes of a schedule in execution order, one code each:
-// (log2(G) << 8) | kPassSync on the last pass of a level.
-std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched);
+// (active << 16) | (log2(G) << 8) | kPassSync on the last pass of a level,
+// where lanes t < active hold the pass's rows (rows in the pass times G).
+std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched, int bs);
 
 // ELL layout of C's (permuted) pattern: entry k of row i at k * n + i, -1 =
 // padding; returns the ELL width.

@@ -10,7 +10,7 @@
 struct expri_symbolic {
   expri::Symbolic sym;
   // flattened schedules for one block size (expri_symbolic_schedule)
-  std::vector<int32_t> lsched, usched, slot_pos, slot_col, row_of, c_ell_col;
+  std::vector<int32_t> lsched, usched, slot_pos, slot_col, row_of, pass_code, c_ell_col;
 };
 
 extern "C" {
@@ -38,20 +38,30 @@ expri_status expri_symbolic_create(expri_symbolic **out, const expri_circuit *k)
   return EXPRI_OK;
 }
 
-expri_status expri_symbolic_schedule(expri_symbolic *s, int32_t bs) {
+expri_status expri_symbolic_schedule(expri_symbolic *s, int32_t bs, int32_t solve_slots) {
   if (!s || (bs != 256 && bs != 512 && bs != 1024)) return EXPRI_EINVAL;
+  if (solve_slots != 0 && solve_slots != 1 && solve_slots != 2 && solve_slots != 4 && solve_slots != 8)
+    return EXPRI_EINVAL;
   std::vector<expri::SolveLevel> L, U;
   s->slot_pos.clear();
   s->slot_col.clear();
   s->row_of.clear();
-  expri::build_solve_schedule(s->sym, bs, true, L, s->slot_pos, s->slot_col, s->row_of);
-  expri::build_solve_schedule(s->sym, bs, false, U, s->slot_pos, s->slot_col, s->row_of);
+  if (!expri::build_solve_schedule(s->sym, bs, true, L, s->slot_pos, s->slot_col, s->row_of, solve_slots) ||
+      !expri::build_solve_schedule(s->sym, bs, false, U, s->slot_pos, s->slot_col, s->row_of, solve_slots)) {
+    s->slot_pos.clear();
+    s->slot_col.clear();
+    s->row_of.clear();
+    return EXPRI_EINVAL;
+  }
   auto flat = [](const std::vector<expri::SolveLevel> &v, std::vector<int32_t> &o) {
     o.clear();
-    for (const auto &l : v) o.insert(o.end(), {l.G, l.P, l.passes, l.pad, l.slot_base, l.row_base});
+    for (const auto &l : v) o.insert(o.end(), {l.G, l.P, l.passes, l.rows, l.slot_base, l.row_base});
   };
   flat(L, s->lsched);
   flat(U, s->usched);
+  s->pass_code = expri::pass_codes(L, bs);
+  const std::vector<int32_t> up = expri::pass_codes(U, bs);
+  s->pass_code.insert(s->pass_code.end(), up.begin(), up.end());
   const int32_t k = expri::build_c_ell(s->sym, s->c_ell_col);
   s->c_ell_col.push_back(k);  // last element: the ELL width
   return EXPRI_OK;
@@ -70,7 +80,7 @@ expri_status expri_symbolic_array(const expri_symbolic *s, const char *name, int
   A(c_src) A(b_rowptr) A(b_col) A(b_src) A(dev_node) A(block_of)
 #undef A
 #define B(X) if (nm == #X) v = &s->X;
-  B(lsched) B(usched) B(slot_pos) B(slot_col) B(row_of) B(c_ell_col)
+  B(lsched) B(usched) B(slot_pos) B(slot_col) B(row_of) B(pass_code) B(c_ell_col)
 #undef B
   if (!v) return EXPRI_EINVAL;
   *len = (int64_t)v->size();

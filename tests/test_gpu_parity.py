@@ -219,6 +219,44 @@ def test_batch_matches_single_instance_runs():
     sb.close()
 
 
+def test_mixed_size_batch_runs_as_concurrent_classes_and_matches_single_runs():
+    # chains of 841, 2521 and 4831 nodes take block sizes 256, 512 and 1024:
+    # three launch classes, the transient kernels concurrent on three streams
+    nets = [netgen.inverter_chain(seed=40 + i, n_stages=L, T=0.3e-9, t_ramp=0.1e-9)
+            for i, L in enumerate((230, 40, 120, 40, 230))]
+    sb = Solver(nets)
+    classes, ic = sb.classes()
+    assert [c["block_size"] for c in classes] == [1024, 512, 256]
+    assert [c["n_inst"] for c in classes] == [2, 1, 2]
+    assert ic.tolist() == [0, 2, 1, 2, 0]
+    xb = sb.zeros()
+    sb.dc(xb)
+    x_dc = [x.clone() for x in xb]
+    sb.factor(xb)
+    rng = np.random.default_rng(3)
+    rhs = sb.to_device([rng.standard_normal(n.n) for n in nets])
+    yb = sb.zeros()
+    sb.solve(rhs, yb)
+    sb.run(xb)
+    assert all(c["kernel_s"] > 0 for c in sb.classes()[0])
+    for i, net in enumerate(nets):
+        s1 = Solver(net)
+        assert s1.classes()[0][0]["block_size"] == classes[ic[i]]["block_size"]
+        x1 = s1.zeros()
+        s1.dc(x1)
+        assert np.array_equal(x1[0].cpu().numpy(), x_dc[i].cpu().numpy())
+        s1.factor(x1)
+        y1 = s1.zeros()
+        s1.solve([rhs[i]], y1)
+        assert np.array_equal(y1[0].cpu().numpy(), yb[i].cpu().numpy())
+        s1.run(x1)
+        a, b = sb.trace(i), s1.trace(0)
+        assert len(a["t"]) > 5 and np.array_equal(a["t"], b["t"]) and np.array_equal(a["x"], b["x"])
+        assert np.array_equal(xb[i].cpu().numpy(), x1[0].cpu().numpy())
+        s1.close()
+    sb.close()
+
+
 def test_error_paths_keep_last_state():
     import paper_1511_04515_amd as E
     # step below h_min: the chain is active from t = 0 and no trial meets an

@@ -163,27 +163,37 @@ def emulate_flat_solve(S, lu, b, bs):
     x = b.copy()
     n = b.size
     nnz = lu.size
+    codes = iter(S["pass_code"].tolist())
+    lane = np.arange(bs)
     for lower, sched in ((True, S["lsched"].reshape(-1, 6)), (False, S["usched"].reshape(-1, 6))):
         assert len(set(sched[:, 1].tolist())) <= 1 and set(sched[:, 1].tolist()) <= {1, 2, 4, 8}
         for G, P, passes, _, sb, rb in sched:
             assert G in (1, 2, 4, 8, 16, 32, 64) and P >= 1 and passes >= 1
             for q in range(passes):
-                idx = sb + (q * P + np.arange(P))[:, None] * bs + np.arange(bs)[None, :]
+                code = next(codes)
+                # lanes t >= active load nothing: their slots and rows must be empty
+                active = code >> 16
+                assert (1 << ((code >> 8) & 15)) == G and (code & 1) == (q == passes - 1)
+                assert 0 < active <= bs and active % G == 0
+                idx = sb + (q * P + np.arange(P))[:, None] * bs + lane[None, :]
                 assert idx.max() < S["slot_pos"].size
-                pos = S["slot_pos"][idx]
-                col = S["slot_col"][idx]
+                pos = np.where(lane[None, :] < active, S["slot_pos"][idx], -1)
+                col = np.where(lane[None, :] < active, S["slot_col"][idx], 0)
+                assert (S["slot_pos"][idx][:, active:] < 0).all()
                 assert pos.max() < nnz and col.min() >= 0 and col.max() < n
                 prod = np.where(pos >= 0, lu[np.maximum(pos, 0)] * x[col], 0.0)
                 acc = prod.sum(0).reshape(bs // G, G).sum(1)
                 ridx = rb + q * bs + np.arange(bs // G)
                 assert ridx.max() < S["row_of"].size
-                rows = S["row_of"][ridx]
+                assert (S["row_of"][ridx][active // G:] < 0).all()
+                rows = np.where(np.arange(bs // G) < active // G, S["row_of"][ridx], -1)
                 ok = rows >= 0
                 assert rows.max() < n
                 if lower:
                     x[rows[ok]] -= acc[ok]
                 else:
                     x[rows[ok]] = (x[rows[ok]] - acc[ok]) / lu[S["lu_diag"][rows[ok]]]
+    assert next(codes, None) is None
     return x
 
 
@@ -230,3 +240,32 @@ def test_flattened_solve_schedule_matches_row_solve(make, bs):
     got_cv = np.array([sum(vals[k, i] * v[ell[k, i]] for k in range(K) if ell[k, i] >= 0) for i in range(net.n)])
     # rows with coupling caps cancel: compare against |C| |v|
     assert np.max(np.abs(got_cv - Cp @ v)) <= 1e-14 * np.max(abs(Cp) @ np.abs(v))
+
+
+@pytest.mark.parametrize("slots", [1, 2, 4, 8])
+@pytest.mark.parametrize("make", [lambda: netgen.config(2), lambda: netgen.config(1)])
+def test_forced_slot_count_schedule_matches_row_solve(make, slots):
+    net = make()
+    S = symbolic_analysis(net, block_size=512, solve_slots=slots)
+    rng = np.random.default_rng(2)
+    lu = rng.uniform(0.5, 1.5, S["lu_col"].size)
+    lu[S["lu_diag"]] += 10.0
+    b = rng.standard_normal(net.n)
+    got = emulate_flat_solve(S, lu, b, 512)
+    ref = emulate_solve(S, lu, b)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # per direction: the requested count, or the automatic one where a
+    # level's longest row does not fit the request in 64 lanes
+    auto = symbolic_analysis(net, block_size=512)
+    for d in ("lsched", "usched"):
+        P = set(S[d].reshape(-1, 6)[:, 1].tolist())
+        assert P == {slots} or P == set(auto[d].reshape(-1, 6)[:, 1].tolist())
+        if P != {slots}:
+            K = (S["lu_diag"] - S["lu_rowptr"][:-1]) if d == "lsched" else (S["lu_rowptr"][1:] - S["lu_diag"] - 1)
+            assert K.max() > 64 * slots
+
+
+def test_schedule_rejects_bad_slot_count():
+    from paper_1511_04515_amd import ExpriError
+    with pytest.raises(ExpriError):
+        symbolic_analysis(netgen.config(2), block_size=512, solve_slots=3)
