@@ -123,6 +123,11 @@ typedef struct {
    * that the longest row of a level does not fit in 64 lanes falls back to
    * the automatic choice) */
   int32_t solve_slots;
+  /* at most this many workgroups of the transient kernel resident on the GPU
+   * at a time, each taking the batch's instances in turn (0 = one per compute
+   * unit; fewer leave compute units to other work) */
+  int32_t max_workgroups;
+  int32_t reserved;  /* 0 */
   double gamma;
 } expri_opts;
 
@@ -232,13 +237,16 @@ expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_
 expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *launches);
 
 /* The launch classes, block size descending: *n_classes receives their
- * number; for the first min(cap, n) classes block_size[q], n_inst[q] and
- * kernel_s[q] (the summed duration of that class's transient-kernel launches
- * in the last transient call, HIP events on the stream it runs on) are
- * written where the array is not NULL, and inst_class (host, n_inst
- * entries, may be NULL) receives the class of every instance. */
+ * number; for the first min(cap, n) classes block_size[q], n_inst[q],
+ * workgroups[q] (the transient kernel's grid; its workgroups take the
+ * class's instances in turn) and kernel_s[q] (the summed duration of that
+ * class's transient-kernel launches in the last transient call, HIP events on
+ * the stream it runs on) are written where the array is not NULL, and
+ * inst_class (host, n_inst entries, may be NULL) receives the class of every
+ * instance. */
 expri_status expri_launch_classes(const expri_ctx *ctx, int32_t cap, int32_t *block_size, int32_t *n_inst,
-                                  double *kernel_s, int32_t *inst_class, int32_t *n_classes);
+                                  int32_t *workgroups, double *kernel_s, int32_t *inst_class,
+                                  int32_t *n_classes);
 
 /* Diagnostic: device time (seconds per repetition, GPU wall clock) of one
  * building block of the step on instance 0's current factors:

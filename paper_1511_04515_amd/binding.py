@@ -67,7 +67,8 @@ class Opts(C.Structure):
                 ("h_max", C.c_double), ("breakdown", C.c_double), ("piv_tol", C.c_double),
                 ("grow_if_rejects_lt", C.c_int32), ("m_max", C.c_int32),
                 ("block_size", C.c_int32), ("trace_cap", C.c_int32),
-                ("erc", C.c_int32), ("solve_slots", C.c_int32), ("gamma", C.c_double)]
+                ("erc", C.c_int32), ("solve_slots", C.c_int32),
+                ("max_workgroups", C.c_int32), ("reserved", C.c_int32), ("gamma", C.c_double)]
 
 
 class RunInfo(C.Structure):
@@ -116,7 +117,7 @@ def load_library(path: str = LIB_PATH):
                               C.POINTER(C.c_int64)], C.c_int),
         "expri_lu_values": ([_p, C.c_int32, _f64p], C.c_int),
         "expri_kernel_time": ([_p, _f64p, _i32p], C.c_int),
-        "expri_launch_classes": ([_p, C.c_int32, _i32p, _i32p, _f64p, _i32p, _i32p], C.c_int),
+        "expri_launch_classes": ([_p, C.c_int32, _i32p, _i32p, _i32p, _f64p, _i32p, _i32p], C.c_int),
         "expri_block_size": ([_p, _i32p], C.c_int),
         "expri_diag_time": ([_p, C.c_int32, C.c_int32, C.c_int32, _f64p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
@@ -368,17 +369,21 @@ class Solver:
 
     def classes(self):
         """(classes, inst_class): the launch classes of the batch as
-        [{"block_size", "n_inst", "kernel_s"}], block size descending
-        (kernel_s: the last transient call's summed duration of that class's
-        launches), and the class index of every instance."""
+        [{"block_size", "n_inst", "workgroups", "kernel_s"}], block size
+        descending (workgroups: the transient kernel's grid; kernel_s: the
+        last transient call's summed duration of that class's launches), and
+        the class index of every instance."""
         n = C.c_int32()
-        self._check(self.lib.expri_launch_classes(self.ctx, 0, None, None, None, None, C.byref(n)))
+        self._check(self.lib.expri_launch_classes(self.ctx, 0, None, None, None, None, None, C.byref(n)))
         bs = (C.c_int32 * n.value)()
         cnt = (C.c_int32 * n.value)()
+        wg = (C.c_int32 * n.value)()
         ks = (C.c_double * n.value)()
         ic = np.zeros(self.n_inst, np.int32)
-        self._check(self.lib.expri_launch_classes(self.ctx, n.value, bs, cnt, ks, _ptr(ic, C.c_int32), C.byref(n)))
-        return [{"block_size": bs[q], "n_inst": cnt[q], "kernel_s": ks[q]} for q in range(n.value)], ic
+        self._check(self.lib.expri_launch_classes(self.ctx, n.value, bs, cnt, wg, ks, _ptr(ic, C.c_int32),
+                                                  C.byref(n)))
+        return [{"block_size": bs[q], "n_inst": cnt[q], "workgroups": wg[q], "kernel_s": ks[q]}
+                for q in range(n.value)], ic
 
     def kernel_time(self):
         """(seconds, launches) of the transient kernel in the last run call."""

@@ -110,7 +110,8 @@ __device__ __forceinline__ double group_sum(double v, int G) {
 //   region : R doubles  -- solve vector, or small dense matrices
 //   slots  : 2 * NW doubles -- reduction exchange (double buffered)
 //   dmain, derr : kHLd doubles each -- small vectors d of the two MEVPs
-//   ipiv   : 8 ints
+//   4 doubles unused
+//   prof, hcol, derr2
 template <int BS>
 struct Lds {
   double *region;  // vector area: solve vector / current Arnoldi basis vector
@@ -118,8 +119,7 @@ struct Lds {
   double *slots;
   double *dmain;
   double *derr;
-  int *ipiv;   // 4 ints of pivot exchange
-  double *bc;  // 1 double of broadcast from wave 0
+
   double *hcol; // kHLd doubles: current Hessenberg column
   double *derr2;  // kHLd doubles: ER-C coefficients on the error basis
   long long *prof;  // kPhases phase counters
@@ -967,8 +967,6 @@ __device__ Lds<BS> lds_setup(int R, int NX) {
   L.slots = smem + R;
   L.dmain = L.slots + 2 * (BS / 64);
   L.derr = L.dmain + kHLd;
-  L.ipiv = reinterpret_cast<int *>(L.derr + kHLd);
-  L.bc = L.derr + kHLd + 2;
   L.prof = reinterpret_cast<long long *>(L.derr + kHLd + 4);
   L.hcol = L.derr + kHLd + 4 + kPhases;
   L.derr2 = L.hcol + kHLd;
@@ -1016,17 +1014,15 @@ __global__ void k_end(const InstDesc *descs, double *const *xout) {
   for (int i = tid(); i < D.n; i += blockDim.x) x[gbl(D.perm)[i]] = gbl(D.xk)[i];
 }
 
-// The ER transient (Algorithm 2), resumable: runs at most max_steps accepted
-// steps of every unfinished instance.  replay != 0: the step ends are taken
-// from gbl(D.bp) (the given grid) and every first trial is accepted.
+// The ER transient (Algorithm 2) of one instance, resumable: runs at most
+// max_steps accepted steps unless the instance is done.  replay != 0: the
+// step ends are taken from gbl(D.bp) (the given grid) and every first trial
+// is accepted.
 template <int BS>
-__global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *order, Opts o,
-                                            int max_steps, int replay, int R, int NX) {
-  // workgroups start in blockIdx order: order[] lists the largest instances first
-  const InstDesc &D = descs[order[blockIdx.x]];
+__device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, const Opts &o, int max_steps,
+                                             int replay) {
   InstState &S = *D.state;
   if (S.done) return;
-  Lds<BS> L = lds_setup<BS>(R, NX);
   double *xs = L.region;
   const int n = D.n;
   double t = S.t, h_prop = S.h_prop;
@@ -1337,6 +1333,34 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
   }
 }
 
+// The transient of one launch class: a grid of at most one workgroup per
+// compute unit left to the class, each taking the next instance of the class's
+// slice of the launch order (largest first) from the counter *next until the
+// slice is exhausted, so that the classes launched together never wait for
+// one another's compute units.  *next starts at 0; every workgroup leaves once
+// the counter passes count.
+template <int BS>
+__global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *order, int count, int *next,
+                                            Opts o, int max_steps, int replay, int R, int NX) {
+  Lds<BS> L = lds_setup<BS>(R, NX);
+  for (;;) {
+    // thread 0 takes a ticket; the workgroup maximum broadcasts it, and
+    // readfirstlane tells the compiler it is uniform, so that the descriptor
+    // is addressed (and its fields loaded) through scalar registers
+    const double got = wg_max(L, tid() == 0 ? (double)atomicAdd(next, 1) : -1.0);
+    const int idx = __builtin_amdgcn_readfirstlane((int)got);
+    if (idx >= count) break;
+    const int inst = __builtin_amdgcn_readfirstlane(order[idx]);
+    run_instance<BS>(descs[inst], L, o, max_steps, replay);
+    __syncthreads();
+  }
+}
+
+// next[i] = 0 for the launch classes' instance counters
+__global__ void k_zero_counters(int *next, int n) {
+  if ((int)threadIdx.x < n) next[threadIdx.x] = 0;
+}
+
 // DC operating point: Newton with the derivative couplings between DC blocks
 // dropped (block Jacobi; the blocks form a DAG so it converges in at most
 // #levels sweeps), updates clipped per node to vclip, until max|dx| <= 1e-9 V;
@@ -1467,8 +1491,8 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, const int *o
   }
 
 size_t lds_bytes(int bs, int R) {
-  // region, reduction slots, dmain, derr, 4 doubles (pivot ints,
-  // broadcast), kPhases profile counters, hcol, derr2
+  // region, reduction slots, dmain, derr, 4 doubles (unused), kPhases
+  // profile counters, hcol, derr2
   return sizeof(double) * ((size_t)R + 2 * (bs / 64) + 4 * kHLd + 4 + kPhases);
 }
 
@@ -1561,11 +1585,16 @@ hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
-                      int replay, int bs, int R, int NX, hipStream_t s) {
+hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, int grid, int *next, const Opts &o,
+                      int max_steps, int replay, int bs, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_run<BS>, dim3(n_inst), dim3(BS), sh, s, d, order, o, max_steps,
-                                        replay, R, NX));
+  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_run<BS>, dim3(grid), dim3(BS), sh, s, d, order, n_inst, next, o,
+                                        max_steps, replay, R, NX));
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(int *next, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, next, n);
   return hipGetLastError();
 }
 

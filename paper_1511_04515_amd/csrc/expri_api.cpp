@@ -26,8 +26,9 @@ hipError_t set_lds_limits(size_t bytes);
 hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
                         hipStream_t s);
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
-hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, const Opts &o, int max_steps,
-                      int replay, int bs, int R, int NX, hipStream_t s);
+hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, int grid, int *next, const Opts &o,
+                      int max_steps, int replay, int bs, int R, int NX, hipStream_t s);
+hipError_t launch_zero_counters(int *next, int n, hipStream_t s);
 hipError_t launch_dc(const InstDesc *d, const int *order, int n_inst, const Opts &o, double t0, int max_it,
                      int bs, int R, int NX, hipStream_t s);
 hipError_t launch_factor(const InstDesc *d, const int *order, int n_inst, const Opts &o, int bs, int R, int NX,
@@ -95,6 +96,7 @@ struct Inst {
 struct LaunchClass {
   int bs = 512, R = 0, NX = 0;
   int first = 0, count = 0;  // their slice of the launch order
+  int grid = 1;              // workgroups of its transient launch (each takes instances in turn)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;  // around its k_run launch, on its stream
@@ -119,6 +121,7 @@ struct expri_ctx {
   int *d_order = nullptr;   // instances by launch class, the largest first within a class
   std::vector<LaunchClass> cls;
   std::vector<int> inst_class;  // launch class of each instance
+  int *d_next = nullptr;        // per class: the next instance a transient workgroup takes
   hipEvent_t ev_fork = nullptr;
   uint16_t *d_ctrl_w = nullptr;  // learned controller: bfloat16 parameters (inference layout)
   float *d_ctrl_norm = nullptr;   // and its standardisation; null = the paper's step control
@@ -363,12 +366,14 @@ expri_status first_error(expri_ctx *c, const std::vector<InstState> &st, const c
 // on the caller's stream); ev0 / ev1 bracket the whole on the caller's stream
 expri_status launch_run_classes(expri_ctx *c, const Opts &ko, int max_steps, int replay) {
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, launch_zero_counters(c->d_next, (int)c->cls.size(), c->stream));
   HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
-  for (auto &K : c->cls) {
+  for (size_t q = 0; q < c->cls.size(); ++q) {
+    LaunchClass &K = c->cls[q];
     if (K.stream != c->stream) HIPCHK(c, hipStreamWaitEvent(K.stream, c->ev_fork, 0));
     HIPCHK(c, hipEventRecord(K.e0, K.stream));
-    HIPCHK(c, launch_run(c->d_desc, c->d_order + K.first, K.count, ko, max_steps, replay, K.bs, K.R, K.NX,
-                         K.stream));
+    HIPCHK(c, launch_run(c->d_desc, c->d_order + K.first, K.count, K.grid, c->d_next + q, ko, max_steps, replay,
+                         K.bs, K.R, K.NX, K.stream));
     HIPCHK(c, hipEventRecord(K.e1, K.stream));
   }
   for (auto &K : c->cls)
@@ -470,6 +475,8 @@ expri_status expri_default_opts(expri_opts *o) {
   o->trace_cap = 4096;
   o->erc = 0;
   o->solve_slots = 0;
+  o->max_workgroups = 0;
+  o->reserved = 0;
   o->gamma = 0.1;
   return EXPRI_OK;
 }
@@ -490,6 +497,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       (op.erc != 0 && op.erc != 1) || !std::isfinite(op.gamma) ||
       (op.solve_slots != 0 && op.solve_slots != 1 && op.solve_slots != 2 && op.solve_slots != 4 &&
        op.solve_slots != 8) ||
+      op.max_workgroups < 0 || op.reserved != 0 ||
       (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
     *out = c.release();
     (*out)->err = "invalid options";
@@ -724,7 +732,24 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       if (K.count == 0) K.first = k;
       ++K.count;
     }
-    e = hipMalloc(reinterpret_cast<void **>(&c->d_order), sizeof(int) * n_inst);
+    // transient grids: the first class (largest block size) one workgroup per
+    // instance; the compute units it leaves are shared by the other classes in
+    // proportion to their instance counts (at least one workgroup each), so
+    // that every workgroup of every class finds a compute unit at once.  With
+    // max_workgroups the first class is capped as well.
+    const int ncls = (int)c->cls.size();
+    const int cus = op.max_workgroups > 0 ? op.max_workgroups : std::max(prop.multiProcessorCount, 1);
+    int rest = 0;
+    for (int q = 1; q < ncls; ++q) rest += c->cls[q].count;
+    c->cls[0].grid = op.max_workgroups > 0 ? std::min(c->cls[0].count, std::max(1, cus - (ncls - 1)))
+                                           : c->cls[0].count;
+    const int left = std::max(cus - c->cls[0].grid, 0);
+    for (size_t q = 1; q < c->cls.size(); ++q) {
+      LaunchClass &K = c->cls[q];
+      K.grid = std::max(1, std::min(K.count, (int)((long long)left * K.count / std::max(rest, 1))));
+    }
+    e = hipMalloc(reinterpret_cast<void **>(&c->d_next), sizeof(int) * c->cls.size());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_order), sizeof(int) * n_inst);
     if (e == hipSuccess) e = hipMemcpy(c->d_order, order.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) { *out = c.release(); return hip_fail(*out, e, "setup upload"); }
@@ -983,7 +1008,8 @@ expri_status expri_kernel_time(const expri_ctx *c, double *seconds, int32_t *lau
 }
 
 expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *block_size, int32_t *n_inst,
-                                  double *kernel_s, int32_t *inst_class, int32_t *n_classes) {
+                                  int32_t *workgroups, double *kernel_s, int32_t *inst_class,
+                                  int32_t *n_classes) {
   if (!c || !n_classes || cap < 0) return EXPRI_EINVAL;
   *n_classes = (int32_t)c->cls.size();
   if (inst_class)
@@ -991,6 +1017,7 @@ expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *bloc
   for (int32_t q = 0; q < std::min<int32_t>(cap, *n_classes); ++q) {
     if (block_size) block_size[q] = c->cls[q].bs;
     if (n_inst) n_inst[q] = c->cls[q].count;
+    if (workgroups) workgroups[q] = c->cls[q].grid;
     if (kernel_s) kernel_s[q] = c->cls[q].kernel_s;
   }
   return EXPRI_OK;
@@ -1035,6 +1062,7 @@ void expri_destroy(expri_ctx *c) {
   if (c->d_desc) (void)hipFree(c->d_desc);
   if (c->d_ptrs) (void)hipFree(c->d_ptrs);
   if (c->d_order) (void)hipFree(c->d_order);
+  if (c->d_next) (void)hipFree(c->d_next);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);

@@ -257,6 +257,32 @@ def test_mixed_size_batch_runs_as_concurrent_classes_and_matches_single_runs():
     sb.close()
 
 
+def test_capped_workgroups_take_instances_in_turn():
+    # four workgroups for nine instances in two launch classes: each
+    # workgroup runs several instances one after another
+    nets = [netgen.inverter_chain(seed=60 + i, n_stages=L, T=0.2e-9, t_ramp=0.1e-9)
+            for i, L in enumerate((120, 8, 12, 120, 10, 9, 14, 11, 120))]
+    sb = Solver(nets, max_workgroups=4)
+    classes, ic = sb.classes()
+    assert [c["block_size"] for c in classes] == [512, 256]
+    assert [c["n_inst"] for c in classes] == [3, 6]
+    assert [c["workgroups"] for c in classes] == [3, 1]
+    xb = sb.zeros()
+    sb.dc(xb)
+    x0 = [x.clone() for x in xb]
+    sb.run(xb, max_steps_per_launch=16)  # several launches: instances resume
+    for i, net in enumerate(nets):
+        s1 = Solver(net)
+        x1 = [x0[i].clone()]
+        s1.run(x1)
+        a, b = sb.trace(i), s1.trace(0)
+        assert len(a["t"]) > 0 and np.array_equal(a["t"], b["t"]) and np.array_equal(a["x"], b["x"])
+        assert np.array_equal(xb[i].cpu().numpy(), x1[0].cpu().numpy())
+        s1.close()
+    assert max(len(sb.trace(i)["t"]) for i in range(len(nets))) > 16
+    sb.close()
+
+
 def test_error_paths_keep_last_state():
     import paper_1511_04515_amd as E
     # step below h_min: the chain is active from t = 0 and no trial meets an
