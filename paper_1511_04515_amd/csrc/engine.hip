@@ -39,6 +39,18 @@ __device__ __forceinline__ GMEM T *gbl(T *p) {
   return (GMEM T *)p;
 }
 
+// Read-only data that the kernels never write during a launch (schedules):
+// re-typed as constant memory, so that uniform reads become scalar loads,
+// counted apart from the vector loads a solve pass keeps in flight.
+#define CMEM __attribute__((address_space(4)))
+
+// s_waitcnt operand: vector memory count 0, the other counters unconstrained
+constexpr unsigned kWaitVm0 = 0x0F70;
+template <class T>
+__device__ __forceinline__ const CMEM T *cst(const T *p) {
+  return (const CMEM T *)p;
+}
+
 // The thread index as an opaque value.  Per-lane values derived from it
 // (addresses, masks) are then computed inside each phase instead of being
 // hoisted to the kernel entry and held in registers across the whole step.
@@ -317,9 +329,9 @@ __device__ __forceinline__ void assemble(const InstDesc &D, bool dc_block) {
 }
 
 // Slot-ordered copy of the factors for the solves: sval[k] is the L\U value
-// of slot k of the flattened schedules (0 on padding) and rdv[r] the pivot
-// u_ii of the row in row slot r of the U passes (1 where the slot holds no
-// row).  A solve pass then reads its operands with coalesced loads that
+// of slot k of the flattened schedules (0 on padding) and rdv[r] the
+// reciprocal 1 / u_ii of the pivot of the row in row slot r of the U passes
+// (1 where the slot holds no row), so that the U passes multiply.  A solve pass then reads its operands with coalesced loads that
 // depend on nothing the solve computes, so they can be issued a pass ahead.
 template <int BS>
 __device__ __forceinline__ void pack_slots(const InstDesc &D) {
@@ -344,7 +356,7 @@ __device__ __forceinline__ void pack_slots(const InstDesc &D) {
     for (int u = 0; u < 8; ++u) p[u] = r0 + u * BS < r1 ? dpos[r0 + u * BS] : -1;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r0 + u * BS < r1) rdv[r0 + u * BS] = p[u] >= 0 ? a[p[u]] : 1.0;
+      if (r0 + u * BS < r1) rdv[r0 + u * BS] = p[u] >= 0 ? 1.0 / a[p[u]] : 1.0;
   }
   __syncthreads();
 }
@@ -456,8 +468,14 @@ __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double p
 }
 
 // Operands of one solve pass held by one lane: P slot values and columns,
-// the row its group owns and that row's pivot.  Lanes at or past the pass's
-// active count (code >> 16) own no row and load nothing.
+// the row its group owns and that row's reciprocal pivot.  Lanes at or past
+// the pass's active count (code >> 16) own no row and load nothing.
+//
+// The fetch first waits for every load still in flight (the previous fetch,
+// issued a pass earlier).  Its own loads sit in a branch that lanes without a
+// row skip, and after such a branch the compiler cannot count the loads in
+// flight: the arithmetic of the pass whose operands arrived before the branch
+// would otherwise wait for this fetch as well.
 template <int P>
 struct PassRegs {
   double v[P];
@@ -472,6 +490,7 @@ __device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__
                                            const GMEM double *__restrict__ rdv, int sbase, int rbase, int code,
                                            int t) {
   const int lg = (code >> 8) & 15;
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
   if (t < (code >> 16)) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -479,7 +498,7 @@ __device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__
       o.c[j] = scol[sbase + j * BS + t];
     }
     o.row = rowof[rbase + (t >> lg)];
-    o.dv = UPPER ? rdv[rbase + (t >> lg)] : 1.0;  // the pivot only divides in the U solve
+    o.dv = UPPER ? rdv[rbase + (t >> lg)] : 1.0;  // 1 / pivot, used in the U solve only
   } else {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -491,25 +510,27 @@ __device__ __forceinline__ void pass_fetch(PassRegs<P> &o, const GMEM double *__
   }
 }
 
+
 template <int P, bool UPPER>
 __device__ __forceinline__ void pass_apply(const PassRegs<P> &o, double *xs, int code, int t) {
   const int lg = (code >> 8) & 15;
+  // the group leader's own row value is read together with the gathers (a
+  // row is written only by its own pass), not after the group sum
+  const bool lead = (t & ((1 << lg) - 1)) == 0 && o.row >= 0;
+  const double xr = lead ? xs[o.row] : 0.0;
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < P; ++j) acc += o.v[j] * xs[o.c[j]];
   acc = group_sum(acc, 1 << lg);
-  if ((t & ((1 << lg) - 1)) == 0 && o.row >= 0) {
-    if (UPPER) xs[o.row] = (xs[o.row] - acc) / o.dv;
-    else xs[o.row] -= acc;
-  }
+  if (lead) xs[o.row] = UPPER ? (xr - acc) * o.dv : xr - acc;
 }
 
 // The passes of one direction in order, each pass's loads issued while the
 // previous pass computes (two register sets, alternating).  Pass q reads
 // slots sbase + (q P + j) BS + t and row slot rbase + q BS + t / G; a barrier
 // follows the last pass of every level.
-template <int BS, int P, bool UPPER>
-__device__ __forceinline__ void solve_dir(const InstDesc &D, double *xs, const GMEM int *__restrict__ code,
+template <int BS, int P, bool UPPER, bool WAVE0 = false>
+__device__ __forceinline__ void solve_dir(const InstDesc &D, double *xs, const CMEM int *__restrict__ code,
                                           int np, int sbase, int rbase) {
   if (np == 0) return;
   const GMEM double *__restrict__ sv = gbl(D.sval);
@@ -526,34 +547,62 @@ __device__ __forceinline__ void solve_dir(const InstDesc &D, double *xs, const G
     cb = code[q1];
     pass_fetch<BS, P, UPPER>(B, sv, scol, rowof, rdv, sbase + q1 * P * BS, rbase + q1 * BS, cb, t);
     pass_apply<P, UPPER>(A, xs, ca, t);
-    if (ca & kPassSync) __syncthreads();
+    if (ca & kPassSync) {
+      if (WAVE0) wfence();  // one wave: its LDS accesses are in order
+      else __syncthreads();
+    }
     if (q + 1 >= np) break;
     const int q2 = q + 2 < np ? q + 2 : np - 1;
     ca = code[q2];
     pass_fetch<BS, P, UPPER>(A, sv, scol, rowof, rdv, sbase + q2 * P * BS, rbase + q2 * BS, ca, t);
     pass_apply<P, UPPER>(B, xs, cb, t);
-    if (cb & kPassSync) __syncthreads();
+    if (cb & kPassSync) {
+      if (WAVE0) wfence();
+      else __syncthreads();
+    }
+  }
+}
+
+// passes [q0, q0 + np) of one direction (slot count p)
+template <int BS, bool UPPER, bool WAVE0>
+__device__ __forceinline__ void solve_range(const InstDesc &D, double *xs, const CMEM int *code, int p, int q0,
+                                            int np, int sbase, int rbase) {
+  code += q0;
+  sbase += q0 * p * BS;
+  rbase += q0 * BS;
+  switch (p) {
+    case 1: solve_dir<BS, 1, UPPER, WAVE0>(D, xs, code, np, sbase, rbase); break;
+    case 2: solve_dir<BS, 2, UPPER, WAVE0>(D, xs, code, np, sbase, rbase); break;
+    case 4: solve_dir<BS, 4, UPPER, WAVE0>(D, xs, code, np, sbase, rbase); break;
+    default: solve_dir<BS, 8, UPPER, WAVE0>(D, xs, code, np, sbase, rbase); break;
   }
 }
 
 // in-place solve G_k y = b with b (and then y) in the LDS vector xs: the L
-// passes, then the U passes, of the flattened level schedules
+// passes, then the U passes, of the flattened level schedules.  The passes
+// near the root of the elimination tree (the last l_narrow L passes and the
+// first u_narrow U passes, each with at most 64 active lanes) run in wave 0
+// alone, ordered by its own LDS access order instead of workgroup barriers;
+// a barrier on either side of that stretch orders it with the wide passes.
+// Returns after a barrier: xs is complete for every thread.
 template <int BS>
 __device__ __forceinline__ void solve_lds(const InstDesc &D, double *xs, bool lower = true, bool upper = true) {
-  const GMEM int *code = gbl(D.pass_code);
-  if (lower) switch (D.pl) {
-    case 1: solve_dir<BS, 1, false>(D, xs, code, D.n_lpass, 0, 0); break;
-    case 2: solve_dir<BS, 2, false>(D, xs, code, D.n_lpass, 0, 0); break;
-    case 4: solve_dir<BS, 4, false>(D, xs, code, D.n_lpass, 0, 0); break;
-    default: solve_dir<BS, 8, false>(D, xs, code, D.n_lpass, 0, 0); break;
+  const CMEM int *lcode = cst(D.pass_code);
+  const CMEM int *ucode = lcode + D.n_lpass;
+  const int lw = D.n_lpass - D.l_narrow;  // wide L passes
+  const int uw0 = D.u_narrow;             // first wide U pass
+  if (lower && lw > 0) solve_range<BS, false, false>(D, xs, lcode, D.pl, 0, lw, 0, 0);
+  const bool narrow = (lower && D.l_narrow > 0) || (upper && D.u_narrow > 0);
+  if (narrow) {
+    __syncthreads();
+    if (tid() < 64) {
+      if (lower) solve_range<BS, false, true>(D, xs, lcode, D.pl, lw, D.l_narrow, 0, 0);
+      if (upper) solve_range<BS, true, true>(D, xs, ucode, D.pu, 0, D.u_narrow, D.u_slot_base, D.u_row_base);
+    }
+    __syncthreads();
   }
-  code += D.n_lpass;
-  if (upper) switch (D.pu) {
-    case 1: solve_dir<BS, 1, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
-    case 2: solve_dir<BS, 2, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
-    case 4: solve_dir<BS, 4, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
-    default: solve_dir<BS, 8, true>(D, xs, code, D.n_upass, D.u_slot_base, D.u_row_base); break;
-  }
+  if (upper && D.n_upass > uw0)
+    solve_range<BS, true, false>(D, xs, ucode, D.pu, uw0, D.n_upass - uw0, D.u_slot_base, D.u_row_base);
 }
 
 // (C v)_i from the ELL copy of C (entries in the CSR order of the row)
@@ -638,24 +687,46 @@ __device__ __forceinline__ void mm_mfma(PT A, PT B, PT C, int ld, bool add, doub
   __syncthreads();
 }
 
-// entry (r, c) of [H | h I] (m x 2m; zero beyond)
-__device__ __forceinline__ double hess_aug(const GMEM double *H, int m, double h, int r, int c) {
+// entry (r, c) of [H | h I] (m x 2m; zero beyond), H read from the global
+// copy (column-major, leading dimension kHLd) or, when IN_LDS, from the
+// row-major staged copy Hs (leading dimension ld, zeros below the subdiagonal)
+template <bool IN_LDS, class PT>
+__device__ __forceinline__ double hess_aug(const GMEM double *H, PT Hs, int ld, int m, double h, int r, int c) {
   if (c >= 2 * m) return 0.0;
   if (c >= m) return c - m == r ? h : 0.0;
+  if (IN_LDS) return Hs[r * ld + c];
   return r <= c + 1 ? H[r + c * kHLd] : 0.0;
 }
 
 // X = h H^{-1} for the m x m upper Hessenberg H (column-major, leading
 // dimension kHLd, entries r <= c + 1 stored); U receives the triangular
-// factor.  Both m x m with leading dimension ld.
-template <int BS, bool IN_LDS, class PT>
-__device__ __forceinline__ void hess_inverse(const GMEM double *H, int m, double h, PT U, PT X, int ld) {
+// factor and rinv the reciprocals of its diagonal.  U and X are m x m with
+// leading dimension ld.  With IN_LDS, H is first staged into Hs (m x m,
+// leading dimension ld) so that the elimination's row reads are LDS reads,
+// each issued one elimination step ahead.
+template <int BS, int NP, bool IN_LDS, class PT>
+__device__ __forceinline__ void hess_inverse(const GMEM double *H, PT Hs, int m, double h, PT U, PT X, PT rinv,
+                                             int ld) {
   const int t = tid();
+  if (IN_LDS) {
+    for (int idx = t; idx < m * m; idx += BS) {
+      const int r = idx % m, c = idx / m;
+      Hs[r * ld + c] = r <= c + 1 ? H[r + c * kHLd] : 0.0;
+    }
+    __syncthreads();
+  }
   if (t < 64) {
     // lane t owns columns t and t + 64 of [H | h I] (2 m <= 126)
-    double R0 = hess_aug(H, m, h, 0, t), R1 = hess_aug(H, m, h, 0, t + 64);  // the carried row
+    double R0 = hess_aug<IN_LDS>(H, Hs, ld, m, h, 0, t);  // the carried row
+    double R1 = hess_aug<IN_LDS>(H, Hs, ld, m, h, 0, t + 64);
+    double N0 = m > 1 ? hess_aug<IN_LDS>(H, Hs, ld, m, h, 1, t) : 0.0;  // row k + 1
+    double N1 = m > 1 ? hess_aug<IN_LDS>(H, Hs, ld, m, h, 1, t + 64) : 0.0;
     for (int k = 0; k + 1 < m; ++k) {
-      const double F0 = hess_aug(H, m, h, k + 1, t), F1 = hess_aug(H, m, h, k + 1, t + 64);
+      const double F0 = N0, F1 = N1;
+      if (k + 2 < m) {
+        N0 = hess_aug<IN_LDS>(H, Hs, ld, m, h, k + 2, t);
+        N1 = hess_aug<IN_LDS>(H, Hs, ld, m, h, k + 2, t + 64);
+      }
       const double Rk = readlane_d(R0, k), Fk = readlane_d(F0, k);
       const bool sw = fabs(Fk) > fabs(Rk);
       const double P0 = sw ? F0 : R0, P1 = sw ? F1 : R1;
@@ -673,8 +744,39 @@ __device__ __forceinline__ void hess_inverse(const GMEM double *H, int m, double
     if (t < m) U[(m - 1) * ld + t] = R0;
     else if (t < 2 * m) X[(m - 1) * ld + t - m] = R0;
     if (t + 64 < 2 * m) X[(m - 1) * ld + t + 64 - m] = R1;
+    // lane t wrote the diagonal entry u_tt itself
+    if (t < m) rinv[t] = 1.0 / U[t * ld + t];
   }
   __syncthreads();
+  if (IN_LDS && NP <= 32) {
+    // back substitution U X = Y (Y in X), right-looking: column c by the 8
+    // lanes of group c, lane p keeping rows p, p + 8, ... of the column in
+    // registers.  At row r (descending) the owner scales its entry by
+    // 1 / u_rr, the group reads it from the owner, and every lane subtracts
+    // u_ir x_r from its rows i < r.
+    constexpr int RPL = NP / 8;
+    const int c = t >> 3, p = t & 7;
+    const bool own = c < m;
+    double y[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) y[q] = (own && p + 8 * q < m) ? X[(p + 8 * q) * ld + c] : 0.0;
+#pragma unroll
+    for (int r = NP - 1; r >= 0; --r) {
+      if (r < m) {
+        const int qr = r >> 3, pr = r & 7;
+        if (p == pr) y[qr] *= rinv[r];
+        const double xr = __shfl(y[qr], (t & ~7) | pr, 64);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+          if (p + 8 * q < r) y[q] -= U[(p + 8 * q) * ld + r] * xr;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if (own && p + 8 * q < m) X[(p + 8 * q) * ld + c] = y[q];
+    __syncthreads();
+    return;
+  }
   // back substitution U X = Y, Y in X: column c by the G lanes of group c
   const int G = 8 * m <= BS ? 8 : 4;
   const int c = t / G, p = t % G;
@@ -684,7 +786,7 @@ __device__ __forceinline__ void hess_inverse(const GMEM double *H, int m, double
     if (own)
       for (int j = r + 1 + p; j < m; j += G) s += U[r * ld + j] * X[j * ld + c];
     s = group_sum(s, G);
-    if (own && p == 0) X[r * ld + c] = (X[r * ld + c] - s) / U[r * ld + r];
+    if (own && p == 0) X[r * ld + c] = (X[r * ld + c] - s) * rinv[r];
     if (IN_LDS) wfence();  // the group's lanes share one wave; LDS is in order
     else __syncthreads();
   }
@@ -697,7 +799,7 @@ __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM do
   constexpr int ld = NP + 1;
   PT P1 = base, P2 = base + NP * ld, P3 = base + 2 * NP * ld, Ta = base + 3 * NP * ld, Tb = base + 4 * NP * ld;
   // ---- M = h H^{-1} into P3 (P2 holds the triangular factor) ----
-  hess_inverse<BS, IN_LDS>(H, m, h, P2, P3, ld);
+  hess_inverse<BS, NP, IN_LDS>(H, P1, m, h, P2, P3, Ta, ld);
   double mbad = 0.0;
   for (int i = tid(); i < m * m; i += BS)
     if (!isfinite(P3[(i / m) * ld + i % m])) mbad = 1.0;

@@ -72,6 +72,7 @@ struct PatternDev {
   std::vector<SolveLevel> lsched, usched;
   std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code, rdv_pos, jpos;
   int32_t c_ell_k = 0, n_lpass = 0, n_upass = 0, pl = 1, pu = 1, u_slot_base = 0, u_row_base = 0;
+  int32_t l_narrow = 0, u_narrow = 0;
   size_t o_pass_code, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col, o_rdv_pos, o_jpos;
   size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
       grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
@@ -287,6 +288,7 @@ void fill_descs(expri_ctx *c) {
     d.dev_node = ci(P.dev_node); d.perm = ci(P.perm);
     d.pass_code = ci(P.o_pass_code);
     d.n_lpass = P.n_lpass; d.n_upass = P.n_upass; d.pl = P.pl; d.pu = P.pu;
+    d.l_narrow = P.l_narrow; d.u_narrow = P.u_narrow;
     d.u_slot_base = P.u_slot_base; d.u_row_base = P.u_row_base;
     d.n_slots = (int32_t)P.slot_pos.size(); d.n_srows = (int32_t)P.row_of.size();
     d.slot_pos = ci(P.o_slot_pos); d.slot_col = ci(P.o_slot_col); d.row_of = ci(P.o_row_of);
@@ -625,6 +627,12 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     const std::vector<int32_t> up = pass_codes(P.usched, P.bs);
     P.n_upass = (int32_t)up.size();
     P.pass_code.insert(P.pass_code.end(), up.begin(), up.end());
+    // passes one wave holds: the trailing L passes and leading U passes with
+    // at most 64 active lanes
+    P.l_narrow = 0;
+    while (P.l_narrow < P.n_lpass && (P.pass_code[P.n_lpass - 1 - P.l_narrow] >> 16) <= 64) ++P.l_narrow;
+    P.u_narrow = 0;
+    while (P.u_narrow < P.n_upass && (P.pass_code[P.n_lpass + P.u_narrow] >> 16) <= 64) ++P.u_narrow;
     P.pl = P.lsched.empty() ? 1 : P.lsched[0].P;
     P.pu = P.usched.empty() ? 1 : P.usched[0].P;
     P.c_ell_k = build_c_ell(P.sym, P.c_ell_col);

@@ -72,7 +72,10 @@ constexpr int kPassSync = 1;  // pass code flag: last pass of its level
 struct InstDesc {
   int32_t n, n_dev, n_src, n_bp;
   int32_t nnz_lu, n_lev, n_ulev, n_probe;
-  int32_t has_dev, max_row, pad1, pad2;  // max_row: longest row of L\U
+  int32_t has_dev, max_row;  // max_row: longest row of L\U
+  // solve passes that one wave holds (at most 64 active lanes): the last
+  // l_narrow L passes and the first u_narrow U passes
+  int32_t l_narrow, u_narrow;
   double vdd, T, h_max;
 
   // symbolic (shared by instances of one pattern)
