@@ -91,12 +91,16 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libexpri.so (raises if it has not been built)."""
+    """Load libexpri.so (raises if it has not been built).  torch is imported
+    first: its HIP runtime is then the one libexpri binds to, so the process
+    holds a single HIP / HSA runtime (a second copy loaded ahead of torch's
+    leaves one of them without a device)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1511_04515_amd.build.build()")
+    import torch  # noqa: F401  (see above)
     lib = C.CDLL(path)
     pp = C.POINTER(_p)
     sig = {

@@ -609,8 +609,8 @@ __device__ __forceinline__ void solve_lds(const InstDesc &D, double *xs, bool lo
 __device__ __forceinline__ double c_row(const InstDesc &D, const double *v, int i) {
   double s = 0.0;
   for (int k = 0; k < D.c_ell_k; ++k) {
-    const int c = gbl(D.c_ell_col)[(int64_t)k * D.n + i];
-    if (c >= 0) s += gbl(D.c_ell_val)[(int64_t)k * D.n + i] * v[c];
+    const int c = gbl(D.c_ell_col)[(int64_t)k * D.c_ell_ld + i];
+    if (c >= 0) s += gbl(D.c_ell_val)[(int64_t)k * D.c_ell_ld + i] * v[c];
   }
   return s;
 }
@@ -912,7 +912,10 @@ struct Work {  // exact work counters of one launch
 // v_{j+1} on exit.  Thread t owns rows t + e BS (e < E): C v_j is gathered
 // from LDS with the ELL loads of all E rows issued together, w stays in
 // registers through the Gram-Schmidt sweep, and v_{i+1} is loaded while the
-// inner product with v_i is reduced.
+// inner product with v_i is reduced.  The basis and C's ELL columns are
+// padded with zeros to E BS rows, so these loads need no bound test (a
+// branch around them would make the compiler wait for every load in flight
+// before the next inner product); rows past n keep w = 0.
 template <int BS, int E>
 __device__ __forceinline__ void arnoldi_step_e(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
                                double breakdown, Prof &pf) {
@@ -928,15 +931,14 @@ __device__ __forceinline__ void arnoldi_step_e(const InstDesc &D, Lds<BS> &L, do
   for (int e = 0; e < E; ++e) w[e] = 0.0;
   const int K = D.c_ell_k;
   for (int k = 0; k < K; ++k) {
-    const GMEM int *__restrict__ ccol = gbl(D.c_ell_col) + (int64_t)k * n;
-    const GMEM double *__restrict__ cval = gbl(D.c_ell_val) + (int64_t)k * n;
+    const GMEM int *__restrict__ ccol = gbl(D.c_ell_col) + (int64_t)k * D.c_ell_ld + t0;
+    const GMEM double *__restrict__ cval = gbl(D.c_ell_val) + (int64_t)k * D.c_ell_ld + t0;
     int cc[E];
     double cv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int i = t0 + e * BS;
-      cc[e] = i < n ? ccol[i] : -1;
-      cv[e] = i < n ? cval[i] : 0.0;
+      cc[e] = ccol[e * BS];
+      cv[e] = cval[e * BS];
     }
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -954,15 +956,15 @@ __device__ __forceinline__ void arnoldi_step_e(const InstDesc &D, Lds<BS> &L, do
   for (int e = 0; e < E; ++e) w[e] = t0 + e * BS < n ? xs[t0 + e * BS] : 0.0;
   double cur[E], nxt[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) cur[e] = t0 + e * BS < n ? Vg[t0 + e * BS] : 0.0;
+  for (int e = 0; e < E; ++e) cur[e] = Vg[t0 + e * BS];
   for (int i = 0; i <= j; ++i) {
     double part = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) part += w[e] * cur[e];
     if (i < j) {
-      const GMEM double *vn = Vg + (int64_t)(i + 1) * ldv;
+      const GMEM double *vn = Vg + (int64_t)(i + 1) * ldv + t0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) nxt[e] = t0 + e * BS < n ? vn[t0 + e * BS] : 0.0;
+      for (int e = 0; e < E; ++e) nxt[e] = vn[e * BS];
     }
     const double hij = wg_sum(L, part);
 #pragma unroll
@@ -996,11 +998,82 @@ __device__ __forceinline__ void arnoldi_step_e(const InstDesc &D, Lds<BS> &L, do
   pf.mark(3);
 }
 
-// rows per thread: 4 when n <= 4 BS, else 9 (set-up keeps n <= 9 BS)
+// Basis combinations of the trial (thread t owns rows t + e BS, e < E; the
+// zero rows past n are loaded and not stored).  The columns run outermost, so
+// each thread keeps E loads of a column in flight; each row's sum still runs
+// over j in increasing order.
+//  main:  x_{k+1} = (x_k + h p) + beta V_m d; returns 1 if an entry is not finite
+template <int BS, int E>
+__device__ __forceinline__ double combine_main(const InstDesc &D, const double *d, int m, double beta, double h) {
+  const int n = D.n, t0 = tid();
+  const GMEM double *Vg = gbl(D.V) + t0, *xk = gbl(D.xk), *pp = gbl(D.p);
+  GMEM double *x1 = gbl(D.x1);
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+#pragma unroll 2
+  for (int j = 0; j < m; ++j) {
+    const double dj = d[j];
+    const GMEM double *col = Vg + (int64_t)j * D.ldv;
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] += col[e * BS] * dj;
+  }
+  double bad = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t0 + e * BS;
+    if (i < n) {
+      const double v = (xk[i] + h * pp[i]) + beta * acc[e];
+      x1[i] = v;
+      if (!isfinite(v)) bad = 1.0;
+    }
+  }
+  return bad;
+}
+
+//  error: max_i |beta_e (V_e d_e)_i|; with ER-C also x_{k+1} -= gamma beta_e V_e d2
+template <int BS, int E>
+__device__ __forceinline__ double combine_err(const InstDesc &D, const double *de, const double *d2, int m,
+                                              double beta, double gamma, bool erc) {
+  const int n = D.n, t0 = tid();
+  const GMEM double *Vg = gbl(D.Ve) + t0;
+  GMEM double *x1 = gbl(D.x1);
+  double acc[E], acc2[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    acc[e] = 0.0;
+    acc2[e] = 0.0;
+  }
+#pragma unroll 2
+  for (int j = 0; j < m; ++j) {
+    const double dj = de[j], d2j = erc ? d2[j] : 0.0;
+    const GMEM double *col = Vg + (int64_t)j * D.ldv;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double vji = col[e * BS];
+      acc[e] += vji * dj;
+      if (erc) acc2[e] += vji * d2j;
+    }
+  }
+  double emax = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t0 + e * BS;
+    if (i < n) {
+      emax = nmax(emax, fabs(beta * acc[e]));
+      if (erc) x1[i] -= gamma * (beta * acc2[e]);
+    }
+  }
+  return emax;
+}
+
+// rows per thread: rows_per_thread(n, BS) = 4, 6 or 9 (set-up keeps n <= 9 BS)
 template <int BS>
 __device__ __forceinline__ void arnoldi_step(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
                              double breakdown, Prof &pf) {
-  if (D.n <= 4 * BS) arnoldi_step_e<BS, 4>(D, L, V, H, B, breakdown, pf);
+  const int e = rows_per_thread(D.n, BS);
+  if (e == 4) arnoldi_step_e<BS, 4>(D, L, V, H, B, breakdown, pf);
+  else if (e == 6) arnoldi_step_e<BS, 6>(D, L, V, H, B, breakdown, pf);
   else arnoldi_step_e<BS, 9>(D, L, V, H, B, breakdown, pf);
 }
 
@@ -1106,6 +1179,18 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
     int b = 0;
     while (b < D.n_bp - 1 && gbl(D.bp)[b] <= t0) ++b;
     S.bp_idx = b;
+  }
+}
+
+// Zero the padding rows n .. ldv - 1 of every column of V and V_e (the
+// kernels load them unconditionally and never write them).
+__global__ void k_zero_basis_pad(const InstDesc *descs) {
+  const InstDesc &D = descs[blockIdx.x];
+  const int pad = (int)D.ldv - D.n;
+  for (int idx = tid(); idx < pad * D.vcols; idx += blockDim.x) {
+    const int64_t o = (int64_t)(idx / pad) * D.ldv + D.n + idx % pad;
+    gbl(D.V)[o] = 0.0;
+    gbl(D.Ve)[o] = 0.0;
   }
 }
 
@@ -1299,18 +1384,10 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
       if (status != kOK) break;
       wk.comb += Bm.m;
       // x_{k+1} = x_k + h p + beta V_m d
-      double bad = 0.0;
-      {
-        const GMEM double *Vg = gbl(D.V), *xk = gbl(D.xk), *pp = gbl(D.p);
-        GMEM double *x1 = gbl(D.x1);
-        for (int i = tid(); i < n; i += BS) {
-          double acc = 0.0;
-          for (int j = 0; j < Bm.m; ++j) acc += Vg[(int64_t)j * D.ldv + i] * L.dmain[j];
-          const double v = (xk[i] + h * pp[i]) + Bm.beta * acc;
-          x1[i] = v;
-          if (!isfinite(v)) bad = 1.0;
-        }
-      }
+      const int rpt = rows_per_thread(n, BS);
+      const double bad = rpt == 4   ? combine_main<BS, 4>(D, L.dmain, Bm.m, Bm.beta, h)
+                         : rpt == 6 ? combine_main<BS, 6>(D, L.dmain, Bm.m, Bm.beta, h)
+                                    : combine_main<BS, 9>(D, L.dmain, Bm.m, Bm.beta, h);
       if (wg_max(L, bad) != 0.0) { status = kENONFINITE; break; }
       err = 0.0;
       m_err = 0;
@@ -1358,20 +1435,12 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
         if (status != kOK) break;
         m_err = Be.m;
         wk.comb += Be.m;
-        double emax = 0.0;
-        const GMEM double *Veg = gbl(D.Ve);
-        GMEM double *x1g = gbl(D.x1);
-        for (int i = tid(); i < n; i += BS) {
-          double acc = 0.0, acc2 = 0.0;
-          for (int j = 0; j < Be.m; ++j) {
-            const double vji = Veg[(int64_t)j * D.ldv + i];
-            acc += vji * L.derr[j];
-            if (o.erc) acc2 += vji * L.derr2[j];
-          }
-          emax = nmax(emax, fabs(Be.beta * acc));
-          // ER-C: x_{k+1} -= gamma h phi_2(hJ) C^{-1} dF = gamma beta_e V_e d2
-          if (o.erc) x1g[i] -= o.gamma * (Be.beta * acc2);
-        }
+        // ER-C: x_{k+1} -= gamma h phi_2(hJ) C^{-1} dF = gamma beta_e V_e d2
+        const int rpe = rows_per_thread(n, BS);
+        const double emax =
+            rpe == 4   ? combine_err<BS, 4>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+            : rpe == 6 ? combine_err<BS, 6>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+                       : combine_err<BS, 9>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0);
         if (o.erc) wk.comb += Be.m;
         err = wg_max(L, emax);
       }
@@ -1679,6 +1748,11 @@ hipError_t launch_diag(const InstDesc *d, int what, int reps, int arg, long long
 hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_begin, dim3(n_inst), dim3(256), 0, s, d, xin, t0, h0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_basis_pad(const InstDesc *d, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_basis_pad, dim3(n_inst), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ hipError_t set_lds_limits(size_t bytes);
 hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
                         hipStream_t s);
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
+hipError_t launch_zero_basis_pad(const InstDesc *d, int n_inst, hipStream_t s);
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, int grid, int *next, const Opts &o,
                       int max_steps, int replay, int bs, int R, int NX, hipStream_t s);
 hipError_t launch_zero_counters(int *next, int n, hipStream_t s);
@@ -72,7 +73,7 @@ struct PatternDev {
   std::vector<SolveLevel> lsched, usched;
   std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code, rdv_pos, jpos;
   int32_t c_ell_k = 0, n_lpass = 0, n_upass = 0, pl = 1, pu = 1, u_slot_base = 0, u_row_base = 0;
-  int32_t l_narrow = 0, u_narrow = 0;
+  int32_t l_narrow = 0, u_narrow = 0, c_ell_ld = 0;
   size_t o_pass_code, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col, o_rdv_pos, o_jpos;
   size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
       grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
@@ -234,7 +235,11 @@ size_t layout_workspace(expri_ctx *c) {
   for (auto &I : c->inst) {
     const auto &S = c->pats[I.pat].sym;
     const size_t n = I.n, nd = std::max(I.n_dev, 1);
-    I.ldv = (int64_t)((n + 31) / 32 * 32);
+    // every thread loads E rows of a basis column without a bound test, the
+    // rows past n holding zeros
+    const int bsp = c->pats[I.pat].bs;
+    const size_t rows = std::max(n, (size_t)rows_per_thread((int)n, bsp) * bsp);
+    I.ldv = (int64_t)((rows + 31) / 32 * 32);
     I.xk = take(8 * n); I.x1 = take(8 * n); I.w = take(8 * n); I.p = take(8 * n);
     I.z = take(8 * n); I.tmp = take(8 * n); I.e = take(8 * n); I.Ik = take(8 * n);
     I.devI = take(8 * nd); I.devD = take(24 * nd); I.devI1 = take(8 * nd);
@@ -292,7 +297,7 @@ void fill_descs(expri_ctx *c) {
     d.u_slot_base = P.u_slot_base; d.u_row_base = P.u_row_base;
     d.n_slots = (int32_t)P.slot_pos.size(); d.n_srows = (int32_t)P.row_of.size();
     d.slot_pos = ci(P.o_slot_pos); d.slot_col = ci(P.o_slot_col); d.row_of = ci(P.o_row_of);
-    d.c_ell_col = ci(P.o_c_ell_col); d.c_ell_k = P.c_ell_k;
+    d.c_ell_col = ci(P.o_c_ell_col); d.c_ell_k = P.c_ell_k; d.c_ell_ld = P.c_ell_ld;
     d.c_ell_val = cd(I.c_ell_val);
     d.probe = ci(I.probe);
     d.g_val = cd(I.g_val); d.c_val = cd(I.c_val); d.b_val = cd(I.b_val); d.g_lu = cd(I.g_lu);
@@ -308,6 +313,7 @@ void fill_descs(expri_ctx *c) {
     d.state = reinterpret_cast<InstState *>(c->d_ws + I.state);
     d.trace = wd(I.trace);
     d.trace_cap = c->opts.trace_cap;
+    d.vcols = c->opts.m_max + 1;
     c->h_desc[k] = d;
   }
 }
@@ -322,6 +328,7 @@ expri_status ensure_ws(expri_ctx *c) {
   fill_descs(c);
   HIPCHK(c, hipMemcpyAsync(c->d_desc, c->h_desc.data(), sizeof(InstDesc) * c->h_desc.size(),
                            hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_zero_basis_pad(c->d_desc, (int)c->inst.size(), c->stream));
   return EXPRI_OK;
 }
 
@@ -635,7 +642,9 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     while (P.u_narrow < P.n_upass && (P.pass_code[P.n_lpass + P.u_narrow] >> 16) <= 64) ++P.u_narrow;
     P.pl = P.lsched.empty() ? 1 : P.lsched[0].P;
     P.pu = P.usched.empty() ? 1 : P.usched[0].P;
-    P.c_ell_k = build_c_ell(P.sym, P.c_ell_col);
+    // C's ELL columns padded to E BS rows (see the basis column stride)
+    P.c_ell_ld = std::max(P.sym.n, rows_per_thread(P.sym.n, P.bs) * P.bs);
+    P.c_ell_k = build_c_ell(P.sym, P.c_ell_col, P.c_ell_ld);
     // pivot positions for the U passes' row slots; positions with device terms
     P.rdv_pos.assign(P.row_of.size(), -1);
     for (size_t r = (size_t)P.u_row_base; r < P.row_of.size(); ++r)
@@ -681,9 +690,10 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     I.c_val = pk.add(cperm);
     {
       const PatternDev &PD = c->pats[I.pat];
-      std::vector<double> ell((size_t)std::max(PD.c_ell_k, 1) * K.n, 0.0);
+      std::vector<double> ell((size_t)std::max(PD.c_ell_k, 1) * PD.c_ell_ld, 0.0);
       for (int i = 0; i < K.n; ++i)
-        for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e) ell[(size_t)(e - S.c_rowptr[i]) * K.n + i] = cperm[e];
+        for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e)
+          ell[(size_t)(e - S.c_rowptr[i]) * PD.c_ell_ld + i] = cperm[e];
       I.c_ell_val = pk.add(ell);
     }
     I.b_val = pk.add(gather(K.B.val, S.b_src));
@@ -799,7 +809,11 @@ expri_status expri_bind_workspace(expri_ctx *c, void *dev_ptr, size_t bytes) {
   c->d_ws = static_cast<char *>(dev_ptr);
   c->ws_owned = false;
   fill_descs(c);
-  return upload_descs(c);
+  expri_status s = upload_descs(c);
+  if (s != EXPRI_OK) return s;
+  // the basis columns' padding rows must read as zero
+  HIPCHK(c, launch_zero_basis_pad(c->d_desc, (int)c->inst.size(), c->stream));
+  return EXPRI_OK;
 }
 
 expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {

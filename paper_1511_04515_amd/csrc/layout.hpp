@@ -10,6 +10,12 @@ namespace expri {
 
 constexpr int kMaxKrylov = 60;        // hard upper bound on m
 constexpr int kHLd = kMaxKrylov + 1;  // leading dimension of stored Hessenbergs
+
+// Rows of a length-n vector one thread of a bs-thread workgroup keeps in
+// registers (rows t + e bs, e < E).  The basis columns and C's ELL columns
+// are padded with zeros to E bs rows so that these rows load without a
+// bound test.  n <= 9 bs.
+constexpr int rows_per_thread(int n, int bs) { return n <= 4 * bs ? 4 : n <= 6 * bs ? 6 : 9; }
 constexpr int kRecFixed = 16;         // fixed doubles per trace record (8 + 8 step features)
 constexpr int kFeat = 8;              // step features seen by the learned controller
 constexpr int kPhases = 6;            // profiled phases of a step
@@ -98,9 +104,10 @@ struct InstDesc {
   int32_t n_lpass, n_upass, pl, pu;   // passes and slots per lane of L and U
   int32_t u_slot_base, u_row_base;    // where the U passes start
   int32_t n_slots, n_srows;           // sizes of slot_pos / row_of
-  // C in ELL layout: entry k of row i at k * n + i (column -1 = padding)
+  // C in ELL layout: entry k of row i at k * c_ell_ld + i (column -1 and
+  // value 0 on padding, rows n .. c_ell_ld - 1 included)
   const int32_t *c_ell_col;
-  int32_t c_ell_k, pad4;
+  int32_t c_ell_k, c_ell_ld;
   const int32_t *perm;          // perm[internal] = caller's node id
   const int32_t *probe;         // internal ids of the probed nodes
 
@@ -123,11 +130,11 @@ struct InstDesc {
   double *V, *Ve;               // Krylov bases, n x (m_max + 1), column j at j * ldv
   double *H, *He;               // Hessenbergs, kHLd x kMaxKrylov column-major
   double *mat;                  // small dense matrices when they do not fit in LDS
-  int64_t ldv;                  // column stride of V / Ve (>= n, multiple of 32)
+  int64_t ldv;                  // column stride of V / Ve (>= E BS, multiple of 32; rows n.. are 0)
   InstState *state;
   double *trace;                // records of kRecFixed + n_probe doubles
   int32_t trace_cap;            // records available
-  int32_t pad3;
+  int32_t vcols;                // columns of V and of Ve (m_max + 1)
 };
 
 }  // namespace expri

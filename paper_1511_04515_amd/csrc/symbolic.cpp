@@ -594,14 +594,16 @@ std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched, int bs) {
   return out;
 }
 
-// ELL layout of C's pattern: entry k of row i at k * n + i; returns K.
-int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col) {
+// ELL layout of C's pattern: entry k of row i at k * ld + i (ld >= n, or n
+// when ld is 0; -1 on padding); returns K.
+int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col, int ld) {
   const int n = S.n;
+  if (ld < n) ld = n;
   int K = 0;
   for (int i = 0; i < n; ++i) K = std::max(K, S.c_rowptr[i + 1] - S.c_rowptr[i]);
-  col.assign((size_t)std::max(K, 1) * n, -1);
+  col.assign((size_t)std::max(K, 1) * ld, -1);
   for (int i = 0; i < n; ++i)
-    for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e) col[(size_t)(e - S.c_rowptr[i]) * n + i] = S.c_col[e];
+    for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e) col[(size_t)(e - S.c_rowptr[i]) * ld + i] = S.c_col[e];
   return K;
 }
 

@@ -88,9 +88,9 @@ bool build_solve_schedule(const Symbolic &S, int bs, bool lower, std::vector<Sol
 // where lanes t < active hold the pass's rows (rows in the pass times G).
 std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched, int bs);
 
-// ELL layout of C's (permuted) pattern: entry k of row i at k * n + i, -1 =
-// padding; returns the ELL width.
-int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col);
+// ELL layout of C's (permuted) pattern: entry k of row i at k * ld + i
+// (ld = n when 0), -1 = padding; returns the ELL width.
+int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col, int ld = 0);
 
 // Fill-reducing order of a symmetric graph (adjacency without self loops) by
 // recursive BFS-level bisection (nested dissection).  Exposed for tests.
