@@ -295,10 +295,12 @@ __device__ __forceinline__ void assemble(const InstDesc &D, bool dc_block) {
   const GMEM double *__restrict__ glu = gbl(D.g_lu);
   GMEM double *__restrict__ lu = gbl(D.lu);
   const int nz = D.nnz_lu;
+  // loads at clamped indices, unconditionally: a branch around each load
+  // would make the compiler wait for every load in flight at each join
   for (int p0 = tid(); p0 < nz; p0 += 8 * BS) {
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = p0 + u * BS < nz ? glu[p0 + u * BS] : 0.0;
+    for (int u = 0; u < 8; ++u) v[u] = glu[min(p0 + u * BS, nz - 1)];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (p0 + u * BS < nz) lu[p0 + u * BS] = v[u];
@@ -340,23 +342,30 @@ __device__ __forceinline__ void pack_slots(const InstDesc &D) {
   GMEM double *__restrict__ sv = gbl(D.sval);
   const GMEM int *__restrict__ dpos = gbl(D.rdv_pos);
   GMEM double *__restrict__ rdv = gbl(D.rdv);
+  // indices clamped and loads unconditional (see assemble)
   const int ns = D.n_slots;
   for (int k0 = tid(); k0 < ns; k0 += 8 * BS) {
     int p[8];
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = k0 + u * BS < ns ? spos[k0 + u * BS] : -1;
+    for (int u = 0; u < 8; ++u) p[u] = spos[min(k0 + u * BS, ns - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a[max(p[u], 0)];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (k0 + u * BS < ns) sv[k0 + u * BS] = p[u] >= 0 ? a[p[u]] : 0.0;
+      if (k0 + u * BS < ns) sv[k0 + u * BS] = p[u] >= 0 ? v[u] : 0.0;
   }
   const int r1 = D.n_srows;
   for (int r0 = D.u_row_base + tid(); r0 < r1; r0 += 8 * BS) {
     int p[8];
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = r0 + u * BS < r1 ? dpos[r0 + u * BS] : -1;
+    for (int u = 0; u < 8; ++u) p[u] = dpos[min(r0 + u * BS, r1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a[max(p[u], 0)];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r0 + u * BS < r1) rdv[r0 + u * BS] = p[u] >= 0 ? 1.0 / a[p[u]] : 1.0;
+      if (r0 + u * BS < r1) rdv[r0 + u * BS] = p[u] >= 0 ? 1.0 / v[u] : 1.0;
   }
   __syncthreads();
 }
@@ -425,6 +434,12 @@ __device__ __forceinline__ void refactor_row_wave(GMEM double *a, const GMEM int
   if (lane == 0 && !(fabs(rb[diag_i - rs]) > piv_tol * rmx)) bad = 1;
 }
 
+// Levels of at most this many rows per wave run one row per wave (the
+// separators near the root, where the rows are long and the group chains
+// deep); wider levels run one row per thread.  (16 rows per wave measured
+// slower on the chains than 4.)
+constexpr int kWaveRowLevels = 4;
+
 template <int BS>
 __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
   GMEM double *a = gbl(D.lu);
@@ -439,7 +454,7 @@ __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double p
   int bad = 0;
   for (int lv = 0; lv < D.n_lev; ++lv) {
     const int q0 = lev_ptr[lv], q1 = lev_ptr[lv + 1];
-    if (wave_rows_fit && q1 - q0 <= 4 * NW) {
+    if (wave_rows_fit && q1 - q0 <= kWaveRowLevels * NW) {
       for (int q = q0 + wave; q < q1; q += NW) {
         const int i = lev_rows[q];
         refactor_row_wave<BS>(a, rowptr, row_grp, grp_pos, grp_diag, grp_ptr, pair_dst, pair_src, i, diag[i],
@@ -961,8 +976,9 @@ __device__ __forceinline__ void arnoldi_step_e(const InstDesc &D, Lds<BS> &L, do
     double part = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) part += w[e] * cur[e];
-    if (i < j) {
-      const GMEM double *vn = Vg + (int64_t)(i + 1) * ldv + t0;
+    {
+      // v_{i+1} (v_j again after the last product: no branch around the loads)
+      const GMEM double *vn = Vg + (int64_t)(i < j ? i + 1 : j) * ldv + t0;
 #pragma unroll
       for (int e = 0; e < E; ++e) nxt[e] = vn[e * BS];
     }
