@@ -1192,6 +1192,7 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
     S.err_prev = 0.0;
     S.m_prev = 0;
     S.rej_prev = 0;
+    S.m_err_prev = 0;
     int b = 0;
     while (b < D.n_bp - 1 && gbl(D.bp)[b] <= t0) ++b;
     S.bp_idx = b;
@@ -1233,7 +1234,7 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
   int lu_count = S.lu_count, rej_total = S.rejects, iters = S.arnoldi;
   int lu_valid = S.lu_valid;
   double h_prev = S.h_prev, rho_prev = S.rho_prev, err_prev = S.err_prev;
-  int m_prev = S.m_prev, rej_prev = S.rej_prev;
+  int m_prev = S.m_prev, rej_prev = S.rej_prev, m_err_prev = S.m_err_prev;
   const bool learned = o.controller && !replay;
   const int steps0 = steps;
   const int rec = kRecFixed + D.n_probe;
@@ -1431,8 +1432,10 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
         basis_start<BS>(D, L, xs, D.Ve, Be);
         pf.mark(5);
         double rho_e;
-        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk, 1,
-                                   o.erc ? L.derr2 : nullptr);
+        // under the learned controller the residual tests of the error MEVP
+        // start two sizes below the previous step's (every size otherwise)
+        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk,
+                                   learned ? max(1, m_err_prev - 2) : 1, o.erc ? L.derr2 : nullptr);
         if (status == kEKRYLOV && learned && !fell_back) {
           fell_back = true;
           double hp = fmin(h_prop, D.h_max);
@@ -1493,6 +1496,7 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
     err_prev = err;
     m_prev = Bm.m;
     rej_prev = rej;
+    m_err_prev = m_err;
   }
   if (tid() == 0) {
     S.t = t;
@@ -1508,6 +1512,7 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
     S.err_prev = err_prev;
     S.m_prev = m_prev;
     S.rej_prev = rej_prev;
+    S.m_err_prev = m_err_prev;
     S.trials += wk.trials;
     S.mgs_terms += wk.mgs;
     S.comb_terms += wk.comb;

@@ -54,7 +54,7 @@ struct InstState {
   int32_t arnoldi;    // total Arnoldi iterations
   int32_t lu_valid;   // factors of G_k are current (linear circuits keep them)
   int32_t trials;     // step trials (accepted + rejected)
-  int32_t pad1;
+  int32_t m_err_prev; // Krylov size of the previous accepted step's error MEVP
   int64_t mgs_terms;  // inner products of modified Gram-Schmidt (sum of j+1)
   int64_t comb_terms; // basis columns combined into x_{k+1} and e_rr
   // wall-clock ticks per phase: factor, rhs, arnoldi solve, mgs, phi, trial
@@ -126,7 +126,7 @@ struct InstDesc {
   double *Ik;                   // node currents at x_k
   double *lu;                   // L\U values
   double *sval;                 // L\U values in solve-slot order (0 on padding)
-  double *rdv;                  // u_ii per row slot (1 where the slot has no row)
+  double *rdv;                  // 1 / u_ii per U row slot (1 where the slot has no row)
   double *V, *Ve;               // Krylov bases, n x (m_max + 1), column j at j * ldv
   double *H, *He;               // Hessenbergs, kHLd x kMaxKrylov column-major
   double *mat;                  // small dense matrices when they do not fit in LDS
