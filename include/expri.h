@@ -167,10 +167,10 @@ expri_status expri_default_opts(expri_opts *o);
 /* Analyse and upload n_inst circuits (host data, copied).  Builds the
  * symbolic analysis of G_k's pattern (fill-reducing order, L\U pattern, level
  * schedules, refactor update lists, stamp maps) once per distinct pattern.
- * Each instance runs in one workgroup whose block size is the smallest of
- * 256 / 512 / 1024 with n <= 2048 / 4608 / 9216 (or opts.block_size, which
- * must then satisfy n <= 9 block_size for every instance); instances of one
- * block size form a launch class.
+ * Each instance runs in one workgroup of 256 threads when n <= 2048, 512
+ * when n <= 6144 and 1024 up to n = 9216 (or opts.block_size, which must
+ * then satisfy n <= 12 x 512 at 512 threads and n <= 9 block_size
+ * otherwise); instances of one block size form a launch class.
  * hip_stream: the hipStream_t all work is queued on (NULL = default stream).
  * EINVAL for malformed input; ENOMEM / EHIP on allocation failure. */
 expri_status expri_setup(expri_ctx **ctx, const expri_circuit *ckt, int32_t n_inst,

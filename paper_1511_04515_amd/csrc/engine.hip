@@ -1083,14 +1083,16 @@ __device__ __forceinline__ double combine_err(const InstDesc &D, const double *d
   return emax;
 }
 
-// rows per thread: rows_per_thread(n, BS) = 4, 6 or 9 (set-up keeps n <= 9 BS)
+// rows per thread: rows_per_thread(n, BS) = 4, 6, 9 or (512 threads) 12;
+// set-up keeps n <= max_rows_per_thread(BS) BS
 template <int BS>
 __device__ __forceinline__ void arnoldi_step(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
                              double breakdown, Prof &pf) {
   const int e = rows_per_thread(D.n, BS);
   if (e == 4) arnoldi_step_e<BS, 4>(D, L, V, H, B, breakdown, pf);
   else if (e == 6) arnoldi_step_e<BS, 6>(D, L, V, H, B, breakdown, pf);
-  else arnoldi_step_e<BS, 9>(D, L, V, H, B, breakdown, pf);
+  else if (BS != 512 || e == 9) arnoldi_step_e<BS, 9>(D, L, V, H, B, breakdown, pf);
+  else arnoldi_step_e<BS, (BS == 512 ? 12 : 9)>(D, L, V, H, B, breakdown, pf);
 }
 
 // Start a basis from the vector v (global or the LDS vector area):
@@ -1404,7 +1406,8 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
       const int rpt = rows_per_thread(n, BS);
       const double bad = rpt == 4   ? combine_main<BS, 4>(D, L.dmain, Bm.m, Bm.beta, h)
                          : rpt == 6 ? combine_main<BS, 6>(D, L.dmain, Bm.m, Bm.beta, h)
-                                    : combine_main<BS, 9>(D, L.dmain, Bm.m, Bm.beta, h);
+                         : rpt == 9 ? combine_main<BS, 9>(D, L.dmain, Bm.m, Bm.beta, h)
+                                    : combine_main<BS, (BS == 512 ? 12 : 9)>(D, L.dmain, Bm.m, Bm.beta, h);
       if (wg_max(L, bad) != 0.0) { status = kENONFINITE; break; }
       err = 0.0;
       m_err = 0;
@@ -1456,10 +1459,12 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
         wk.comb += Be.m;
         // ER-C: x_{k+1} -= gamma h phi_2(hJ) C^{-1} dF = gamma beta_e V_e d2
         const int rpe = rows_per_thread(n, BS);
+        constexpr int E12 = BS == 512 ? 12 : 9;
         const double emax =
             rpe == 4   ? combine_err<BS, 4>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
             : rpe == 6 ? combine_err<BS, 6>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
-                       : combine_err<BS, 9>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0);
+            : rpe == 9 ? combine_err<BS, 9>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+                       : combine_err<BS, E12>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0);
         if (o.erc) wk.comb += Be.m;
         err = wg_max(L, emax);
       }

@@ -572,14 +572,16 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   int wall_khz = 0;
   if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
     c->wall_hz = 1e3 * wall_khz;
-  // ---- launch classes.  A thread keeps at most 9 rows of a vector in
-  // registers (n <= 9 bs): a pattern takes the smallest block size of 256,
-  // 512, 1024 that holds it (or the one the options force), and the
-  // instances of one block size form a launch class ----
+  // ---- launch classes.  A thread keeps at most max_rows_per_thread(bs)
+  // rows of a vector in registers (12 at 512 threads, 9 otherwise): a
+  // pattern takes 256 threads up to n = 2048, 512 up to 12 x 512 = 6144 and
+  // 1024 beyond (or the block size the options force), and the instances of
+  // one block size form a launch class ----
   (void)n_max;
   for (auto &P : c->pats) {
-    P.bs = op.block_size ? op.block_size : (P.sym.n <= 2048 ? 256 : P.sym.n <= 9 * 512 ? 512 : 1024);
-    if (P.sym.n > 9 * P.bs) {
+    P.bs = op.block_size ? op.block_size
+                         : (P.sym.n <= 2048 ? 256 : P.sym.n <= max_rows_per_thread(512) * 512 ? 512 : 1024);
+    if (P.sym.n > max_rows_per_thread(P.bs) * P.bs) {
       *out = c.release();
       (*out)->err = "block size " + std::to_string(P.bs) + " too small for n = " + std::to_string(P.sym.n);
       return EXPRI_EINVAL;

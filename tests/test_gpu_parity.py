@@ -220,10 +220,10 @@ def test_batch_matches_single_instance_runs():
 
 
 def test_mixed_size_batch_runs_as_concurrent_classes_and_matches_single_runs():
-    # chains of 841, 2521 and 4831 nodes take block sizes 256, 512 and 1024:
+    # chains of 841, 2521 and 6301 nodes take block sizes 256, 512 and 1024:
     # three launch classes, the transient kernels concurrent on three streams
     nets = [netgen.inverter_chain(seed=40 + i, n_stages=L, T=0.3e-9, t_ramp=0.1e-9)
-            for i, L in enumerate((230, 40, 120, 40, 230))]
+            for i, L in enumerate((300, 40, 120, 40, 300))]
     sb = Solver(nets)
     classes, ic = sb.classes()
     assert [c["block_size"] for c in classes] == [1024, 512, 256]
