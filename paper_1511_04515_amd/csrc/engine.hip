@@ -436,10 +436,10 @@ __device__ __forceinline__ void refactor_row_wave(GMEM double *a, const GMEM int
 
 // Levels of at most this many rows per wave run one row per wave (the
 // separators near the root, where the rows are long and the group chains
-// deep); wider levels run one row per thread.  (16 rows per wave measured
-// slower on the chains than 4.)
+// deep); wider levels run one row per thread.  (16 rows per wave, and groups
+// of 2 to 8 lanes per row for the wider levels, measured slower on the
+// chains.)
 constexpr int kWaveRowLevels = 4;
-
 template <int BS>
 __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
   GMEM double *a = gbl(D.lu);
@@ -1753,6 +1753,14 @@ __global__ void __launch_bounds__(BS) k_diag(const InstDesc *descs, int what, in
       assemble<BS>(D, false);
       __syncthreads();
       acc += refactor<BS>(D, L, 0.0) ? 1.0 : 0.0;
+    } else if (what == 8) {
+      assemble<BS>(D, false);
+      __syncthreads();
+    } else if (what == 9) {
+      pack_slots<BS>(D);
+    } else if (what == 10) {
+      stamp_devices<BS>(D, D.xk, D.devI, D.devD);
+      __syncthreads();
     }
   }
   const long long t1 = wall_clock64();
