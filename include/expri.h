@@ -257,7 +257,8 @@ expri_status expri_launch_classes(const expri_ctx *ctx, int32_t cap, int32_t *bl
  * reduction, 5 one barrier per solve pass and nothing else, 6 the Hessenberg
  * exponential and residual for m = arg on a synthetic H, 7 assembly and
  * refactor of G_k (with the slot repacking) at the last stamp, 8 the
- * assembly alone, 9 the slot repacking alone, 10 the device stamp alone.  It overwrites
+ * assembly alone, 9 the slot repacking alone, 10 the device stamp alone,
+ * 11 the first arg levels of the refactor and the repacking.  It overwrites
  * instance 0's basis, Hessenbergs and solve vector with synthetic data.
  * EXPRI_EINVAL unless 0 <= arg < m_max (and arg >= 1 for what = 6). */
 expri_status expri_diag_time(expri_ctx *ctx, int32_t what, int32_t reps, int32_t arg, double *seconds);

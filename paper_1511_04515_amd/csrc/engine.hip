@@ -441,7 +441,7 @@ __device__ __forceinline__ void refactor_row_wave(GMEM double *a, const GMEM int
 // chains.)
 constexpr int kWaveRowLevels = 4;
 template <int BS>
-__device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol) {
+__device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double piv_tol, int max_levels = 1 << 30) {
   GMEM double *a = gbl(D.lu);
   const GMEM int *lev_ptr = gbl(D.lev_ptr), *lev_rows = gbl(D.lev_rows), *rowptr = gbl(D.lu_rowptr);
   const GMEM int *row_grp = gbl(D.row_grp), *grp_pos = gbl(D.grp_pos), *grp_diag = gbl(D.grp_diag);
@@ -452,7 +452,7 @@ __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double p
   // per-wave row buffers in the LDS vector area (free while G_k is refactored)
   const bool wave_rows_fit = NW * D.max_row <= L.R;
   int bad = 0;
-  for (int lv = 0; lv < D.n_lev; ++lv) {
+  for (int lv = 0; lv < min(D.n_lev, max_levels); ++lv) {
     const int q0 = lev_ptr[lv], q1 = lev_ptr[lv + 1];
     if (wave_rows_fit && q1 - q0 <= kWaveRowLevels * NW) {
       for (int q = q0 + wave; q < q1; q += NW) {
@@ -463,13 +463,38 @@ __device__ __forceinline__ bool refactor(const InstDesc &D, Lds<BS> &L, double p
     } else {
       for (int q = q0 + t; q < q1; q += BS) {
         const int i = lev_rows[q];
+        const int r0 = rowptr[i], r1 = rowptr[i + 1];
         double rmax = 0.0;
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) rmax = fmax(rmax, fabs(a[p]));
+        for (int p = r0; p < r1; p += 8) {  // eight loads in flight at clamped indices
+          double v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = a[min(p + k, r1 - 1)];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) rmax = fmax(rmax, fabs(v[k]));
+        }
         for (int g = row_grp[i]; g < row_grp[i + 1]; ++g) {
           const int pik = grp_pos[g];
+          const int u0 = grp_ptr[g], u1 = grp_ptr[g + 1];
           const double l = a[pik] / a[grp_diag[g]];
           a[pik] = l;
-          for (int u = grp_ptr[g]; u < grp_ptr[g + 1]; ++u) a[pair_dst[u]] -= l * a[pair_src[u]];
+          // a group's pairs have distinct targets in row i and sources in
+          // the (final) pivot row: four at a time, their loads issued
+          // together at clamped indices
+          for (int u = u0; u < u1; u += 4) {
+            int dd[4];
+            double dv[4], sv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int uu = min(u + k, u1 - 1);
+              dd[k] = pair_dst[uu];
+              sv[k] = a[pair_src[uu]];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dv[k] = a[dd[k]];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (u + k < u1) a[dd[k]] = dv[k] - l * sv[k];
+          }
         }
         const double dii = a[diag[i]];
         if (!(fabs(dii) > piv_tol * rmax)) bad = 1;
@@ -1761,6 +1786,8 @@ __global__ void __launch_bounds__(BS) k_diag(const InstDesc *descs, int what, in
     } else if (what == 10) {
       stamp_devices<BS>(D, D.xk, D.devI, D.devD);
       __syncthreads();
+    } else if (what == 11) {
+      acc += refactor<BS>(D, L, 0.0, arg) ? 1.0 : 0.0;  // the first arg levels, then the repacking
     }
   }
   const long long t1 = wall_clock64();

@@ -1001,7 +1001,7 @@ expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
 }
 
 expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, int32_t arg, double *seconds) {
-  if (!c || !seconds || what < 0 || what > 10 || reps < 1) return EXPRI_EINVAL;
+  if (!c || !seconds || what < 0 || what > 11 || reps < 1) return EXPRI_EINVAL;
   if (arg < 0 || arg > c->opts.m_max - 1 || (what == 6 && arg < 1)) return EXPRI_EINVAL;
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
