@@ -182,8 +182,9 @@ expri_status expri_workspace_size(const expri_ctx *ctx, size_t *bytes);
 /* Give the context a caller-owned device workspace of at least
  * expri_workspace_size bytes (must outlive the context's use).  Without it
  * the first compute call allocates one.  Queues a kernel on the context's
- * stream that zeroes the padding rows of the Krylov basis storage (the
- * caller need not clear the workspace).  EINVAL if too small or misaligned. */
+ * stream that initialises the entries the kernels read but never write (the
+ * padding rows of the Krylov basis storage, the empty solve slots), so the
+ * caller need not clear the workspace.  EINVAL if too small or misaligned. */
 expri_status expri_bind_workspace(expri_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* DC operating point at time t0 (Algorithm 2, x(0) = DC_solution): x[i]

@@ -333,39 +333,49 @@ __device__ __forceinline__ void assemble(const InstDesc &D, bool dc_block) {
 // Slot-ordered copy of the factors for the solves: sval[k] is the L\U value
 // of slot k of the flattened schedules (0 on padding) and rdv[r] the
 // reciprocal 1 / u_ii of the pivot of the row in row slot r of the U passes
-// (1 where the slot holds no row), so that the U passes multiply.  A solve pass then reads its operands with coalesced loads that
-// depend on nothing the solve computes, so they can be issued a pass ahead.
+// (1 where the slot holds no row), so that the U passes multiply.  A solve
+// pass then reads its operands with coalesced loads that depend on nothing
+// the solve computes, so they can be issued a pass ahead.
 template <int BS>
 __device__ __forceinline__ void pack_slots(const InstDesc &D) {
   const GMEM double *__restrict__ a = gbl(D.lu);
-  const GMEM int *__restrict__ spos = gbl(D.slot_pos);
   GMEM double *__restrict__ sv = gbl(D.sval);
-  const GMEM int *__restrict__ dpos = gbl(D.rdv_pos);
   GMEM double *__restrict__ rdv = gbl(D.rdv);
-  // indices clamped and loads unconditional (see assemble)
-  const int ns = D.n_slots;
-  for (int k0 = tid(); k0 < ns; k0 += 8 * BS) {
-    int p[8];
+  // only the slots that hold an entry (the others keep their 0), eight at a
+  // time with their loads issued together at clamped indices
+  const GMEM int *__restrict__ ks = gbl(D.pk_slot), *__restrict__ kp = gbl(D.pk_pos);
+  const int np = D.n_pk;
+  for (int k0 = tid(); k0 < np; k0 += 8 * BS) {
+    int s8[8], p8[8];
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = spos[min(k0 + u * BS, ns - 1)];
+    for (int u = 0; u < 8; ++u) {
+      const int k = min(k0 + u * BS, np - 1);
+      s8[u] = ks[k];
+      p8[u] = kp[k];
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = a[max(p[u], 0)];
+    for (int u = 0; u < 8; ++u) v[u] = a[p8[u]];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (k0 + u * BS < ns) sv[k0 + u * BS] = p[u] >= 0 ? v[u] : 0.0;
+      if (k0 + u * BS < np) sv[s8[u]] = v[u];
   }
-  const int r1 = D.n_srows;
-  for (int r0 = D.u_row_base + tid(); r0 < r1; r0 += 8 * BS) {
-    int p[8];
+  const GMEM int *__restrict__ rs = gbl(D.rd_slot), *__restrict__ rp = gbl(D.rd_pos);
+  const int nr = D.n_rd;
+  for (int k0 = tid(); k0 < nr; k0 += 8 * BS) {
+    int s8[8], p8[8];
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = dpos[min(r0 + u * BS, r1 - 1)];
+    for (int u = 0; u < 8; ++u) {
+      const int k = min(k0 + u * BS, nr - 1);
+      s8[u] = rs[k];
+      p8[u] = rp[k];
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = a[max(p[u], 0)];
+    for (int u = 0; u < 8; ++u) v[u] = a[p8[u]];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r0 + u * BS < r1) rdv[r0 + u * BS] = p[u] >= 0 ? 1.0 / v[u] : 1.0;
+      if (k0 + u * BS < nr) rdv[s8[u]] = 1.0 / v[u];
   }
   __syncthreads();
 }
@@ -1226,9 +1236,10 @@ __global__ void k_begin(const InstDesc *descs, const double *const *xin, double 
   }
 }
 
-// Zero the padding rows n .. ldv - 1 of every column of V and V_e (the
-// kernels load them unconditionally and never write them).
-__global__ void k_zero_basis_pad(const InstDesc *descs) {
+// Workspace entries that the kernels read but never write: the padding rows
+// n .. ldv - 1 of every column of V and V_e (0), the solve slots without an
+// entry (0) and the U row slots without a row (pivot 1).
+__global__ void k_init_workspace(const InstDesc *descs) {
   const InstDesc &D = descs[blockIdx.x];
   const int pad = (int)D.ldv - D.n;
   for (int idx = tid(); idx < pad * D.vcols; idx += blockDim.x) {
@@ -1236,6 +1247,8 @@ __global__ void k_zero_basis_pad(const InstDesc *descs) {
     gbl(D.V)[o] = 0.0;
     gbl(D.Ve)[o] = 0.0;
   }
+  for (int k = tid(); k < D.n_slots; k += blockDim.x) gbl(D.sval)[k] = 0.0;
+  for (int r = tid(); r < D.n_srows; r += blockDim.x) gbl(D.rdv)[r] = 1.0;
 }
 
 // Write x_k back in the caller's numbering.
@@ -1812,8 +1825,8 @@ hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin,
   return hipGetLastError();
 }
 
-hipError_t launch_zero_basis_pad(const InstDesc *d, int n_inst, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_basis_pad, dim3(n_inst), dim3(256), 0, s, d);
+hipError_t launch_init_workspace(const InstDesc *d, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_workspace, dim3(n_inst), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

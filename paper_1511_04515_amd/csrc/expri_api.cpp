@@ -26,7 +26,7 @@ hipError_t set_lds_limits(size_t bytes);
 hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin, double t0, double h0,
                         hipStream_t s);
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
-hipError_t launch_zero_basis_pad(const InstDesc *d, int n_inst, hipStream_t s);
+hipError_t launch_init_workspace(const InstDesc *d, int n_inst, hipStream_t s);
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, int grid, int *next, const Opts &o,
                       int max_steps, int replay, int bs, int R, int NX, hipStream_t s);
 hipError_t launch_zero_counters(int *next, int n, hipStream_t s);
@@ -72,9 +72,11 @@ struct PatternDev {
   // flattened solve schedules and C ELL pattern (depend on the block size)
   std::vector<SolveLevel> lsched, usched;
   std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code, rdv_pos, jpos;
+  std::vector<int32_t> pk_slot, pk_pos, rd_slot, rd_pos;  // repacking work lists
   int32_t c_ell_k = 0, n_lpass = 0, n_upass = 0, pl = 1, pu = 1, u_slot_base = 0, u_row_base = 0;
   int32_t l_narrow = 0, u_narrow = 0, c_ell_ld = 0;
   size_t o_pass_code, o_slot_pos, o_slot_col, o_row_of, o_c_ell_col, o_rdv_pos, o_jpos;
+  size_t o_pk_slot, o_pk_pos, o_rd_slot, o_rd_pos;
   size_t lu_rowptr, lu_col, lu_diag, lev_ptr, lev_rows, ulev_ptr, ulev_rows, row_grp, grp_pos,
       grp_diag, grp_ptr, pair_src, pair_dst, lu_gidx, jac_ptr, jac_code, node_ptr, node_code,
       g_rowptr, g_col, c_rowptr, c_col, b_rowptr, b_col, dev_node, perm;
@@ -302,6 +304,8 @@ void fill_descs(expri_ctx *c) {
     d.probe = ci(I.probe);
     d.g_val = cd(I.g_val); d.c_val = cd(I.c_val); d.b_val = cd(I.b_val); d.g_lu = cd(I.g_lu);
     d.rdv_pos = ci(P.o_rdv_pos); d.jpos = ci(P.o_jpos); d.n_jpos = (int32_t)P.jpos.size();
+    d.pk_slot = ci(P.o_pk_slot); d.pk_pos = ci(P.o_pk_pos); d.n_pk = (int32_t)P.pk_slot.size();
+    d.rd_slot = ci(P.o_rd_slot); d.rd_pos = ci(P.o_rd_pos); d.n_rd = (int32_t)P.rd_slot.size();
     d.dev_par = cd(I.dev_par); d.src_ptr = ci(I.src_ptr); d.src_t = cd(I.src_t);
     d.src_v = cd(I.src_v); d.bp = cd(I.bp);
     d.xk = wd(I.xk); d.x1 = wd(I.x1); d.w = wd(I.w); d.p = wd(I.p); d.z = wd(I.z);
@@ -328,7 +332,7 @@ expri_status ensure_ws(expri_ctx *c) {
   fill_descs(c);
   HIPCHK(c, hipMemcpyAsync(c->d_desc, c->h_desc.data(), sizeof(InstDesc) * c->h_desc.size(),
                            hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, launch_zero_basis_pad(c->d_desc, (int)c->inst.size(), c->stream));
+  HIPCHK(c, launch_init_workspace(c->d_desc, (int)c->inst.size(), c->stream));
   return EXPRI_OK;
 }
 
@@ -514,7 +518,6 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   }
   expri_status s;
   std::map<uint64_t, int> by_hash;
-  int n_max = 0;
   for (int k = 0; k < n_inst; ++k) {
     if ((s = validate_circuit(c.get(), ckt[k], k)) != EXPRI_OK) {
       *out = c.release();
@@ -560,7 +563,6 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     I.T = K.T;
     I.h_max = op.h_max > 0 ? op.h_max : K.T / 20;
     c->inst.push_back(std::move(I));
-    n_max = std::max(n_max, K.n);
   }
 
   // ---- launch shape ----
@@ -577,7 +579,6 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   // pattern takes 256 threads up to n = 2048, 512 up to 12 x 512 = 6144 and
   // 1024 beyond (or the block size the options force), and the instances of
   // one block size form a launch class ----
-  (void)n_max;
   for (auto &P : c->pats) {
     P.bs = op.block_size ? op.block_size
                          : (P.sym.n <= 2048 ? 256 : P.sym.n <= max_rows_per_thread(512) * 512 ? 512 : 1024);
@@ -651,6 +652,11 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.rdv_pos.assign(P.row_of.size(), -1);
     for (size_t r = (size_t)P.u_row_base; r < P.row_of.size(); ++r)
       if (P.row_of[r] >= 0) P.rdv_pos[r] = P.sym.lu_diag[P.row_of[r]];
+    P.pk_slot.clear(); P.pk_pos.clear(); P.rd_slot.clear(); P.rd_pos.clear();
+    for (size_t k = 0; k < P.slot_pos.size(); ++k)
+      if (P.slot_pos[k] >= 0) { P.pk_slot.push_back((int32_t)k); P.pk_pos.push_back(P.slot_pos[k]); }
+    for (size_t r = 0; r < P.rdv_pos.size(); ++r)
+      if (P.rdv_pos[r] >= 0) { P.rd_slot.push_back((int32_t)r); P.rd_pos.push_back(P.rdv_pos[r]); }
     P.jpos.clear();
     for (size_t p = 0; p + 1 < P.sym.jac_ptr.size(); ++p)
       if (P.sym.jac_ptr[p + 1] > P.sym.jac_ptr[p]) P.jpos.push_back((int32_t)p);
@@ -672,6 +678,8 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.dev_node = pk.add(S.dev_node); P.perm = pk.add(S.perm);
     P.o_pass_code = pk.add(P.pass_code);
     P.o_rdv_pos = pk.add(P.rdv_pos);
+    P.o_pk_slot = pk.add(P.pk_slot); P.o_pk_pos = pk.add(P.pk_pos);
+    P.o_rd_slot = pk.add(P.rd_slot); P.o_rd_pos = pk.add(P.rd_pos);
     P.o_jpos = pk.add(P.jpos);
     P.o_slot_pos = pk.add(P.slot_pos); P.o_slot_col = pk.add(P.slot_col); P.o_row_of = pk.add(P.row_of);
     P.o_c_ell_col = pk.add(P.c_ell_col);
@@ -813,8 +821,8 @@ expri_status expri_bind_workspace(expri_ctx *c, void *dev_ptr, size_t bytes) {
   fill_descs(c);
   expri_status s = upload_descs(c);
   if (s != EXPRI_OK) return s;
-  // the basis columns' padding rows must read as zero
-  HIPCHK(c, launch_zero_basis_pad(c->d_desc, (int)c->inst.size(), c->stream));
+  // entries read but never written (basis padding, empty solve slots)
+  HIPCHK(c, launch_init_workspace(c->d_desc, (int)c->inst.size(), c->stream));
   return EXPRI_OK;
 }
 

@@ -103,6 +103,11 @@ struct InstDesc {
   const int32_t *pass_code;
   const int32_t *slot_pos, *slot_col, *row_of;
   const int32_t *rdv_pos;             // per row slot of the U passes: position of u_ii (-1: none)
+  // the repacking's work lists: slots holding an entry (slot, L\U position)
+  // and U row slots holding a row (row slot, position of u_ii); every other
+  // slot keeps the 0 (value) or 1 (pivot) written when the workspace is bound
+  const int32_t *pk_slot, *pk_pos, *rd_slot, *rd_pos;
+  int32_t n_pk, n_rd;
   const int32_t *jpos;                // L\U positions that receive device derivatives
   int32_t n_jpos, pad5;
   int32_t n_lpass, n_upass, pl, pu;   // passes and slots per lane of L and U
