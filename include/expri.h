@@ -176,6 +176,21 @@ expri_status expri_default_opts(expri_opts *o);
 expri_status expri_setup(expri_ctx **ctx, const expri_circuit *ckt, int32_t n_inst,
                          const expri_opts *o, void *hip_stream);
 
+/* Replace the values of instance `inst` (0 <= inst < n_inst) by those of
+ * *ckt, keeping its symbolic analysis: the circuit data of the system
+ * C x' = -G x + F(x) + B u (Section 3) for one more point of a sweep over
+ * one topology.  *ckt must have the instance's sparsity pattern (n, G, C and
+ * B patterns, device terminals, number of sources), its number of probes and
+ * its total number of PWL corners; every value may change: G, C, B, the
+ * device parameters, the PWL corners (times and values), vdd and T.  Host
+ * arrays are copied before the call returns.  Waits for the context's
+ * streams, so no kernel of the context reads the old values.  Every later
+ * run, step and DC call factorises afresh; expri_solve and expri_mevp
+ * return EINVAL until expri_factor runs again.  EPATTERN if the pattern
+ * differs, EINVAL for other mismatches or malformed values (the instance
+ * keeps its old values then). */
+expri_status expri_set_values(expri_ctx *ctx, int32_t inst, const expri_circuit *ckt);
+
 /* Device workspace the context needs (bytes, 256-byte aligned use). */
 expri_status expri_workspace_size(const expri_ctx *ctx, size_t *bytes);
 

@@ -24,7 +24,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -
           -6: "ENONFINITE", -7: "EHIP", -8: "EPATTERN", -9: "ENOCONV"}
 
 # the names every C-ABI entry point of include/expri.h exports
-ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_workspace_size", "expri_bind_workspace",
+ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_set_values", "expri_workspace_size",
+                "expri_bind_workspace",
                 "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run",
                 "expri_run_schedule", "expri_step", "expri_trace", "expri_get_run_info",
                 "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_launch_classes",
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "expri_default_opts": ([C.POINTER(Opts)], C.c_int),
         "expri_setup": ([C.POINTER(_p), C.POINTER(Circuit), C.c_int32, C.POINTER(Opts), _p], C.c_int),
+        "expri_set_values": ([_p, C.c_int32, C.POINTER(Circuit)], C.c_int),
         "expri_workspace_size": ([_p, C.POINTER(C.c_size_t)], C.c_int),
         "expri_bind_workspace": ([_p, _p, C.c_size_t], C.c_int),
         "expri_dc": ([_p, pp, C.c_double], C.c_int),
@@ -297,6 +299,17 @@ class Solver:
         return _dev_ptrs(xs)
 
     # -- entry points ----------------------------------------------------
+    def set_values(self, inst: int, net, probes=None):
+        """Give instance `inst` the values of `net` (same sparsity pattern,
+        probe count and PWL corner count; see expri_set_values)."""
+        if not 0 <= inst < self.n_inst:
+            raise IndexError(inst)
+        m = _Marshal()
+        k = m.circuit(net, probes)
+        self._check(self.lib.expri_set_values(self.ctx, inst, C.byref(k)))
+        del m
+        self.nets[inst] = net
+
     def dc(self, xs, t0: float = 0.0):
         p, keep = self._vecs(xs)
         self._check(self.lib.expri_dc(self.ctx, p, t0))

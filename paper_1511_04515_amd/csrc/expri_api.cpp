@@ -87,6 +87,7 @@ struct Inst {
   int32_t n = 0, n_dev = 0, n_src = 0, n_probe = 0, n_bp = 0;
   double vdd = 1.0, T = 0.0, h_max = 0.0;
   size_t g_val, g_lu, c_val, b_val, c_ell_val, dev_par, src_ptr, src_t, src_v, bp, probe;  // const offsets
+  int32_t n_corners = 0;  // PWL corners over all sources (the breakpoint array holds n_corners + 1)
   // workspace offsets
   size_t xk, x1, w, p, z, tmp, e, Ik, devI, devD, devI1, lu, sval, rdv, V, Ve, H, He, mat, state, trace;
   int64_t ldv = 0;
@@ -137,6 +138,7 @@ struct expri_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double run_kernel_s = 0.0;  // summed duration of the k_run launches of the last call
   int32_t run_launches = 0;
+  bool factors_stale = false;  // values replaced since the last expri_factor
   std::string err;
 };
 
@@ -186,6 +188,67 @@ std::vector<double> gather(const double *val, const std::vector<int32_t> &src) {
   std::vector<double> out(src.size());
   for (size_t e = 0; e < src.size(); ++e) out[e] = val[src[e]];
   return out;
+}
+
+PatternInput pattern_input(const expri_circuit &K) {
+  PatternInput pin;
+  pin.n = K.n;
+  pin.g_rowptr = K.G.rowptr; pin.g_col = K.G.colidx;
+  pin.c_rowptr = K.C.rowptr; pin.c_col = K.C.colidx;
+  pin.b_rowptr = K.B.rowptr; pin.b_col = K.B.colidx;
+  pin.n_src = K.n_src;
+  pin.n_dev = K.dev.n;
+  pin.dev_d = K.dev.d; pin.dev_g = K.dev.g; pin.dev_s = K.dev.s;
+  return pin;
+}
+
+// The value arrays of one instance in the internal numbering: G, G scattered
+// to the L\U positions, C (CSR and padded ELL), B, the device parameters, the
+// PWL sources, the breakpoints (corners inside (0, T), then T; padded to
+// n_corners + 1 entries) and the probed nodes.  Built by expri_setup and
+// again by expri_set_values.
+struct InstValues {
+  std::vector<double> g, glu, c, ell, b, par, st, sv, bps;
+  std::vector<int32_t> sp, pr;
+  int32_t n_bp = 0;
+};
+
+InstValues inst_values(const expri_circuit &K, const PatternDev &PD) {
+  const Symbolic &S = PD.sym;
+  InstValues v;
+  v.g = gather(K.G.val, S.g_src);
+  v.glu.assign(S.lu_gidx.size(), 0.0);
+  for (size_t p = 0; p < v.glu.size(); ++p)
+    if (S.lu_gidx[p] >= 0) v.glu[p] = v.g[S.lu_gidx[p]];
+  v.c = gather(K.C.val, S.c_src);
+  v.ell.assign((size_t)std::max(PD.c_ell_k, 1) * PD.c_ell_ld, 0.0);
+  for (int i = 0; i < K.n; ++i)
+    for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e)
+      v.ell[(size_t)(e - S.c_rowptr[i]) * PD.c_ell_ld + i] = v.c[e];
+  v.b = gather(K.B.val, S.b_src);
+  v.par.resize(4 * (size_t)K.dev.n);
+  for (int i = 0; i < K.dev.n; ++i) {
+    v.par[4 * i] = K.dev.type[i];
+    v.par[4 * i + 1] = K.dev.kp[i] * K.dev.wl[i];
+    v.par[4 * i + 2] = K.dev.vth[i];
+    v.par[4 * i + 3] = K.dev.lam[i];
+  }
+  v.sp.assign(K.n_src + 1, 0);
+  for (int q = 0; q < K.n_src; ++q) {
+    v.sp[q + 1] = v.sp[q] + K.src[q].npts;
+    v.st.insert(v.st.end(), K.src[q].t, K.src[q].t + K.src[q].npts);
+    v.sv.insert(v.sv.end(), K.src[q].v, K.src[q].v + K.src[q].npts);
+    for (int i = 0; i < K.src[q].npts; ++i)
+      if (K.src[q].t[i] > 0 && K.src[q].t[i] < K.T) v.bps.push_back(K.src[q].t[i]);
+  }
+  std::sort(v.bps.begin(), v.bps.end());
+  v.bps.erase(std::unique(v.bps.begin(), v.bps.end()), v.bps.end());
+  v.bps.push_back(K.T);
+  v.n_bp = (int32_t)v.bps.size();
+  v.bps.resize(v.st.size() + 1, K.T);
+  v.pr.resize(K.n_probe);
+  for (int q = 0; q < K.n_probe; ++q) v.pr[q] = S.iperm[K.probe[q]];
+  return v;
 }
 
 
@@ -524,14 +587,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       return s;
     }
     const expri_circuit &K = ckt[k];
-    PatternInput pin;
-    pin.n = K.n;
-    pin.g_rowptr = K.G.rowptr; pin.g_col = K.G.colidx;
-    pin.c_rowptr = K.C.rowptr; pin.c_col = K.C.colidx;
-    pin.b_rowptr = K.B.rowptr; pin.b_col = K.B.colidx;
-    pin.n_src = K.n_src;
-    pin.n_dev = K.dev.n;
-    pin.dev_d = K.dev.d; pin.dev_g = K.dev.g; pin.dev_s = K.dev.s;
+    const PatternInput pin = pattern_input(K);
     const uint64_t h = pattern_hash(pin);
     int pid;
     auto it = by_hash.find(h);
@@ -685,56 +741,21 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     P.o_c_ell_col = pk.add(P.c_ell_col);
   }
   for (int k = 0; k < n_inst; ++k) {
-    const expri_circuit &K = ckt[k];
     Inst &I = c->inst[k];
-    const Symbolic &S = c->pats[I.pat].sym;
-    I.g_val = pk.add(gather(K.G.val, S.g_src));
-    {
-      const std::vector<double> gperm = gather(K.G.val, S.g_src);
-      std::vector<double> glu(S.lu_gidx.size(), 0.0);
-      for (size_t p = 0; p < glu.size(); ++p)
-        if (S.lu_gidx[p] >= 0) glu[p] = gperm[S.lu_gidx[p]];
-      I.g_lu = pk.add(glu);
-    }
-    const std::vector<double> cperm = gather(K.C.val, S.c_src);
-    I.c_val = pk.add(cperm);
-    {
-      const PatternDev &PD = c->pats[I.pat];
-      std::vector<double> ell((size_t)std::max(PD.c_ell_k, 1) * PD.c_ell_ld, 0.0);
-      for (int i = 0; i < K.n; ++i)
-        for (int e = S.c_rowptr[i]; e < S.c_rowptr[i + 1]; ++e)
-          ell[(size_t)(e - S.c_rowptr[i]) * PD.c_ell_ld + i] = cperm[e];
-      I.c_ell_val = pk.add(ell);
-    }
-    I.b_val = pk.add(gather(K.B.val, S.b_src));
-    std::vector<double> par(4 * (size_t)K.dev.n);
-    for (int i = 0; i < K.dev.n; ++i) {
-      par[4 * i] = K.dev.type[i];
-      par[4 * i + 1] = K.dev.kp[i] * K.dev.wl[i];
-      par[4 * i + 2] = K.dev.vth[i];
-      par[4 * i + 3] = K.dev.lam[i];
-    }
-    I.dev_par = pk.add(par);
-    std::vector<int32_t> sp(K.n_src + 1, 0);
-    std::vector<double> st, sv, bps;
-    for (int q = 0; q < K.n_src; ++q) {
-      sp[q + 1] = sp[q] + K.src[q].npts;
-      st.insert(st.end(), K.src[q].t, K.src[q].t + K.src[q].npts);
-      sv.insert(sv.end(), K.src[q].v, K.src[q].v + K.src[q].npts);
-      for (int i = 0; i < K.src[q].npts; ++i)
-        if (K.src[q].t[i] > 0 && K.src[q].t[i] < K.T) bps.push_back(K.src[q].t[i]);
-    }
-    std::sort(bps.begin(), bps.end());
-    bps.erase(std::unique(bps.begin(), bps.end()), bps.end());
-    bps.push_back(K.T);
-    I.n_bp = (int32_t)bps.size();
-    I.src_ptr = pk.add(sp);
-    I.src_t = pk.add(st);
-    I.src_v = pk.add(sv);
-    I.bp = pk.add(bps);
-    std::vector<int32_t> pr(K.n_probe);
-    for (int q = 0; q < K.n_probe; ++q) pr[q] = S.iperm[K.probe[q]];
-    I.probe = pk.add(pr);
+    const InstValues v = inst_values(ckt[k], c->pats[I.pat]);
+    I.g_val = pk.add(v.g);
+    I.g_lu = pk.add(v.glu);
+    I.c_val = pk.add(v.c);
+    I.c_ell_val = pk.add(v.ell);
+    I.b_val = pk.add(v.b);
+    I.dev_par = pk.add(v.par);
+    I.n_bp = v.n_bp;
+    I.n_corners = (int32_t)v.st.size();
+    I.src_ptr = pk.add(v.sp);
+    I.src_t = pk.add(v.st);
+    I.src_v = pk.add(v.sv);
+    I.bp = pk.add(v.bps);
+    I.probe = pk.add(v.pr);
   }
   c->const_bytes = pk.img.size();
   void *p = nullptr;
@@ -805,6 +826,52 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   return EXPRI_OK;
 }
 
+expri_status expri_set_values(expri_ctx *c, int32_t inst, const expri_circuit *ckt) {
+  if (!c) return EXPRI_EINVAL;
+  if (!ckt || inst < 0 || inst >= (int32_t)c->inst.size())
+    return fail(c, EXPRI_EINVAL, "set_values: instance out of range or null circuit");
+  expri_status s;
+  if ((s = validate_circuit(c, *ckt, inst)) != EXPRI_OK) return s;
+  const expri_circuit &K = *ckt;
+  Inst &I = c->inst[inst];
+  const PatternDev &P = c->pats[I.pat];
+  const Symbolic &S = P.sym;
+  const std::string w = "set_values: instance " + std::to_string(inst) + ": ";
+  const bool same = pattern_hash(pattern_input(K)) == S.hash && S.n == K.n && S.n_dev == K.dev.n &&
+                    S.n_src == K.n_src && (int32_t)S.g_col.size() == K.G.nnz &&
+                    (int32_t)S.c_col.size() == K.C.nnz && (int32_t)S.b_col.size() == K.B.nnz;
+  if (!same) return fail(c, EXPRI_EPATTERN, w + "the circuit's sparsity pattern differs from the instance's");
+  if (K.n_probe != I.n_probe) return fail(c, EXPRI_EINVAL, w + "the number of probes differs");
+  const InstValues v = inst_values(K, P);
+  if ((int32_t)v.st.size() != I.n_corners) return fail(c, EXPRI_EINVAL, w + "the number of PWL corners differs");
+  // no kernel of this context may still read the old values
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (const auto &Q : c->cls)
+    if (Q.stream && Q.stream != c->stream) HIPCHK(c, hipStreamSynchronize(Q.stream));
+  auto put = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpy(c->d_const + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  const std::pair<size_t, std::pair<const void *, size_t>> parts[] = {
+      {I.g_val, {v.g.data(), 8 * v.g.size()}},        {I.g_lu, {v.glu.data(), 8 * v.glu.size()}},
+      {I.c_val, {v.c.data(), 8 * v.c.size()}},        {I.c_ell_val, {v.ell.data(), 8 * v.ell.size()}},
+      {I.b_val, {v.b.data(), 8 * v.b.size()}},        {I.dev_par, {v.par.data(), 8 * v.par.size()}},
+      {I.src_ptr, {v.sp.data(), 4 * v.sp.size()}},    {I.src_t, {v.st.data(), 8 * v.st.size()}},
+      {I.src_v, {v.sv.data(), 8 * v.sv.size()}},      {I.bp, {v.bps.data(), 8 * v.bps.size()}},
+      {I.probe, {v.pr.data(), 4 * v.pr.size()}}};
+  for (const auto &q : parts) HIPCHK(c, put(q.first, q.second.first, q.second.second));
+  I.vdd = K.vdd;
+  I.T = K.T;
+  I.h_max = c->opts.h_max > 0 ? c->opts.h_max : K.T / 20;
+  I.n_bp = v.n_bp;
+  c->factors_stale = true;
+  if (c->d_ws) {
+    fill_descs(c);
+    if ((s = upload_descs(c)) != EXPRI_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return EXPRI_OK;
+}
+
 expri_status expri_workspace_size(const expri_ctx *c, size_t *bytes) {
   if (!c || !bytes) return EXPRI_EINVAL;
   *bytes = c->ws_bytes;
@@ -863,11 +930,14 @@ expri_status expri_factor(expri_ctx *c, const double *const *x) {
                             c->stream));
   std::vector<InstState> st;
   if ((s = read_states(c, st)) != EXPRI_OK) return s;
-  return first_error(c, st, "factor");
+  if ((s = first_error(c, st, "factor")) != EXPRI_OK) return s;
+  c->factors_stale = false;
+  return EXPRI_OK;
 }
 
 expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y) {
   if (!c || !b || !y) return EXPRI_EINVAL;
+  if (c->factors_stale) return fail(c, EXPRI_EINVAL, "solve: values replaced since the last expri_factor");
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();
@@ -884,6 +954,7 @@ expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y)
 expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out, double h, double eps,
                         int32_t *m, double *rho) {
   if (!c || !v || !out || !(h > 0) || !(eps > 0)) return EXPRI_EINVAL;
+  if (c->factors_stale) return fail(c, EXPRI_EINVAL, "mevp: values replaced since the last expri_factor");
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();

@@ -219,6 +219,54 @@ def test_batch_matches_single_instance_runs():
     sb.close()
 
 
+def test_set_values_matches_a_fresh_setup():
+    """expri_set_values on instances of a shared-pattern batch gives, bit for
+    bit, the factors, solves and transients of a fresh setup with those
+    values; a circuit of another pattern is refused with EPATTERN and solve
+    waits for a new factor."""
+    import paper_1511_04515_amd as E
+    import torch
+    kw = dict(seed=1004, n_stages=30, T=0.8e-9, t_ramp=0.3e-9)
+    vals = netgen.inverter_chain(**kw).meta["values"]
+    var = [netgen.inverter_chain(**kw, base=vals, variation=dict(seed=3000 + i)) for i in range(4)]
+    want = [var[0], var[3], var[0]]
+    x0s = [Oracle(n).dc() for n in want]
+    s = Solver(var[:3], block_size=512)
+    s.set_values(1, var[3])
+    s.set_values(2, var[0])
+    ref = Solver(want, block_size=512)
+
+    xs, xr = s.to_device(x0s), ref.to_device(x0s)
+    rng = np.random.default_rng(11)
+    bs = s.to_device([rng.standard_normal(n.n) for n in want])
+    ys = [torch.empty_like(b) for b in bs]
+    yr = [torch.empty_like(b) for b in bs]
+    with pytest.raises(E.ExpriError) as ei:
+        s.solve(bs, ys)
+    assert ei.value.status == -1
+    s.factor(xs)
+    ref.factor(xr)
+    s.solve(bs, ys)
+    ref.solve(bs, yr)
+    for i in range(3):
+        assert np.array_equal(s.lu_values(i), ref.lu_values(i))
+        assert np.array_equal(ys[i].cpu().numpy(), yr[i].cpu().numpy())
+
+    s.run(xs)
+    ref.run(xr)
+    for i in range(3):
+        a, b = s.trace(i), ref.trace(i)
+        assert np.array_equal(a["t"], b["t"]) and np.array_equal(a["x"], b["x"])
+        assert np.array_equal(xs[i].cpu().numpy(), xr[i].cpu().numpy())
+
+    other = netgen.inverter_chain(seed=9, n_stages=17, T=0.8e-9, t_ramp=0.3e-9)
+    with pytest.raises(E.ExpriError) as ei:
+        s.set_values(0, other)
+    assert ei.value.status == -8
+    s.close()
+    ref.close()
+
+
 def test_mixed_size_batch_runs_as_concurrent_classes_and_matches_single_runs():
     # chains of 841, 2521 and 6301 nodes take block sizes 256, 512 and 1024:
     # three launch classes, the transient kernels concurrent on three streams
