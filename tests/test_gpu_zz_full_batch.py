@@ -1,0 +1,82 @@
+"""The benchmark batch at full size, in the launch configuration the benchmark
+times (run on an MI355X).
+
+320 instances, 1.39M nodes: 256 variants of a 200-stage inverter chain
+(shared sparsity) and 64 chains of 50-400 stages. They run as three
+concurrent launch classes (1,024 / 512 / 256 threads), each a work queue
+over its instances. The oracle cannot run the whole batch in a test, so the
+checks are:
+  * invariants of every instance: status OK, t = T, one LU per accepted step,
+    a finite state;
+  * one sampled instance per class equals its single-instance run bit for bit
+    (same kernels, so the batch adds no arithmetic of its own);
+  * for each sampled instance, started from the oracle's own DC point, the
+    oracle's adaptive run (Algorithm 2) over its first K accepted steps. The
+    two controllers take the same decisions except where an error estimate
+    sits on E_rr, so the states are compared at the accepted times both grids
+    share. Each side's MEVP is within eps_K of the exact product (the residual
+    test of Algorithm 1), and a step after a rejection reuses the basis. So
+    the two trajectories may drift apart by at most 2 eps_K per step, and K
+    steps of a stable circuit by no more than 2 K eps_K.
+"""
+import numpy as np
+import pytest
+
+import netgen
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+K_REPLAY = 200
+
+
+def test_full_batch_in_the_benchmark_launch_configuration():
+    import paper_1511_04515_amd as E
+    import torch
+    nets = netgen.config(4)
+    assert len(nets) == 320
+    # one instance per class: the smallest of the 1,024 class, instance 0 (a
+    # shared-pattern variant) and the largest of the 256 class
+    by_bs = {}
+    for i, net in enumerate(nets):
+        bs = 256 if net.n <= 2048 else 512 if net.n <= 6144 else 1024
+        by_bs.setdefault(bs, []).append(i)
+    picks = [min(by_bs[1024], key=lambda i: nets[i].n), 0, max(by_bs[256], key=lambda i: nets[i].n)]
+    ref_x0 = {i: Oracle(nets[i]).dc() for i in picks}
+
+    s = E.Solver(nets, trace_cap=8192)
+    classes, _ = s.classes()
+    assert [(c["block_size"], c["n_inst"]) for c in classes] == [(1024, 22), (512, 289), (256, 9)]
+    xs = s.zeros()
+    s.dc(xs)
+    for i in picks:
+        xs[i].copy_(torch.from_numpy(ref_x0[i]))
+    x0 = [x.clone() for x in xs]
+    info = s.run(xs, max_steps_per_launch=8192)
+    for i, (net, r) in enumerate(zip(nets, info)):
+        assert r["status"] == 0 and r["t"] == net.T, i
+        assert r["lu_count"] == r["steps"] > 0, i
+        assert np.all(np.isfinite(xs[i].cpu().numpy())), i
+
+    eps_k = s.opts.eps_krylov
+    for i in picks:
+        net = nets[i]
+        s1 = E.Solver(net, trace_cap=8192)
+        x1 = [x0[i].clone()]
+        s1.run(x1, max_steps_per_launch=8192)
+        a, b = s.trace(i), s1.trace(0)
+        assert np.array_equal(a["t"], b["t"]) and np.array_equal(a["x"], b["x"]), i
+        assert np.array_equal(xs[i].cpu().numpy(), x1[0].cpu().numpy()), i
+        s1.close()
+
+        ref = Oracle(net).run(ref_x0[i], keep=net.probes, max_steps=K_REPLAY)
+        rt = np.array(ref.t)
+        common = np.intersect1d(a["t"], rt)
+        ia = np.searchsorted(a["t"], common)
+        ib = np.searchsorted(rt, common)
+        err = np.max(np.abs(a["x"][ia] - np.array(ref.x)[ib])) if common.size else np.inf
+        print(f"instance {i} (n = {net.n}): {len(a['t'])} steps; {common.size} of the oracle's first "
+              f"{rt.size} accepted times shared, max |dx| there {err:.2e} V", flush=True)
+        assert common.size >= min(10, rt.size), i
+        assert err <= 2 * K_REPLAY * eps_k, (i, err)
+    s.close()
