@@ -10,6 +10,12 @@ checks are:
     a finite state;
   * one sampled instance per class equals its single-instance run bit for bit
     (same kernels, so the batch adds no arithmetic of its own);
+  * with the learned step controller (the benchmark's default mode), trained
+    on disjoint circuits: every instance ends at T, every accepted step meets
+    the error budget E_rr (the paper's estimate still judges each step), the
+    sampled instances equal their single runs bitwise, and their final states
+    stay within 1e-3 V of the paper's control (both runs meet the same local
+    budget; the bound is loose on purpose and the observed gap is printed);
   * for each sampled instance, started from the oracle's own DC point, the
     oracle's adaptive run (Algorithm 2) over its first K accepted steps. The
     two controllers take the same decisions except where an error estimate
@@ -79,4 +85,47 @@ def test_full_batch_in_the_benchmark_launch_configuration():
               f"{rt.size} accepted times shared, max |dx| there {err:.2e} V", flush=True)
         assert common.size >= min(10, rt.size), i
         assert err <= 2 * K_REPLAY * eps_k, (i, err)
+
+    # the learned step controller on the same batch, from the same states
+    from paper_1511_04515_amd import control
+    tnets = _training_set()
+    st = E.Solver(tnets, probes=[np.zeros(0, np.int32)] * len(tnets), trace_cap=8192)
+    xt = st.zeros()
+    st.dc(xt)
+    st.run(xt, max_steps_per_launch=8192)
+    X, T = control.samples_from_traces([st.trace(i) for i in range(len(tnets))])
+    st.close()
+    params, norm, _ = control.train(X, T, epochs=40, batch=4096, lr=1e-3)
+    s.load_controller(params, norm, safety=1.0)
+    xl = [x.clone() for x in x0]
+    info_l = s.run(xl, max_steps_per_launch=8192)
+    E_rr = s.opts.E_rr
+    for i, (net, r) in enumerate(zip(nets, info_l)):
+        assert r["status"] == 0 and r["t"] == net.T, i
+        tr = s.trace(i)
+        assert tr["t"][-1] == net.T and np.all(tr["err"] <= E_rr), i
+    print(f"learned: {sum(r['steps'] for r in info_l)} accepted steps, "
+          f"{sum(r['rejects'] for r in info_l)} rejections (paper's control: "
+          f"{sum(r['steps'] for r in info)}, {sum(r['rejects'] for r in info)})", flush=True)
+    for i in picks:
+        s1 = E.Solver(nets[i], trace_cap=8192)
+        s1.load_controller(params, norm, safety=1.0)
+        x1 = [x0[i].clone()]
+        s1.run(x1, max_steps_per_launch=8192)
+        a, b = s.trace(i), s1.trace(0)
+        assert np.array_equal(a["t"], b["t"]) and np.array_equal(a["x"], b["x"]), i
+        assert np.array_equal(xl[i].cpu().numpy(), x1[0].cpu().numpy()), i
+        s1.close()
+        gap = np.max(np.abs(xl[i].cpu().numpy() - xs[i].cpu().numpy()))
+        print(f"instance {i}: final state, learned vs paper's control: max |dx| {gap:.2e} V", flush=True)
+        assert gap <= 1e-3, (i, gap)
     s.close()
+
+
+def _training_set():
+    # circuits disjoint from the batch (seeds 7000+)
+    base = netgen.inverter_chain(seed=7000, n_stages=80).meta["values"]
+    nets = [netgen.inverter_chain(seed=7000, n_stages=80, base=base, variation=dict(seed=7100 + i))
+            for i in range(8)]
+    nets += [netgen.inverter_chain(seed=7300 + j, n_stages=L) for j, L in enumerate((60, 110, 150, 190))]
+    return nets
