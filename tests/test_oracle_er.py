@@ -159,3 +159,106 @@ def test_erc_with_zero_gamma_is_er_and_correction_is_small():
     erc = Oracle(net, Options(erc=True, gamma=0.1)).replay(x0, ts, keep="all")
     diff = np.max(np.abs(np.array(erc.x) - np.array(er.x)))
     assert 0.0 < diff <= 20 * net.tol
+
+
+def _one_node_nmos_circuit():
+    """One node x: a capacitor to ground, a voltage source through R, and an
+    NMOS with its drain on x, its gate on the supply rail and its source on
+    ground.  The source falls linearly, so p and z are both non-zero."""
+    b = netgen.Builder()
+    x = b.node()
+    R, Cap, kp, wl, vth, lam = 1e3, 1e-15, 200e-6, 2.0, 0.3, 0.05
+    b.voltage_source(x, R, netgen.PWL([0.0, 10e-12], [0.2, 0.1]))
+    b.capacitor(x, -1, Cap)
+    b.mosfet(1, x, -2, -1, kp, wl, vth, lam)
+    net = b.build("one_node_nmos", T=10e-12)
+    return net, dict(g=1.0 / R, Cap=Cap, K=kp * wl, vov=1.0 - vth, lam=lam, u0=0.2, slope=-0.1 / 10e-12)
+
+
+def _nmos_current(x, K, vov, lam):
+    """Level-1 drain current of the grounded-source NMOS with V_gs = vov + V_th,
+    V_ds = x >= 0, and its derivative in x (written out for this test)."""
+    if x < vov:
+        P = vov * x - 0.5 * x * x
+        return K * P * (1 + lam * x), K * ((vov - x) * (1 + lam * x) + P * lam)
+    return 0.5 * K * vov * vov * (1 + lam * x), 0.5 * K * vov * vov * lam
+
+
+@pytest.mark.parametrize("h", [0.3e-12, 1e-12, 4e-12])
+def test_one_step_of_er_and_erc_on_one_node_matches_scalar_closed_form(h):
+    # With one unknown every matrix is a scalar and the Krylov space is exact
+    # at m = 1.  The ER step (the closed forms after the ER equation), the
+    # local error estimate and the ER-C correction (section on the modified
+    # correction term: x_{k+1,c} = x_{k+1} - gamma h phi_2(hJ) C^{-1} dF) are
+    # evaluated here from scalars, with phi_2(q) = (e^q - 1 - q) / q^2.
+    net, c = _one_node_nmos_circuit()
+    x0 = 0.9
+    g, Cap, K, vov, lam = c["g"], c["Cap"], c["K"], c["vov"], c["lam"]
+    I0, a = _nmos_current(x0, K, vov, lam)
+    Gk = g + a
+    q = -h * Gk / Cap                        # h J_k
+    r = g * c["u0"] - g * x0 - I0
+    w, p = r / Gk, g * c["slope"] / Gk
+    z = Cap * p / Gk
+    x1 = x0 + h * p - np.expm1(q) * (w - z)
+    I1, _ = _nmos_current(x1, K, vov, lam)
+    dF = a * (x1 - x0) - (I1 - I0)
+    err = abs(-np.expm1(q) * dF / Gk)
+    phi2 = (np.expm1(q) - q) / (q * q)
+    gamma = 0.1
+    x1c = x1 - gamma * h * phi2 * dF / Cap
+    # the correction is far above rounding, so its sign and size are visible
+    assert abs(x1c - x1) > 1e-8 * abs(x1)
+
+    er = Oracle(net, Options(tol=1.0)).replay(np.array([x0]), [h])
+    assert er.x[-1][0] == pytest.approx(x1, rel=1e-12, abs=0)
+    assert er.err[-1] == pytest.approx(err, rel=1e-10, abs=0)
+    erc = Oracle(net, Options(tol=1.0, erc=True, gamma=gamma)).replay(np.array([x0]), [h])
+    assert erc.x[-1][0] == pytest.approx(x1c, rel=1e-12, abs=0)
+    # the step is accepted on the estimate of the uncorrected state
+    assert erc.err[-1] == pytest.approx(err, rel=1e-10, abs=0)
+
+
+def test_erc_step_on_three_nodes_matches_dense_phi_functions():
+    # The single inverter has a capacitor on each of its three nodes, so C is
+    # invertible and J = -C^{-1} G_k can be formed.  phi_1 and phi_2 of hJ come
+    # from one dense exponential of the block matrix [[hJ, I, 0], [0, 0, I],
+    # [0, 0, 0]], whose first block row holds e^{hJ}, phi_1(hJ), phi_2(hJ).
+    import scipy.linalg
+    from oracle.mosfet import device_currents
+    from oracle.sources import source_values, source_slopes
+    net = netgen.single_inverter()
+    n = net.n
+    o = Oracle(net)
+    x0 = o.run(o.dc(), T=30e-12).x[-1]
+    t0 = 30e-12
+    h, gamma = 2e-12, 0.1
+    C = net.C.toarray()
+    assert np.linalg.matrix_rank(C) == n
+    I0, Jd = device_currents(net, x0)
+    Gk = net.G.toarray() + Jd.toarray()
+    J = -np.linalg.solve(C, Gk)
+    Z = np.zeros((3 * n, 3 * n))
+    Z[:n, :n] = h * J
+    Z[:n, n:2 * n] = np.eye(n)
+    Z[n:2 * n, 2 * n:] = np.eye(n)
+    E = scipy.linalg.expm(Z)
+    eJ, phi1, phi2 = E[:n, :n], E[:n, n:2 * n], E[:n, 2 * n:]
+    u = source_values(net, t0)
+    s = source_slopes(net, t0, h)
+    r = net.B @ u - net.G @ x0 - I0
+    g_k = np.linalg.solve(C, r)
+    b_k = np.linalg.solve(C, net.B @ s)
+    # the ER step as the paper writes it, before any cancellation of C^{-1}
+    x1 = x0 + h * phi1 @ g_k + h * h * phi2 @ b_k
+    I1, _ = device_currents(net, x1)
+    dF = Jd @ (x1 - x0) - (I1 - I0)
+    err = np.max(np.abs(h * phi1 @ np.linalg.solve(C, dF)))
+    x1c = x1 - gamma * h * phi2 @ np.linalg.solve(C, dF)
+    assert np.max(np.abs(x1c - x1)) > 1e-6
+    opts = dict(tol=1.0, eps_krylov=1e-16)
+    er = Oracle(net, Options(**opts)).replay(x0, [t0 + h], t0=t0)
+    erc = Oracle(net, Options(erc=True, gamma=gamma, **opts)).replay(x0, [t0 + h], t0=t0)
+    assert np.max(np.abs(er.x[-1] - x1)) <= 1e-11
+    assert er.err[-1] == pytest.approx(err, rel=1e-8)
+    assert np.max(np.abs(erc.x[-1] - x1c)) <= 1e-11

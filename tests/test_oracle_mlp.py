@@ -80,3 +80,44 @@ def test_bf16_inference_is_close_to_float64():
     y64, _ = mlp.forward(theta, X)
     y16 = mlp.forward_bf16(theta, X)
     assert np.max(np.abs(y16 - y64)) <= 0.05 * max(1.0, np.max(np.abs(y64)))
+
+
+def test_standardize_stats_hand_values():
+    # population statistics: column [1, 2, 3, 4] has mean 2.5 and standard
+    # deviation sqrt(1.25); a constant column keeps its mean and gets 1
+    X = np.zeros((4, 8))
+    X[:, 0] = [1.0, 2.0, 3.0, 4.0]
+    X[:, 1] = 5.0
+    X[:, 2] = [-2.0, 2.0, -2.0, 2.0]
+    T = np.array([[0.0, 7.0], [2.0, 7.0], [4.0, 7.0], [6.0, 7.0]])
+    xm, xs, tm, ts = mlp.standardize_stats(X, T)
+    assert xm[0] == 2.5 and xs[0] == pytest.approx(np.sqrt(1.25), rel=1e-15)
+    assert xm[1] == 5.0 and xs[1] == 1.0
+    assert xm[2] == 0.0 and xs[2] == 2.0
+    assert np.all(xm[3:] == 0.0) and np.all(xs[3:] == 1.0)
+    assert tm.tolist() == [3.0, 7.0] and ts[0] == pytest.approx(np.sqrt(5.0), rel=1e-15) and ts[1] == 1.0
+
+
+def test_bf16_inference_hand_rounded_network():
+    # A network whose every number is worked out by hand.  Each path checks one
+    # rounding: inputs, layer-1 weights, layer-1 activations, layer-2
+    # activations; dropping any of them changes an output.
+    theta = np.zeros(mlp.n_params())
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(theta)
+    X = np.zeros((1, 8))
+    X[0, 0] = 1.0
+    X[0, 1] = 1.0
+    X[0, 2] = 1 + 2.0 ** -8 + 2.0 ** -12          # input: bfloat16 gives 1 + 2^-7
+    W1[0, 0], b1[0] = 1.0, 3 * 2.0 ** -8          # z = 1 + 3 2^-8, a tie: rounds to 1 + 2^-6
+    W1[1, 1], b1[1] = 1 + 2.0 ** -9, -1.0         # weight: bfloat16 gives 1, so a = 0
+    W1[2, 2], b1[2] = 1.0, -1.0                    # a = 2^-7
+    W2[0, 0], b2[0] = 1.0, -1.0                    # (1 + 2^-6) - 1 = 2^-6
+    W2[1, 0], b2[1] = 1 + 2.0 ** -7, 0.0           # 1 + 3 2^-7 + 2^-13 rounds to 1 + 3 2^-7
+    W2[2, 1] = 1.0                                  # passes the weight-rounding path (0)
+    W2[3, 2] = 1.0                                  # passes the input-rounding path (2^-7)
+    W3[0, 0], W3[0, 2], W3[0, 3] = 1.0, 1.0, 1.0   # y0 = 2^-6 + 0 + 2^-7
+    W3[1, 1], b3[1] = 1.0, -1.0                    # y1 = 3 2^-7
+    y = mlp.forward_bf16(theta, X)
+    assert y.dtype == np.float32
+    assert y[0, 0] == np.float32(2.0 ** -6 + 2.0 ** -7)
+    assert y[0, 1] == np.float32(3 * 2.0 ** -7)
