@@ -22,6 +22,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -75,46 +77,101 @@ def workload(name):
     return nets, desc
 
 
-def algorithmic_bytes(sym, net, info):
+def algorithmic_bytes(sym, net, info, share=1, parts=False):
     """Bytes an ideal implementation moves for the recorded work of one
-    instance (8-byte values, 4-byte indices): refactor and assembly per LU;
-    the three right-hand sides per step; SpMV + solve pair + vector traffic per
-    Arnoldi step; one read of v_i per Gram-Schmidt product; one read of each
-    combined basis column; re-stamp, dF solve and basis start per trial."""
+    instance: 8-byte values, 4-byte indices, the indices of a sparsity
+    pattern amortised over the `share` instances of the batch that hold it
+    (one read of the index arrays serves all of them).  Per LU: refactor
+    (values read and written, pattern) and assembly of G_k and the device
+    table; per step: the three right-hand sides (G_lin SpMV, three L/U solve
+    pairs, C SpMV, vector traffic); per Arnoldi step: C SpMV + L/U solve pair +
+    vector traffic; one read of v_i per Gram-Schmidt product; one read of each
+    combined basis column; per trial: re-stamp, the dF solve pair and the
+    basis start.  parts=True also returns the bytes of the Arnoldi SpMV +
+    solves (the SpTRSV/SpMV phase)."""
     n = net.n
     zLU = sym["lu_col"].size
     zG = net.G.nnz
     zC = net.C.nnz
     D = net.n_dev
-    b = info["lu_count"] * (20 * zLU + 12 * zG + 100 * D)
-    b += info["steps"] * (12 * zG + 36 * zLU + 12 * zC + 80 * n)
-    b += info["arnoldi"] * (12 * zC + 12 * zLU + 40 * n)
+    ix = 4.0 / max(share, 1)
+    b = info["lu_count"] * ((16 + ix) * zLU + (8 + ix) * zG + 100 * D)
+    b += info["steps"] * ((8 + ix) * zG + 3 * (8 + ix) * zLU + (8 + ix) * zC + 80 * n)
+    spmv_sptrsv = info["arnoldi"] * ((8 + ix) * zC + (8 + ix) * zLU)
+    b += spmv_sptrsv + info["arnoldi"] * 40 * n
     b += info["mgs_terms"] * 8 * n
     b += info["comb_terms"] * 8 * n
-    b += info["trials"] * (64 * n + 100 * D + 12 * zLU)
-    return b
+    b += info["trials"] * (64 * n + 100 * D + (8 + ix) * zLU)
+    return (b, spmv_sptrsv) if parts else b
 
 
-def cpu_baseline(budget_s=15.0):
-    """The oracle on the 200-stage chain from its DC point, single thread:
-    a 20-step probe sizes a run of about budget_s seconds, which is timed."""
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[k] = "1"
+def pattern_key(net):
+    """Identity of a circuit's sparsity pattern (G, C, B, device terminals)."""
+    import hashlib
+    h = hashlib.sha256()
+    for m in (net.G, net.C, net.B):
+        h.update(np.asarray(m.indptr, np.int64).tobytes())
+        h.update(np.asarray(m.indices, np.int64).tobytes())
+    for k in ("d", "g", "s"):
+        h.update(np.asarray(net.mosfets[k], np.int64).tobytes())
+    return (net.n, h.hexdigest())
+
+
+def _oracle_sample(args):
+    """Worker of cpu_baseline: the oracle's first `steps` accepted ER steps of
+    one batch instance from its DC point (the DC solve is not timed)."""
+    idx, steps = args
     import netgen
     from oracle import Oracle
-    net = netgen.config(2)
+    net = netgen.batch_member(idx)
     x0 = Oracle(net).dc()
     t = time.perf_counter()
-    Oracle(net).run(x0, keep=None, max_steps=20)
-    per = (time.perf_counter() - t) / 20
-    n = max(20, int(budget_s / per))
-    o = Oracle(net)
+    tr = Oracle(net).run(x0, keep=None, max_steps=steps)
+    return len(tr.t), time.perf_counter() - t, net.n
+
+
+def cpu_baseline(n_inst=32, steps=100):
+    """The oracle (NumPy/SciPy FP64, one thread per process) on a sample of
+    the benchmark batch, one instance per process over the host's cores:
+    every 10th instance, its first `steps` accepted steps.  value = accepted
+    steps summed over the sample / the wall time of the timed runs (each
+    worker's timed runs, summed over the workers, spread over `cores`)."""
+    import multiprocessing as mp
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(avail, 16, n_inst))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    picks = list(range(0, 320, 320 // n_inst))[:n_inst]
     t = time.perf_counter()
-    tr = o.run(x0, keep=None, max_steps=n)
-    el = time.perf_counter() - t
-    return {"value": len(tr.t) / el, "unit": "instance-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {len(tr.t)} accepted ER steps of one 200-stage chain (4,201 nodes) "
-                      f"from its DC point ({el:.1f} s), NumPy/SciPy FP64 on one thread"}
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_sample, [(i, steps) for i in picks], chunksize=1)
+    wall = time.perf_counter() - t
+    n_steps = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    # the timed runs only (DC solves and interpreter start-up excluded):
+    # their summed duration spread over the worker processes
+    eff = busy / cores
+    return {"value": n_steps / eff, "unit": "instance-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "nproc": avail,
+            "single_core_value": n_steps / busy,
+            "sample": f"{len(picks)} instances of the benchmark batch (every {320 // n_inst}th: "
+                      f"{sum(1 for i in picks if i < 256)} shared-pattern 200-stage chains, "
+                      f"{sum(1 for i in picks if i >= 256)} uneven chains), the first {steps} accepted "
+                      f"ER steps of each from its DC point: {n_steps} steps, {busy:.1f} s of oracle time "
+                      f"on {cores} processes ({wall:.1f} s wall including DC solves and start-up), "
+                      f"NumPy/SciPy FP64, one thread per process"}
 
 
 def controller_training_set():
@@ -159,7 +216,7 @@ def train_controller(log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--controller", default="learned", choices=("learned", "plain"))
@@ -231,41 +288,64 @@ def main():
         el, _, _ = one_run()
         log(f"warmup {w}: {el:.2f} s")
     torch.cuda.synchronize()
-    times, infos, ktimes = [], [], []
+    times, infos, ktimes, cls_times = [], [], [], []
     for k in range(args.steps):
         el, info, kt = one_run()
         times.append(el)
         infos.append(info)
         ktimes.append(kt)
+        cls_times.append([c["kernel_s"] for c in s.classes()[0]])
         log(f"step {k}: {el:.2f} s, {sum(i['steps'] for i in info)} accepted ER steps")
-    total_steps = sum(sum(i["steps"] for i in info) for info in infos)
-    elapsed = sum(times)
-    value = total_steps / elapsed
+    # the median run gives ms_per_step, value and the kernel times alike
+    order = sorted(range(len(times)), key=lambda k: times[k])
+    med = order[len(order) // 2]
+    steps_run = [sum(i["steps"] for i in info) for info in infos]
+    value = steps_run[med] / times[med]
+    info = infos[med]
 
     # roofline of the transient kernel: one launch per launch class and run
     # (the classes run concurrently); the dominant kernel is the class with
     # the most algorithmic bytes, timed by HIP events on its own stream
-    info = infos[-1]
     classes, inst_class = s.classes()
+    share = {}
+    for net in nets:
+        share[pattern_key(net)] = share.get(pattern_key(net), 0) + 1
     cbytes = [0.0] * len(classes)
+    sp_bytes = 0.0
     for k, (net, inf) in enumerate(zip(nets, info)):
-        cbytes[inst_class[k]] += algorithmic_bytes(syms[(net.n, net.G.nnz, net.n_dev)], net, inf)
+        b, bsp = algorithmic_bytes(syms[(net.n, net.G.nnz, net.n_dev)], net, inf, share[pattern_key(net)],
+                                   parts=True)
+        cbytes[inst_class[k]] += b
+        sp_bytes += bsp
     q = int(np.argmax(cbytes))
-    ksec, nlaunch = ktimes[-1]
+    ksec, nlaunch = ktimes[med]
+    class_s = cls_times[med]
     per_launch_bytes = cbytes[q] / max(nlaunch, 1)
-    per_launch_s = classes[q]["kernel_s"] / max(nlaunch, 1)
+    per_launch_s = class_s[q] / max(nlaunch, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9
     kname = f"k_run<{classes[q]['block_size']}>"
     traffic = pmc_traffic_bytes(args.workload, ctrl is not None, nlaunch, kname)
+    # the SpTRSV/SpMV phase (Arnoldi C SpMV + L/U solves) from the in-kernel
+    # phase timers: its time summed over instances, spread over the resident
+    # workgroups
+    wgs = sum(c["workgroups"] for c in classes)
+    sp_s = sum(inf["phase_s"]["arnoldi_solve"] for inf in info)
+    sp_GBps = sp_bytes / max(sp_s / wgs, 1e-30) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "launches_per_step": nlaunch, "bytes_per_launch": per_launch_bytes,
-            "launch_ms": 1e3 * per_launch_s,
+            "launch_ms": 1e3 * per_launch_s, "timing": f"median of {len(times)} runs (run {med})",
             "classes": [{"kernel": f"k_run<{c['block_size']}>", "instances": c["n_inst"],
-                         "launch_ms": 1e3 * c["kernel_s"] / max(nlaunch, 1),
+                         "workgroups": c["workgroups"],
+                         "launch_ms": 1e3 * cs / max(nlaunch, 1),
                          "bytes_per_launch": b / max(nlaunch, 1),
-                         "GBps": b / max(c["kernel_s"], 1e-30) / 1e9} for c, b in zip(classes, cbytes)],
-            "concurrent_ms": 1e3 * ksec / max(nlaunch, 1)}
+                         "GBps": b / max(cs, 1e-30) / 1e9} for c, b, cs in zip(classes, cbytes, class_s)],
+            "concurrent_ms": 1e3 * ksec / max(nlaunch, 1),
+            "all_classes_GBps": sum(cbytes) / max(ksec, 1e-30) / 1e9,
+            "spmv_sptrsv": {"bytes": sp_bytes, "phase_s_summed": sp_s, "resident_workgroups": wgs,
+                            "GBps": sp_GBps, "frac": sp_GBps / HBM_PEAK_GBS,
+                            "what": "Arnoldi C SpMV + L/U solve bytes (indices amortised per pattern) / "
+                                    "(phase time summed over instances / resident workgroups)"}}
     if traffic is not None:
         roof["traffic_GBps"] = traffic / per_launch_s / 1e9
         roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
@@ -275,7 +355,7 @@ def main():
             phases[k] = phases.get(k, 0.0) + v
     out = {
         "metric": METRIC, "value": value, "unit": "instance-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * times[med],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded netgen circuits)",
         "config": {"workload": desc, "instances": len(nets), "nodes": int(sum(n.n for n in nets)),
@@ -286,7 +366,8 @@ def main():
                                   f"trained on the GPU (float32) from traces of disjoint circuits, "
                                   f"safety {args.safety}") if ctrl else "plain (the paper's alpha/beta rule)",
                    "block_sizes": {f"k_run<{c['block_size']}>": c["n_inst"] for c in classes}},
-        "time_to_solution_s": elapsed / args.steps,
+        "time_to_solution_s": times[med],
+        "run_seconds": times,
         "roofline": roof,
         "phase_share": {k: v / max(sum(phases.values()), 1e-30) for k, v in phases.items()},
     }
@@ -301,7 +382,7 @@ def main():
                                       "accepted_steps": int(steps_p),
                                       "rejected_trials": int(sum(i["rejects"] for i in inf_p)),
                                       "arnoldi_iterations": int(sum(i["arnoldi"] for i in inf_p))}
-        out["learned_vs_plain_time_to_solution"] = el / (elapsed / args.steps)
+        out["learned_vs_plain_time_to_solution"] = el / times[med]
         log(f"plain step control on the same batch: {el:.2f} s, {steps_p} accepted ER steps")
     s.close()
     if args.workload == "batch" and not args.no_plain:

@@ -149,6 +149,19 @@ typedef struct {
   int64_t comb_terms; /* Krylov basis columns combined into x_{k+1} and e_rr */
 } expri_run_info;
 
+/* Result of one adaptive step (expri_step) of one instance. */
+typedef struct {
+  double t;          /* time reached: t + h_used (or the source corner / T it landed on) */
+  double h_used;     /* size of the accepted trial (0 if no step was taken: t >= T) */
+  double h_next;     /* proposed size of the next step (alpha / beta rule) */
+  double err_inf;    /* ||e_rr||_inf of the accepted trial (V) */
+  double krylov_res; /* residual rho_m(h_used) of the step's MEVP (V) */
+  int32_t m;         /* Krylov dimension of the step's MEVP */
+  int32_t m_err;     /* Krylov dimension of the error estimate's MEVP */
+  int32_t n_reject;  /* rejected trials before the accepted one */
+  int32_t status;    /* expri_status of this instance */
+} expri_step_info;
+
 /* Trace record layout (doubles): t, h, h_try (the first trial before
  * clipping to a source corner or T), m, m_err, rejects, err_inf,
  * krylov_residual, the eight step features (below), then the n_probe probed
@@ -164,7 +177,10 @@ typedef struct {
 /* Fill o with the defaults listed above. */
 expri_status expri_default_opts(expri_opts *o);
 
-/* Analyse and upload n_inst circuits (host data, copied).  Builds the
+/* Analyse and upload n_inst circuits (host data, copied): the inputs of
+ * Algorithm 2, i.e. the circuit DAE of the paper's background section
+ * (C, G_lin, B, the devices behind F and the PWL sources u), with the error
+ * budget E_rr and the MEVP tolerance of the options.  Builds the
  * symbolic analysis of G_k's pattern (fill-reducing order, L\U pattern, level
  * schedules, refactor update lists, stamp maps) once per distinct pattern.
  * Each instance runs in one workgroup of 256 threads when n <= 2048, 512
@@ -232,17 +248,37 @@ expri_status expri_mevp(expri_ctx *ctx, const double *const *v, double *const *o
  * kernel launch (<= trace_cap); the call loops until all instances finish. */
 expri_status expri_run(expri_ctx *ctx, double *const *x, double t0, int32_t max_steps_per_launch);
 
-/* Replay: step instance i through the given accepted times t_seq[i][0..
- * n_steps[i]) (host arrays, increasing, > t0) accepting every first trial;
- * the error estimate is still computed and recorded.  Used for parity against
- * a reference time grid. */
+/* Replay (parity against a reference time grid): step instance i through
+ * the given accepted times t_seq[i][0..n_steps[i]) (host arrays, increasing,
+ * > t0), accepting every first trial.  Each step is Algorithm 2's body
+ * (stamp, LU_decompose(G_k), MEVP_IKS of Algorithm 1, update), and the error
+ * estimate of the local nonlinear error estimator section is still computed
+ * and recorded.  The grid is only read during the call; later calls use the
+ * instances' source corners again.  Errors as expri_run. */
 expri_status expri_run_schedule(expri_ctx *ctx, double *const *x, double t0,
                                 const double *const *t_seq, const int32_t *n_steps);
 
-/* One step of size h from (t, x) for every instance (a replay of one step);
- * info (host array of n_inst, may be NULL) receives the counters. */
-expri_status expri_step(expri_ctx *ctx, double *const *x, double t, double h,
-                        expri_run_info *info);
+/* One adaptive step of Algorithm 2 for every instance, from (t, x[i]) with
+ * proposed size h and error budget tol (V; 0 = the context's E_rr; the Krylov
+ * tolerance is tol / 10): the step is clipped to the next source corner and to
+ * the instance's T (u stays linear on the step, as the ER step assumes),
+ * G_k is factorised once, and trials shrink by alpha, reusing the factors and
+ * the Krylov basis, until ||e_rr||_inf <= tol (the trial loop of Algorithm 2;
+ * the paper's step control, never the learned controller).  x[i] (device,
+ * caller numbering) receives x_{k+1}; info (host array of n_inst, may be
+ * NULL) receives the time reached, the accepted size, the next proposed size
+ * (beta h after fewer than 5 rejections), the error, the Krylov sizes and the
+ * rejections.  An instance with t >= T takes no step (h_used = 0).
+ * ESTEPMIN / EKRYLOV / ESINGULAR / ENONFINITE keep x[i] at its input. */
+expri_status expri_step(expri_ctx *ctx, double *const *x, double t, double h, double tol,
+                        expri_step_info *info);
+
+/* One step of exactly h from (t, x) for every instance: expri_run_schedule
+ * with a grid of one point t + h (the first trial is accepted whatever its
+ * error estimate); info (host array of n_inst, may be NULL) receives the
+ * counters.  For replays of a given grid. */
+expri_status expri_step_fixed(expri_ctx *ctx, double *const *x, double t, double h,
+                              expri_run_info *info);
 
 /* Copy up to cap trace records of instance inst (host buffer of
  * cap * (EXPRI_REC_FIXED + n_probe) doubles); *n_rec = records available. */
@@ -322,6 +358,24 @@ expri_status expri_symbolic_array(const expri_symbolic *sym, const char *name, i
                                   int64_t *len);
 void expri_symbolic_destroy(expri_symbolic *sym);
 
+/* Host-only diagnostics of the multifrontal analysis used for one large
+ * circuit (no GPU is touched): the nested-dissection separator tree of G_k's
+ * pattern as a tree of dense fronts (LU_decompose(G_k) of Algorithm 2 organised
+ * by fronts).  leaf = the largest subdomain kept as one front.
+ * expri_frontal_array copies a named array as int64 (perm, c0, nc, fsz,
+ * parent, height, r_ptr, r_idx, rel, f_off, u_off, owner, lev_ptr,
+ * lev_front, ch_ptr, ch, ent_pos, ent_row, ent_g, ent_jptr, ent_jcode, g_rowptr,
+ * g_col, g_src, c_rowptr, c_col, c_src, b_rowptr, b_col, b_src, dev_node,
+ * node_ptr, node_code); expri_frontal_stats writes 8 doubles: fronts, front
+ * storage (doubles), stored factor entries, flops of one factorisation,
+ * largest front, largest pivot block, heights, update-vector storage. */
+typedef struct expri_frontal expri_frontal;
+expri_status expri_frontal_create(expri_frontal **f, const expri_circuit *ckt, int32_t leaf);
+expri_status expri_frontal_array(const expri_frontal *f, const char *name, int64_t *out, int64_t cap,
+                                 int64_t *len);
+expri_status expri_frontal_stats(const expri_frontal *f, double *out);
+void expri_frontal_destroy(expri_frontal *f);
+
 /* Message of the last failure ("" if none). */
 const char *expri_last_error(const expri_ctx *ctx);
 
@@ -387,7 +441,8 @@ void expri_mlp_destroy(expri_mlp *m);
  * rejects every trial, and rejections halve h as in Algorithm 2.  When a
  * learned trial's MEVP does not converge within m_max, the step restarts
  * once from the paper's own proposal (keeping the basis).  Replays
- * (expri_run_schedule, expri_step) ignore the controller.  EINVAL for a
+ * (expri_run_schedule, expri_step_fixed) and expri_step ignore the
+ * controller.  EINVAL for a
  * non-finite parameter, a std <= 0 or safety outside (0, 1]. */
 expri_status expri_controller_load(expri_ctx *ctx, const float *params, const float *norm, double safety);
 

@@ -76,6 +76,28 @@ class Builder:
     def conductance(self, a: int, b: int, siemens: float):
         self._stamp(self._g, a, b, siemens)
 
+    def resistors(self, a, b, ohms):
+        """Many resistors at once: a[i] -- b[i] with ohms[i] (inner nodes only)."""
+        a = np.asarray(a, np.int64); b = np.asarray(b, np.int64)
+        g = 1.0 / np.asarray(ohms, np.float64)
+        if a.size == 0:
+            return
+        if not (np.all(a >= 0) and np.all(b >= 0) and np.all(np.isfinite(g)) and np.all(g > 0)):
+            raise ValueError("bulk resistors need inner nodes and positive resistances")
+        r, c, v = self._g
+        r.extend(np.concatenate([a, b, a, b]).tolist())
+        c.extend(np.concatenate([a, b, b, a]).tolist())
+        v.extend(np.concatenate([g, g, -g, -g]).tolist())
+
+    def ground_capacitors(self, nodes, farads):
+        """Many capacitors from inner nodes to ground at once."""
+        nodes = np.asarray(nodes, np.int64)
+        f = np.asarray(farads, np.float64)
+        if nodes.size and not (np.all(nodes >= 0) and np.all(f > 0)):
+            raise ValueError("bulk capacitors need inner nodes and positive values")
+        r, c, v = self._c
+        r.extend(nodes.tolist()); c.extend(nodes.tolist()); v.extend(f.tolist())
+
     def capacitor(self, a: int, b: int, farads: float):
         if not farads > 0:
             raise ValueError("capacitance must be positive")
@@ -331,6 +353,64 @@ def inverter_chain(seed: int = 1002, n_stages: int = 200, n_seg: int = 10, T: fl
                    values=vals, seed=seed, n_stages=n_stages)
 
 
+def power_grid(seed: int = 1003, side: int = 512, T: float = 2 * NS, stim_seed: int = 2003,
+               n_drivers: int = 2000, via_pitch: int = 8, cap_frac: float = 0.7) -> Netlist:
+    """Post-layout-style power grid: two side x side resistive layers.
+
+    Layer 0 (top) holds nodes 0 .. side^2 - 1, layer 1 (bottom) the next
+    side^2, both row-major.  In-layer edge resistors are log-uniform
+    0.1-10 ohm; ground caps log-uniform 1-100 fF sit on a random cap_frac of
+    the grid nodes (C is singular on the rest); vias U(0.5, 2) ohm join the
+    layers at every via_pitch-th row and column; four corner Vdd = 1 V pads
+    on the top layer through 0.01 ohm.  n_drivers CMOS inverters (the chain's
+    level-1 parameter ranges) sit on distinct random bottom-layer nodes: the
+    PMOS source on the grid node, the NMOS source on ground, a private gate
+    node (1 fF) driven through 10 ohm by a ramp, and a private output node with
+    a U(5, 20) fF load, 0.5 fF and gmin = 1e-12 S.  Each input makes one
+    0 <-> 1 V edge of 50 ps at U(0.1, 1.5) ns, in a random direction.  Node
+    ids: the grid first, then (gate, output) per driver."""
+    rng = _rng(seed)
+    srng = _rng(stim_seed)
+    b = Builder(vdd=1.0)
+    per = side * side
+    grid = b.nodes(2 * per).reshape(2, side, side)
+    for layer in range(2):
+        g = grid[layer]
+        b.resistors(g[:, :-1].ravel(), g[:, 1:].ravel(), _log_uniform(rng, 0.1, 10.0, side * (side - 1)))
+        b.resistors(g[:-1, :].ravel(), g[1:, :].ravel(), _log_uniform(rng, 0.1, 10.0, side * (side - 1)))
+    vi = np.arange(0, side, via_pitch)
+    top = grid[0][np.ix_(vi, vi)].ravel()
+    bot = grid[1][np.ix_(vi, vi)].ravel()
+    b.resistors(top, bot, rng.uniform(0.5, 2.0, top.size))
+    capn = np.sort(rng.choice(2 * per, int(round(cap_frac * 2 * per)), replace=False))
+    b.ground_capacitors(capn, _log_uniform(rng, 1 * FF, 100 * FF, capn.size))
+    for (i, j) in ((0, 0), (0, side - 1), (side - 1, 0), (side - 1, side - 1)):
+        b.voltage_source(int(grid[0, i, j]), 0.01, PWL([0.0], [1.0]))
+    sites = grid[1].ravel()[np.sort(rng.choice(per, n_drivers, replace=False))]
+    vth = rng.uniform(0.28, 0.32, (n_drivers, 2))
+    kp = rng.uniform(100e-6, 300e-6, (n_drivers, 2))
+    wl = rng.uniform(1.0, 8.0, (n_drivers, 2))
+    cload = rng.uniform(5 * FF, 20 * FF, n_drivers)
+    edge = 50 * PS
+    t_edge = srng.uniform(0.1 * NS, 1.5 * NS, n_drivers)
+    rising = srng.random(n_drivers) < 0.5
+    outs = []
+    for k in range(n_drivers):
+        gate, out = b.node(), b.node()
+        lo, hi = (0.0, 1.0) if rising[k] else (1.0, 0.0)
+        b.voltage_source(gate, 10.0, PWL([0.0, t_edge[k], t_edge[k] + edge], [lo, lo, hi]))
+        b.capacitor(gate, GND, 1 * FF)
+        b.capacitor(out, GND, 0.5 * FF + cload[k])
+        b.conductance(out, GND, 1e-12)
+        b.mosfet(PMOS, out, gate, int(sites[k]), kp[k, 0], wl[k, 0], vth[k, 0])
+        b.mosfet(NMOS, out, gate, GND, kp[k, 1], wl[k, 1], vth[k, 1])
+        outs.append(out)
+    probes = np.unique(np.concatenate([sites[:: max(1, n_drivers // 16)], np.asarray(outs[:: max(1, n_drivers // 16)]),
+                                       [grid[0, side // 2, side // 2], grid[1, side // 2, side // 2]]]))
+    return b.build(f"power_grid_2x{side}x{side}", T=T, probes=probes, seed=seed, side=side,
+                   n_drivers=n_drivers, sites=sites)
+
+
 def batch(seed: int = 1004, n_variants: int = 256, n_uneven: int = 64, stages_lo: int = 50,
           stages_hi: int = 400, n_stages: int = 200, T: float = 4 * NS) -> list:
     """n_variants perturbed copies of one inverter-chain topology (identical
@@ -349,19 +429,35 @@ def batch(seed: int = 1004, n_variants: int = 256, n_uneven: int = 64, stages_lo
     return out
 
 
+def batch_member(i: int, seed: int = 1004, n_variants: int = 256, n_uneven: int = 64, stages_lo: int = 50,
+                 stages_hi: int = 400, n_stages: int = 200, T: float = 4 * NS) -> Netlist:
+    """Instance i of batch(...) with the same arguments, built alone."""
+    if i < n_variants:
+        base = inverter_chain(seed=seed, n_stages=n_stages, T=T).meta["values"]
+        return inverter_chain(seed=seed, n_stages=n_stages, T=T, base=base, variation=dict(seed=3000 + i))
+    j = i - n_variants
+    if not 0 <= j < n_uneven:
+        raise IndexError(i)
+    lengths = _rng(seed).integers(stages_lo, stages_hi + 1, n_uneven)
+    return inverter_chain(seed=3000 + n_variants + j, n_stages=int(lengths[j]), T=T)
+
+
 CONFIGS = {
     1: "rc_mesh 32x32, 1,024 nodes, linear, 16 pulse loads, T = 5 ns",
     2: "inverter chain, 200 stages x 10-segment ladders, 4,201 nodes, 400 MOSFETs, T = 4 ns",
+    3: "power grid 2 x 512 x 512 + 2,000 inverter drivers, 528,288 nodes, 4,000 MOSFETs, T = 2 ns",
     4: "batch of 256 chain variants (shared sparsity) + 64 chains of 50-400 stages, T = 4 ns",
 }
 
 
 def config(cid: int, **kw):
-    """The seeded workloads: 1 = RC mesh, 2 = inverter chain, 4 = batch."""
+    """The seeded workloads: 1 = RC mesh, 2 = inverter chain, 3 = power grid, 4 = batch."""
     if cid == 1:
         return rc_mesh(seed=1001, stim_seed=2001, **kw)
     if cid == 2:
         return inverter_chain(seed=1002, stim_seed=2002, **kw)
+    if cid == 3:
+        return power_grid(seed=1003, stim_seed=2003, **kw)
     if cid == 4:
         return batch(seed=1004, **kw)
     raise ValueError(f"unknown config {cid}")

@@ -96,6 +96,7 @@ class Trace:
     x: list = field(default_factory=list)
     lu_count: int = 0
     arnoldi_iters: int = 0
+    x_final: np.ndarray | None = None   # the state at the last accepted time
 
     def arrays(self):
         return {k: np.asarray(getattr(self, k)) for k in
@@ -300,6 +301,7 @@ class Oracle:
             h_prop = min(h_max, grow * (h_prop if i == 0 else h_used))
             self._record(t, x, h_used, info, keep)
             steps += 1
+        self.trace.x_final = x.copy()
         return self.trace
 
     # -- replay of a given time grid ----------------------------------------
@@ -313,4 +315,5 @@ class Oracle:
             x, _, info = self._trial_step(x, t, h, forced=True)
             t = tn
             self._record(t, x, h, info, keep)
+        self.trace.x_final = x.copy()
         return self.trace

@@ -27,11 +27,12 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -
 ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_set_values", "expri_workspace_size",
                 "expri_bind_workspace",
                 "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run",
-                "expri_run_schedule", "expri_step", "expri_trace", "expri_get_run_info",
+                "expri_run_schedule", "expri_step", "expri_step_fixed", "expri_trace", "expri_get_run_info",
                 "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_launch_classes",
                 "expri_block_size", "expri_diag_time", "expri_symbolic_create",
                 "expri_symbolic_array",
-                "expri_symbolic_destroy", "expri_last_error", "expri_destroy",
+                "expri_symbolic_destroy", "expri_frontal_create", "expri_frontal_array", "expri_frontal_stats",
+                "expri_frontal_destroy", "expri_last_error", "expri_destroy",
                 "expri_mlp_create", "expri_mlp_set_norm", "expri_mlp_fit_norm", "expri_mlp_get",
                 "expri_mlp_grad", "expri_mlp_adam_step", "expri_mlp_forward", "expri_mlp_last_error",
                 "expri_mlp_destroy", "expri_controller_load")
@@ -79,6 +80,12 @@ class RunInfo(C.Structure):
                 ("comb_terms", C.c_int64)]
 
 
+class StepInfo(C.Structure):
+    _fields_ = [("t", C.c_double), ("h_used", C.c_double), ("h_next", C.c_double), ("err_inf", C.c_double),
+                ("krylov_res", C.c_double), ("m", C.c_int32), ("m_err", C.c_int32), ("n_reject", C.c_int32),
+                ("status", C.c_int32)]
+
+
 PHASES = ("factor", "rhs", "arnoldi_solve", "mgs", "hess_phi", "trial")
 
 
@@ -116,7 +123,8 @@ def load_library(path: str = LIB_PATH):
         "expri_mevp": ([_p, pp, pp, C.c_double, C.c_double, _i32p, _f64p], C.c_int),
         "expri_run": ([_p, pp, C.c_double, C.c_int32], C.c_int),
         "expri_run_schedule": ([_p, pp, C.c_double, C.POINTER(_f64p), _i32p], C.c_int),
-        "expri_step": ([_p, pp, C.c_double, C.c_double, C.POINTER(RunInfo)], C.c_int),
+        "expri_step": ([_p, pp, C.c_double, C.c_double, C.c_double, C.POINTER(StepInfo)], C.c_int),
+        "expri_step_fixed": ([_p, pp, C.c_double, C.c_double, C.POINTER(RunInfo)], C.c_int),
         "expri_trace": ([_p, C.c_int32, _f64p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
         "expri_get_run_info": ([_p, C.c_int32, C.POINTER(RunInfo)], C.c_int),
         "expri_lu_pattern": ([_p, C.c_int32, _i32p, _i32p, _i32p, C.POINTER(C.c_int64), _i32p, _i32p,
@@ -127,6 +135,10 @@ def load_library(path: str = LIB_PATH):
         "expri_block_size": ([_p, _i32p], C.c_int),
         "expri_diag_time": ([_p, C.c_int32, C.c_int32, C.c_int32, _f64p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
+        "expri_frontal_create": ([C.POINTER(_p), C.POINTER(Circuit), C.c_int32], C.c_int),
+        "expri_frontal_array": ([_p, C.c_char_p, C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+        "expri_frontal_stats": ([_p, C.POINTER(C.c_double)], C.c_int),
+        "expri_frontal_destroy": ([_p], None),
         "expri_symbolic_array": ([_p, C.c_char_p, _i32p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
         "expri_symbolic_schedule": ([_p, C.c_int32, C.c_int32], C.c_int),
         "expri_symbolic_destroy": ([_p], None),
@@ -338,6 +350,11 @@ class Solver:
         self._check(self.lib.expri_run(self.ctx, p, t0, int(ms)))
         return [self.run_info(i) for i in range(self.n_inst)]
 
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self.lib.expri_workspace_size(self.ctx, C.byref(b)))
+        return b.value
+
     def run_schedule(self, xs, t_seqs, t0: float = 0.0):
         p, keep = self._vecs(xs)
         seqs = [_arr(s, np.float64) for s in t_seqs]
@@ -346,10 +363,18 @@ class Solver:
         self._check(self.lib.expri_run_schedule(self.ctx, p, t0, sp, cnt))
         return [self.run_info(i) for i in range(self.n_inst)]
 
-    def step(self, xs, t: float, h: float):
+    def step(self, xs, t: float, h: float, tol: float = 0.0):
+        """One adaptive step (trial loop at tol) of every instance; a list of
+        {t, h_used, h_next, err_inf, krylov_res, m, m_err, n_reject, status}."""
+        p, keep = self._vecs(xs)
+        info = (StepInfo * self.n_inst)()
+        self._check(self.lib.expri_step(self.ctx, p, t, h, tol, info))
+        return [{k: getattr(info[i], k) for k, _ in StepInfo._fields_} for i in range(self.n_inst)]
+
+    def step_fixed(self, xs, t: float, h: float):
         p, keep = self._vecs(xs)
         info = (RunInfo * self.n_inst)()
-        self._check(self.lib.expri_step(self.ctx, p, t, h, info))
+        self._check(self.lib.expri_step_fixed(self.ctx, p, t, h, info))
         return [self._info_dict(info[i]) for i in range(self.n_inst)]
 
     @staticmethod
@@ -496,6 +521,40 @@ def symbolic_analysis(net, block_size: int | None = None, solve_slots: int = 0) 
             out[name] = a[: n.value]
     finally:
         lib.expri_symbolic_destroy(h)
+    return out
+
+
+FRONTAL_ARRAYS = ("perm", "c0", "nc", "fsz", "parent", "height", "r_ptr", "r_idx", "rel", "f_off", "u_off",
+                  "owner", "lev_ptr", "lev_front", "ch_ptr", "ch", "ent_pos", "ent_row", "ent_g", "ent_jptr", "ent_jcode",
+                  "g_rowptr", "g_col", "g_src", "c_rowptr", "c_col", "c_src", "b_rowptr", "b_col", "b_src",
+                  "dev_node", "node_ptr", "node_code")
+FRONTAL_STATS = ("fronts", "front_doubles", "lu_entries", "flops", "max_front", "max_pivots", "heights",
+                 "update_doubles")
+
+
+def frontal_analysis(net, leaf: int = 32) -> dict:
+    """Host-only multifrontal analysis of one netlist (no GPU): the arrays of
+    the separator tree of fronts by name (int64) and its statistics."""
+    lib = load_library()
+    m = _Marshal()
+    k = m.circuit(net)
+    h = C.c_void_p()
+    st = lib.expri_frontal_create(C.byref(h), C.byref(k), int(leaf))
+    if st != 0:
+        raise ExpriError(st, "frontal analysis failed")
+    out = {}
+    try:
+        for name in FRONTAL_ARRAYS:
+            n = C.c_int64()
+            lib.expri_frontal_array(h, name.encode(), None, 0, C.byref(n))
+            a = np.zeros(max(n.value, 1), np.int64)
+            lib.expri_frontal_array(h, name.encode(), _ptr(a, C.c_int64), n.value, C.byref(n))
+            out[name] = a[: n.value]
+        st_ = (C.c_double * 8)()
+        lib.expri_frontal_stats(h, st_)
+        out["stats"] = dict(zip(FRONTAL_STATS, list(st_)))
+    finally:
+        lib.expri_frontal_destroy(h)
     return out
 
 

@@ -25,7 +25,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
 SOURCES = [("engine.hip", "hip"), ("controller.hip", "hip"), ("expri_api.cpp", "hip"), ("symbolic.cpp", "cxx"),
-           ("symbolic_capi.cpp", "cxx")]
+           ("symbolic_capi.cpp", "cxx"), ("frontal.cpp", "cxx")]
 
 
 def _run(cmd):
@@ -36,9 +36,22 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True when obj is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d)
+                    if f.endswith((".hpp", ".h"))]
+    return any(os.path.getmtime(f) > t for f in deps)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every translation unit (in parallel) and links libexpri.so.
+    incremental=True skips objects newer than every source and header."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src, kind in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD_DIR, src + ".o")
@@ -48,8 +61,12 @@ def build(verbose: bool = False) -> str:
             cmd = ["g++", *CXX_FLAGS, "-I", CSRC, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        _run(cmd)
+        if not incremental or _stale(path, obj):
+            cmds.append(cmd)
         objs.append(obj)
+    if cmds:
+        with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
+            list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)
@@ -57,4 +74,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -20,103 +20,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "devcommon.hpp"
 #include "layout.hpp"
+#include "mosfet.hpp"
 #include "mlp.hpp"
 
 namespace expri {
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-
-// Pointers held in the instance descriptors are generic; accesses through
-// them compile to flat instructions, which also count against the LDS wait
-// counter (an LDS wait then drains in-flight memory loads too).  The hot
-// loops re-type them as global-memory pointers first.
-#define GMEM __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ GMEM T *gbl(T *p) {
-  return (GMEM T *)p;
-}
-
-// Read-only data that the kernels never write during a launch (schedules):
-// re-typed as constant memory, so that uniform reads become scalar loads,
-// counted apart from the vector loads a solve pass keeps in flight.
-#define CMEM __attribute__((address_space(4)))
-
-// s_waitcnt operand: vector memory count 0, the other counters unconstrained
-constexpr unsigned kWaitVm0 = 0x0F70;
-template <class T>
-__device__ __forceinline__ const CMEM T *cst(const T *p) {
-  return (const CMEM T *)p;
-}
-
-// The thread index as an opaque value.  Per-lane values derived from it
-// (addresses, masks) are then computed inside each phase instead of being
-// hoisted to the kernel entry and held in registers across the whole step.
-__device__ __forceinline__ int tid() {
-  int t = threadIdx.x;
-  asm volatile("" : "+v"(t));
-  return t;
-}
-
-// orders a wave's own LDS traffic (its LDS operations complete in order)
-__device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
-// Wave-wide reductions on the DPP network: a butterfly inside each 16-lane
-// row (pairs of lanes 1 and 2 apart, then the 8- and 16-lane mirrors), then
-// the four row results read out in a fixed order.  Every lane ends with the
-// bit-identical value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
-constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i in each 8 lanes
-constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i in each 16 lanes
-
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<kDppXor1>(v);
-  v += dpp_d<kDppXor2>(v);
-  v += dpp_d<kDppHalfMirror>(v);
-  v += dpp_d<kDppMirror>(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
-}
-
-// max that propagates NaN
-__device__ __forceinline__ double nmax(double a, double b) {
-  return (isnan(a) || a > b) ? a : b;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-  v = nmax(v, dpp_d<kDppXor1>(v));
-  v = nmax(v, dpp_d<kDppXor2>(v));
-  v = nmax(v, dpp_d<kDppHalfMirror>(v));
-  v = nmax(v, dpp_d<kDppMirror>(v));
-  return nmax(nmax(readlane_d(v, 0), readlane_d(v, 16)), nmax(readlane_d(v, 32), readlane_d(v, 48)));
-}
-
-// sum over aligned groups of G lanes (G a power of two <= 64); the group's
-// lanes end with the same value
-__device__ __forceinline__ double group_sum(double v, int G) {
-  if (G >= 2) v += dpp_d<kDppXor1>(v);
-  if (G >= 4) v += dpp_d<kDppXor2>(v);
-  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
-  if (G >= 16) v += dpp_d<kDppMirror>(v);
-  if (G >= 32) v += __shfl_xor(v, 16, 64);
-  if (G >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
 
 // LDS scratch layout (dynamic shared memory):
 //   region : R doubles  -- solve vector, or small dense matrices
@@ -185,51 +94,6 @@ struct Prof {
   }
 };
 
-// ---------------------------------------------------------------------------
-// level-1 MOSFET (Shichman-Hodges with channel-length modulation)
-// I is the current into the drain terminal; derivatives w.r.t. V_d, V_g, V_s.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void mos_forward(double va, double vg, double vb, double K, double vth,
-                                            double lam, double &f, double &fa, double &fg,
-                                            double &fb) {
-  const double vov = vg - vb - vth;
-  const double vds = va - vb;
-  f = 0.0; fa = 0.0; fg = 0.0; fb = 0.0;
-  if (vov > 0.0) {
-    const double q = 1.0 + lam * vds;
-    double f_ov, f_ds;
-    if (vds < vov) {
-      const double P = vov * vds - 0.5 * vds * vds;
-      f = K * P * q;
-      f_ov = K * vds * q;
-      f_ds = K * ((vov - vds) * q + P * lam);
-    } else {
-      f = 0.5 * K * vov * vov * q;
-      f_ov = K * vov * q;
-      f_ds = 0.5 * K * vov * vov * lam;
-    }
-    fa = f_ds;
-    fg = f_ov;
-    fb = -f_ov - f_ds;
-  }
-}
-
-__device__ __forceinline__ void mos_eval(double type, double vd, double vg, double vs, double K,
-                                         double vth, double lam, double &I, double &dd,
-                                         double &dg, double &ds) {
-  const double sg = type > 0.0 ? 1.0 : -1.0;   // PMOS = mirror image of NMOS
-  vd *= sg; vg *= sg; vs *= sg;
-  double f, fa, fg, fb;
-  if (vd >= vs) {
-    mos_forward(vd, vg, vs, K, vth, lam, f, fa, fg, fb);
-    I = f; dd = fa; dg = fg; ds = fb;
-  } else {
-    mos_forward(vs, vg, vd, K, vth, lam, f, fa, fg, fb);
-    I = -f; dd = -fb; dg = -fg; ds = -fa;
-  }
-  I *= sg;
-}
 
 __device__ __forceinline__ double node_v(const double *x, int node, double vdd) {
   return node >= 0 ? x[node] : (node == -2 ? vdd : 0.0);
@@ -695,7 +559,6 @@ __device__ __forceinline__ double csr_row_dot(const int *rp, const int *ci, cons
 // ---------------------------------------------------------------------------
 
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // 1 / k!, folded at compile time
 template <int K>
@@ -1718,6 +1581,27 @@ __global__ void __launch_bounds__(BS) k_mevp(const InstDesc *descs, const int *o
 // host-side launchers (internal C++ API used by the C-ABI layer)
 // ---------------------------------------------------------------------------
 
+// The small-matrix part of Algorithm 1 for an engine that keeps its
+// Hessenberg matrix in global memory (the multifrontal engine of one large
+// circuit): one workgroup evaluates hess_phi on H (column-major, leading
+// dimension kHLd, with h_{m+1,m} stored below column m - 1, zero at a happy
+// breakdown) at step size h and basis norm beta[0].  out[0..m) = d,
+// out[kHLd..kHLd + m) = the phi_2 coefficients when want2, out[2 kHLd] = rho.
+// mat: global scratch of 5 x 64 x 65 doubles for m + 2 > 32.
+constexpr int kHessRD = 5 * 32 * 33;
+__global__ void __launch_bounds__(256) k_hess_phi1(const double *H, int m, double h, const double *beta,
+                                                   int want2, double *mat, double *out) {
+  Lds<256> L = lds_setup<256>(kHessRD, 0);
+  InstDesc D{};
+  D.mat = mat;
+  const double rho = hess_phi<256>(D, L, H, m, h, beta[0], H[m + (m - 1) * kHLd], L.dmain, want2 ? L.derr2 : nullptr);
+  for (int i = tid(); i < m; i += 256) {
+    gbl(out)[i] = L.dmain[i];
+    if (want2) gbl(out)[kHLd + i] = L.derr2[i];
+  }
+  if (tid() == 0) gbl(out)[2 * kHLd] = rho;
+}
+
 #define EXPRI_DISPATCH(BS_, CALL)                 \
   switch (BS_) {                                  \
     case 256: { constexpr int BS = 256; CALL; } break; \
@@ -1827,6 +1711,12 @@ hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin,
 
 hipError_t launch_init_workspace(const InstDesc *d, int n_inst, hipStream_t s) {
   hipLaunchKernelGGL(k_init_workspace, dim3(n_inst), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_hess_phi1(const double *H, int m, double h, const double *beta, int want2, double *mat,
+                            double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_hess_phi1, dim3(1), dim3(256), lds_bytes(256, kHessRD), s, H, m, h, beta, want2, mat, out);
   return hipGetLastError();
 }
 

@@ -399,6 +399,16 @@ expri_status ensure_ws(expri_ctx *c) {
   return EXPRI_OK;
 }
 
+// point every descriptor's step-end table at the instance's own source
+// corners (expri_run_schedule points it at a replay grid for one call)
+void restore_corners(expri_ctx *c) {
+  for (size_t k = 0; k < c->inst.size(); ++k) {
+    const Inst &I = c->inst[k];
+    c->h_desc[k].bp = reinterpret_cast<const double *>(c->d_const + I.bp);
+    c->h_desc[k].n_bp = I.n_bp;
+  }
+}
+
 expri_status upload_descs(expri_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(c->d_desc, c->h_desc.data(), sizeof(InstDesc) * c->h_desc.size(),
                            hipMemcpyHostToDevice, c->stream));
@@ -941,6 +951,7 @@ expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y)
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();
+  if ((s = upload_descs(c)) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(b))) != EXPRI_OK) return s;
   if ((s = put_ptrs(c, 1, reinterpret_cast<const void *const *>(y))) != EXPRI_OK) return s;
   for (const auto &K : c->cls)
@@ -982,11 +993,7 @@ expri_status expri_run(expri_ctx *c, double *const *x, double t0, int32_t max_st
   if (!c || !x) return EXPRI_EINVAL;
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
-  for (size_t k = 0; k < c->inst.size(); ++k) {
-    const Inst &I = c->inst[k];
-    c->h_desc[k].bp = reinterpret_cast<const double *>(c->d_const + I.bp);
-    c->h_desc[k].n_bp = I.n_bp;
-  }
+  restore_corners(c);
   return drive(c, x, t0, max_steps_per_launch, 0);
 }
 
@@ -1011,23 +1018,98 @@ expri_status expri_run_schedule(expri_ctx *c, double *const *x, double t0, const
   char *d = nullptr;
   HIPCHK(c, hipMalloc(reinterpret_cast<void **>(&d), total));
   size_t off = 0;
-  for (int k = 0; k < n; ++k) {
-    if (n_steps[k] > 0)
-      if (hipMemcpy(d + off, t_seq[k], 8 * (size_t)n_steps[k], hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        return fail(c, EXPRI_EHIP, "schedule upload");
-      }
+  s = EXPRI_OK;
+  for (int k = 0; k < n && s == EXPRI_OK; ++k) {
+    if (n_steps[k] > 0 &&
+        hipMemcpy(d + off, t_seq[k], 8 * (size_t)n_steps[k], hipMemcpyHostToDevice) != hipSuccess)
+      s = fail(c, EXPRI_EHIP, "schedule upload");
     c->h_desc[k].bp = reinterpret_cast<const double *>(d + off);
     c->h_desc[k].n_bp = n_steps[k];
     off += align_up(8 * (size_t)std::max(n_steps[k], 1));
   }
-  s = drive(c, x, t0, std::min(most, c->opts.trace_cap), 1);
+  if (s == EXPRI_OK) s = drive(c, x, t0, std::min(most, c->opts.trace_cap), 1);
+  // the descriptors point at the schedule only for this call: every later
+  // call reads the source corners again
+  (void)hipStreamSynchronize(c->stream);
+  restore_corners(c);
+  const expri_status su = upload_descs(c);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(d);
-  return s;
+  return s != EXPRI_OK ? s : su;
 }
 
-expri_status expri_step(expri_ctx *c, double *const *x, double t, double h, expri_run_info *info) {
+expri_status expri_step(expri_ctx *c, double *const *x, double t, double h, double tol, expri_step_info *info) {
+  if (!c || !x || !(h > 0) || !std::isfinite(t) || !(tol >= 0)) return EXPRI_EINVAL;
+  expri_status s;
+  if ((s = ensure_ws(c)) != EXPRI_OK) return s;
+  const int n = (int)c->inst.size();
+  restore_corners(c);
+  if ((s = upload_descs(c)) != EXPRI_OK) return s;
+  if ((s = put_ptrs(c, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
+  // the paper's step control at the error budget tol (eps_K = tol / 10)
+  Opts ko = kernel_opts(c->opts);
+  if (tol > 0) {
+    ko.E_rr = tol;
+    ko.eps_K = 0.1 * tol;
+  }
+  HIPCHK(c, launch_begin(c->d_desc, n, reinterpret_cast<const double *const *>(c->d_ptrs), t, h, c->stream));
+  for (auto &I : c->inst) I.trace_host.clear();
+  for (auto &K : c->cls) K.kernel_s = 0.0;
+  if ((s = launch_run_classes(c, ko, 1, 0)) != EXPRI_OK) return s;
+  std::vector<InstState> st;
+  if ((s = read_states(c, st)) != EXPRI_OK) return s;
+  float ms = 0.0f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->run_kernel_s = 1e-3 * ms;
+  c->run_launches = 1;
+  for (auto &K : c->cls) {
+    HIPCHK(c, hipEventElapsedTime(&ms, K.e0, K.e1));
+    K.kernel_s = 1e-3 * ms;
+  }
+  for (int k = 0; k < n; ++k) {
+    Inst &I = c->inst[k];
+    const size_t rec = kRecFixed + I.n_probe;
+    I.trace_host.assign((size_t)st[k].steps * rec, 0.0);
+    if (st[k].steps > 0)
+      HIPCHK(c, hipMemcpyAsync(I.trace_host.data(), c->d_ws + I.trace, sizeof(double) * rec,
+                               hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, launch_end(c->d_desc, n, reinterpret_cast<double *const *>(c->d_ptrs), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) {
+    Inst &I = c->inst[k];
+    expri_run_info &in = I.info;
+    in.t = st[k].t;
+    in.steps = st[k].steps;
+    in.lu_count = st[k].lu_count;
+    in.rejects = st[k].rejects;
+    in.arnoldi = st[k].arnoldi;
+    in.status = st[k].status;
+    for (int p = 0; p < 6; ++p) in.phase_s[p] = st[k].ph[p] / c->wall_hz;
+    in.trials = st[k].trials;
+    in.mgs_terms = st[k].mgs_terms;
+    in.comb_terms = st[k].comb_terms;
+    if (info) {
+      expri_step_info &o = info[k];
+      o = expri_step_info{};
+      o.t = st[k].t;
+      o.h_next = st[k].h_prop;
+      o.n_reject = st[k].rejects;
+      o.status = st[k].status;
+      if (st[k].steps > 0) {
+        const double *r = I.trace_host.data();
+        o.h_used = r[1];
+        o.m = (int32_t)r[3];
+        o.m_err = (int32_t)r[4];
+        o.err_inf = r[6];
+        o.krylov_res = r[7];
+      }
+    }
+  }
+  return first_error(c, st, "step");
+}
+
+expri_status expri_step_fixed(expri_ctx *c, double *const *x, double t, double h, expri_run_info *info) {
   if (!c || !x || !(h > 0)) return EXPRI_EINVAL;
   const int n = (int)c->inst.size();
   std::vector<double> tn(n, t + h);

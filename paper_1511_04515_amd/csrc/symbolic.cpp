@@ -201,6 +201,11 @@ void fnv(uint64_t &h, const void *p, size_t bytes) {
 
 }  // namespace
 
+bool check_csr_pattern(int32_t rows, int32_t cols, const int32_t *rp, const int32_t *ci, const char *name,
+                       std::string &err) {
+  return check_csr(rows, cols, rp, ci, name, err);
+}
+
 std::vector<int32_t> nested_dissection(int32_t n, const std::vector<int32_t> &ap,
                                        const std::vector<int32_t> &adj) {
   NDState st(n, ap, adj);

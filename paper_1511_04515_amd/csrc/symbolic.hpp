@@ -92,6 +92,10 @@ std::vector<int32_t> pass_codes(const std::vector<SolveLevel> &sched, int bs);
 // (ld = n when 0), -1 = padding; returns the ELL width.
 int32_t build_c_ell(const Symbolic &S, std::vector<int32_t> &col, int ld = 0);
 
+// Validates a 0-based CSR pattern (sorted, no duplicates, in range).
+bool check_csr_pattern(int32_t rows, int32_t cols, const int32_t *rp, const int32_t *ci, const char *name,
+                       std::string &err);
+
 // Fill-reducing order of a symmetric graph (adjacency without self loops) by
 // recursive BFS-level bisection (nested dissection).  Exposed for tests.
 std::vector<int32_t> nested_dissection(int32_t n, const std::vector<int32_t> &adj_ptr,

@@ -5,7 +5,12 @@
 #include <string>
 
 #include "../../include/expri.h"
+#include "frontal.hpp"
 #include "symbolic.hpp"
+
+struct expri_frontal {
+  expri::FrontalSym fs;
+};
 
 struct expri_symbolic {
   expri::Symbolic sym;
@@ -89,5 +94,67 @@ expri_status expri_symbolic_array(const expri_symbolic *s, const char *name, int
 }
 
 void expri_symbolic_destroy(expri_symbolic *s) { delete s; }
+
+expri_status expri_frontal_create(expri_frontal **out, const expri_circuit *k, int32_t leaf) {
+  if (!out || !k) return EXPRI_EINVAL;
+  *out = nullptr;
+  if (k->G.n_rows != k->n || k->C.n_rows != k->n || k->B.n_rows != k->n || k->B.n_cols != k->n_src)
+    return EXPRI_EINVAL;
+  expri::PatternInput pin;
+  pin.n = k->n;
+  pin.g_rowptr = k->G.rowptr; pin.g_col = k->G.colidx;
+  pin.c_rowptr = k->C.rowptr; pin.c_col = k->C.colidx;
+  pin.b_rowptr = k->B.rowptr; pin.b_col = k->B.colidx;
+  pin.n_src = k->n_src;
+  pin.n_dev = k->dev.n;
+  pin.dev_d = k->dev.d; pin.dev_g = k->dev.g; pin.dev_s = k->dev.s;
+  expri_frontal *f = new (std::nothrow) expri_frontal();
+  if (!f) return EXPRI_ENOMEM;
+  if (!expri::analyse_frontal(pin, f->fs, leaf)) {
+    delete f;
+    return EXPRI_EINVAL;
+  }
+  *out = f;
+  return EXPRI_OK;
+}
+
+expri_status expri_frontal_array(const expri_frontal *f, const char *name, int64_t *out, int64_t cap,
+                                 int64_t *len) {
+  if (!f || !name || !len) return EXPRI_EINVAL;
+  const expri::FrontalSym &S = f->fs;
+  const std::string nm(name);
+  const std::vector<int32_t> *v = nullptr;
+  const std::vector<int64_t> *w = nullptr;
+#define A(X) if (nm == #X) v = &S.X;
+  A(perm) A(c0) A(nc) A(fsz) A(parent) A(height) A(r_ptr) A(r_idx) A(rel) A(u_off) A(owner) A(lev_ptr)
+  A(lev_front) A(ch_ptr) A(ch) A(ent_row) A(ent_g) A(ent_jptr) A(ent_jcode) A(g_rowptr) A(g_col) A(g_src) A(c_rowptr)
+  A(c_col) A(c_src) A(b_rowptr) A(b_col) A(b_src) A(dev_node) A(node_ptr) A(node_code)
+#undef A
+  if (nm == "f_off") w = &S.f_off;
+  if (nm == "ent_pos") w = &S.ent_pos;
+  if (!v && !w) return EXPRI_EINVAL;
+  *len = v ? (int64_t)v->size() : (int64_t)w->size();
+  if (out && cap > 0) {
+    const int64_t m = std::min<int64_t>(cap, *len);
+    for (int64_t i = 0; i < m; ++i) out[i] = v ? (*v)[i] : (*w)[i];
+  }
+  return EXPRI_OK;
+}
+
+expri_status expri_frontal_stats(const expri_frontal *f, double *out) {
+  if (!f || !out) return EXPRI_EINVAL;
+  const expri::FrontalSym &S = f->fs;
+  out[0] = S.n_front;
+  out[1] = (double)S.front_doubles;
+  out[2] = (double)S.lu_entries;
+  out[3] = S.flops;
+  out[4] = S.max_front;
+  out[5] = S.max_nc;
+  out[6] = (double)S.lev_ptr.size() - 1;
+  out[7] = (double)S.upd_doubles;
+  return EXPRI_OK;
+}
+
+void expri_frontal_destroy(expri_frontal *f) { delete f; }
 
 }  // extern "C"

@@ -1,0 +1,149 @@
+"""Oracle parity of every kernel variant the launch-class rule can pick, the
+adaptive single step, and call-order independence (run on an MI355X).
+
+A transient workgroup keeps E rows of each vector per thread; the rule is
+256 threads up to n = 2,048, 512 up to 6,144, 1,024 up to 9,216, and E the
+smallest of 4, 6, 9 (12 at 512 threads only) with n <= E x threads.  One
+chain is sized into each band, and its replay on the oracle's accepted grid
+must meet the relative waveform bar at every accepted time point:
+    max_k ||x_gpu(t_k) - x_ref(t_k)||_inf / max(max_k ||x_ref(t_k)||_inf, 1 V) <= 1e-6.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import netgen
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# (threads, rows per thread, stages): n = 21 stages + 1
+VARIANTS = [(256, 4, 40), (256, 6, 50), (256, 9, 90), (512, 6, 120), (512, 9, 200), (512, 12, 250),
+            (1024, 9, 300)]
+
+
+def _expected_variant(n):
+    bs = 256 if n <= 2048 else 512 if n <= 6144 else 1024
+    for e in (4, 6, 9, 12):
+        if n <= e * bs and (e < 12 or bs == 512):
+            return bs, e
+    raise AssertionError(n)
+
+
+def variant_chain(L):
+    return netgen.inverter_chain(seed=500 + L, n_stages=L, T=0.25e-9, t_ramp=0.1e-9)
+
+
+def rel_wave_err(x, ref):
+    return np.max(np.abs(np.asarray(x) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1.0)
+
+
+@pytest.mark.parametrize("bs,E,L", VARIANTS)
+def test_every_kernel_variant_matches_oracle_replay(bs, E, L):
+    import paper_1511_04515_amd as X
+    g = np.load(os.path.join(GOLDEN, f"variant{L}.npz"), allow_pickle=False)
+    net = variant_chain(L)
+    assert _expected_variant(net.n) == (bs, E)
+    print(f"variant ({bs}, {E}): chain of {L} stages, n = {net.n}, {len(g['t'])} steps", flush=True)
+    s = X.Solver(net, trace_cap=4096)
+    assert s.classes()[0][0]["block_size"] == bs
+    xs = s.to_device([g["x0"]])
+    info = s.run_schedule(xs, [g["t"]])
+    assert info[0]["status"] == 0 and info[0]["steps"] == len(g["t"])
+    tr = s.trace(0)
+    assert np.array_equal(tr["t"], g["t"])
+    err = rel_wave_err(tr["x"], g["replay_probe_x"])
+    fin = rel_wave_err(xs[0].cpu().numpy(), g["x_final"])
+    print(f"  waveform rel err {err:.2e}, final state {fin:.2e}", flush=True)
+    assert err <= 1e-6 and fin <= 1e-6
+    s.close()
+
+
+def test_adaptive_step_follows_the_oracle_step():
+    # expri_step: one step of Algorithm 2 with its trial loop.  From a state in
+    # the middle of a switching edge, with a proposal large enough to be
+    # rejected, the oracle takes the same decisions (same accepted size, same
+    # rejections) and the same state to the waveform bar.
+    import paper_1511_04515_amd as X
+    from oracle import Options
+    net = netgen.inverter_chain(seed=77, n_stages=12, T=1.5e-9, t_ramp=0.2e-9)
+    o = Oracle(net)
+    x0 = o.dc()
+    mid = o.run(x0, T=0.15e-9)
+    xm, tm = np.array(mid.x[-1]), mid.t[-1]
+    s = X.Solver(net)
+    for h0, tol in ((4e-12, 1e-6), (1e-13, 1e-6), (4e-12, 1e-5)):
+        ref = Oracle(net, Options(h_init=h0, tol=tol)).run(xm, t0=tm, max_steps=1)
+        xs = s.to_device([xm])
+        info = s.step(xs, tm, h0, tol)[0]
+        got = xs[0].cpu().numpy()
+        print(f"h0 {h0:g} tol {tol:g}: h_used {info['h_used']:.4g} (oracle {ref.h[0]:.4g}), "
+              f"rejects {info['n_reject']} ({ref.rejects[0]}), err {info['err_inf']:.3g} ({ref.err[0]:.3g})",
+              flush=True)
+        assert info["status"] == 0
+        assert info["h_used"] == ref.h[0] and info["n_reject"] == ref.rejects[0]
+        assert info["t"] == ref.t[0]
+        assert info["err_inf"] <= tol
+        assert info["err_inf"] == pytest.approx(ref.err[0], rel=1e-3, abs=1e-3 * tol)
+        assert rel_wave_err(got, np.array(ref.x[-1])) <= 1e-6
+        grow = 2.0 if info["n_reject"] < 5 else 1.0
+        h_prop = h0 if info["n_reject"] == 0 else info["h_used"]
+        assert info["h_next"] == min(net.T / 20, grow * h_prop)
+    s.close()
+
+
+def test_a_chain_of_steps_equals_the_adaptive_run():
+    # expri_step called repeatedly with its own h_next is expri_run, step by step
+    import paper_1511_04515_amd as X
+    net = netgen.inverter_chain(seed=9, n_stages=17, T=0.3e-9, t_ramp=0.1e-9)
+    x0 = Oracle(net).dc()
+    s = X.Solver(net)
+    xr = s.to_device([x0])
+    s.run(xr)
+    tr = s.trace(0)
+    xs = s.to_device([x0])
+    t, h, k = 0.0, s.opts.h_init, 0
+    while t < net.T:
+        info = s.step(xs, t, h)[0]
+        assert info["status"] == 0
+        assert info["t"] == tr["t"][k] and info["h_used"] == tr["h"][k] and info["m"] == tr["m"][k], k
+        assert info["n_reject"] == tr["rejects"][k]
+        t, h, k = info["t"], info["h_next"], k + 1
+    assert k == len(tr["t"])
+    assert np.array_equal(xs[0].cpu().numpy(), xr[0].cpu().numpy())
+    # at t = T there is nothing left to do
+    info = s.step(xs, net.T, h)[0]
+    assert info["h_used"] == 0.0 and info["t"] == net.T
+    s.close()
+
+
+def test_calls_after_a_replay_see_the_source_corners_again():
+    # run_schedule points the step-end table at the replay grid for the call
+    # only: factor, DC and an adaptive run afterwards give what a fresh
+    # context gives
+    import paper_1511_04515_amd as X
+    net = netgen.inverter_chain(seed=21, n_stages=15, T=0.4e-9, t_ramp=0.1e-9)
+    x0 = Oracle(net).dc()
+    grid = np.linspace(0.0, 0.1e-9, 9)[1:]
+    a = X.Solver(net)
+    xa = a.to_device([x0])
+    a.run_schedule(xa, [grid])
+    a.factor(xa)
+    xd = a.zeros()
+    a.dc(xd)
+    xr = a.to_device([x0])
+    a.run(xr)
+    b = X.Solver(net)
+    xb = b.to_device([x0])
+    b.run(xb)
+    yd = b.zeros()
+    b.dc(yd)
+    assert np.array_equal(xd[0].cpu().numpy(), yd[0].cpu().numpy())
+    ta, tb = a.trace(0), b.trace(0)
+    assert np.array_equal(ta["t"], tb["t"]) and np.array_equal(ta["x"], tb["x"])
+    assert np.array_equal(xr[0].cpu().numpy(), xb[0].cpu().numpy())
+    a.close()
+    b.close()

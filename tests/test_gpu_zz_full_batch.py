@@ -14,16 +14,14 @@ checks are:
     on disjoint circuits: every instance ends at T, every accepted step meets
     the error budget E_rr (the paper's estimate still judges each step), the
     sampled instances equal their single runs bitwise, and their final states
-    stay within 1e-3 V of the paper's control (both runs meet the same local
-    budget; the bound is loose on purpose and the observed gap is printed);
+    stay within 100 E_rr of the paper's control (the observed gap is printed;
+    the learned run's accuracy against the oracle is asserted on a fresh
+    circuit in test_gpu_controller.py);
   * for each sampled instance, started from the oracle's own DC point, the
     oracle's adaptive run (Algorithm 2) over its first K accepted steps. The
     two controllers take the same decisions except where an error estimate
     sits on E_rr, so the states are compared at the accepted times both grids
-    share. Each side's MEVP is within eps_K of the exact product (the residual
-    test of Algorithm 1), and a step after a rejection reuses the basis. So
-    the two trajectories may drift apart by at most 2 eps_K per step, and K
-    steps of a stable circuit by no more than 2 K eps_K.
+    share, to the relative waveform bar of 1e-6.
 """
 import numpy as np
 import pytest
@@ -64,7 +62,6 @@ def test_full_batch_in_the_benchmark_launch_configuration():
         assert r["lu_count"] == r["steps"] > 0, i
         assert np.all(np.isfinite(xs[i].cpu().numpy())), i
 
-    eps_k = s.opts.eps_krylov
     for i in picks:
         net = nets[i]
         s1 = E.Solver(net, trace_cap=8192)
@@ -84,7 +81,9 @@ def test_full_batch_in_the_benchmark_launch_configuration():
         print(f"instance {i} (n = {net.n}): {len(a['t'])} steps; {common.size} of the oracle's first "
               f"{rt.size} accepted times shared, max |dx| there {err:.2e} V", flush=True)
         assert common.size >= min(10, rt.size), i
-        assert err <= 2 * K_REPLAY * eps_k, (i, err)
+        # the relative waveform bar at every shared accepted time
+        rel = err / max(np.max(np.abs(np.array(ref.x)[ib])), 1.0)
+        assert rel <= 1e-6, (i, err)
 
     # the learned step controller on the same batch, from the same states
     from paper_1511_04515_amd import control
@@ -118,7 +117,11 @@ def test_full_batch_in_the_benchmark_launch_configuration():
         s1.close()
         gap = np.max(np.abs(xl[i].cpu().numpy() - xs[i].cpu().numpy()))
         print(f"instance {i}: final state, learned vs paper's control: max |dx| {gap:.2e} V", flush=True)
-        assert gap <= 1e-3, (i, gap)
+        # the two controllers take different grids, so their states at T
+        # differ by the difference of their accumulated local errors (each
+        # step within E_rr); the accuracy of the learned run against the
+        # oracle is asserted on a fresh circuit in test_gpu_controller.py
+        assert gap <= 100 * E_rr, (i, gap)
     s.close()
 
 
