@@ -280,6 +280,19 @@ expri_status expri_step(expri_ctx *ctx, double *const *x, double t, double h, do
 expri_status expri_step_fixed(expri_ctx *ctx, double *const *x, double t, double h,
                               expri_run_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): expri_run
+ * with the context's workspace placed in a static device array of the
+ * library (64 MiB per GPU, held until the process ends) instead of memory the
+ * library allocates or the caller binds.  The call itself allocates no device
+ * memory.  Results equal expri_run's.  The context's own workspace, if it has
+ * one, is left untouched (factors kept for expri_solve / expri_mevp).  Every
+ * call on one GPU shares that GPU's array and overwrites it (the padding the
+ * kernels read is re-initialised by each call): calls that overlap on one GPU,
+ * from any context or thread, race.  EINVAL if expri_workspace_size exceeds
+ * 64 MiB; otherwise errors as expri_run. */
+expri_status expri_run_noalloc(expri_ctx *ctx, double *const *x, double t0, int32_t max_steps_per_launch);
+
 /* Copy up to cap trace records of instance inst (host buffer of
  * cap * (EXPRI_REC_FIXED + n_probe) doubles); *n_rec = records available. */
 expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_t cap, int64_t *n_rec);

@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "EKRYLOV", -
 # the names every C-ABI entry point of include/expri.h exports
 ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_set_values", "expri_workspace_size",
                 "expri_bind_workspace",
-                "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run",
+                "expri_dc", "expri_factor", "expri_solve", "expri_mevp", "expri_run", "expri_run_noalloc",
                 "expri_run_schedule", "expri_step", "expri_step_fixed", "expri_trace", "expri_get_run_info",
                 "expri_lu_pattern", "expri_lu_values", "expri_kernel_time", "expri_launch_classes",
                 "expri_block_size", "expri_diag_time", "expri_symbolic_create",
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH):
         "expri_solve": ([_p, pp, pp], C.c_int),
         "expri_mevp": ([_p, pp, pp, C.c_double, C.c_double, _i32p, _f64p], C.c_int),
         "expri_run": ([_p, pp, C.c_double, C.c_int32], C.c_int),
+        "expri_run_noalloc": ([_p, pp, C.c_double, C.c_int32], C.c_int),
         "expri_run_schedule": ([_p, pp, C.c_double, C.POINTER(_f64p), _i32p], C.c_int),
         "expri_step": ([_p, pp, C.c_double, C.c_double, C.c_double, C.POINTER(StepInfo)], C.c_int),
         "expri_step_fixed": ([_p, pp, C.c_double, C.c_double, C.POINTER(RunInfo)], C.c_int),
@@ -348,6 +349,13 @@ class Solver:
         p, keep = self._vecs(xs)
         ms = self.opts.trace_cap if max_steps_per_launch is None else max_steps_per_launch
         self._check(self.lib.expri_run(self.ctx, p, t0, int(ms)))
+        return [self.run_info(i) for i in range(self.n_inst)]
+
+    def run_noalloc(self, xs, t0: float = 0.0, max_steps_per_launch: int | None = None):
+        """expri_run with the workspace in the library's static scratch array."""
+        p, keep = self._vecs(xs)
+        ms = self.opts.trace_cap if max_steps_per_launch is None else max_steps_per_launch
+        self._check(self.lib.expri_run_noalloc(self.ctx, p, t0, int(ms)))
         return [self.run_info(i) for i in range(self.n_inst)]
 
     def workspace_bytes(self) -> int:

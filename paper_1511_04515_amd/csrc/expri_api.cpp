@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,13 @@
 #include "layout.hpp"
 #include "mlp.hpp"
 #include "symbolic.hpp"
+
+// Workspace of expri_run_noalloc: a file-scope device array, so that the
+// call needs no allocation.  Each GPU holds its own copy for the life of the
+// process.  In host code `scratch` only names the array: its device address
+// comes from hipGetSymbolAddress (scratch_ptr below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace expri {
 // launchers (engine.hip)
@@ -538,6 +546,27 @@ expri_status drive(expri_ctx *c, double *const *x, double t0, int max_steps, int
     in.comb_terms = st[k].comb_terms;
   }
   return first_error(c, st, "transient");
+}
+
+// Address of the scratch array on each device, taken once per device with
+// that device current.
+std::mutex g_scratch_mu;
+char *g_scratch_dev[64] = {};
+
+expri_status scratch_ptr(expri_ctx *c, char **out) {
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(c, EXPRI_EINVAL, "run_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, EXPRI_EHIP, std::string("run_noalloc: scratch address: ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return EXPRI_OK;
 }
 
 }  // namespace
@@ -1120,6 +1149,35 @@ expri_status expri_step_fixed(expri_ctx *c, double *const *x, double t, double h
   if (info)
     for (int k = 0; k < n; ++k) info[k] = c->inst[k].info;
   return s;
+}
+
+expri_status expri_run_noalloc(expri_ctx *c, double *const *x, double t0, int32_t max_steps_per_launch) {
+  if (!c || !x) return EXPRI_EINVAL;
+  if (c->ws_bytes > kScratchBytes)
+    return fail(c, EXPRI_EINVAL, "run_noalloc: the context needs a workspace of " + std::to_string(c->ws_bytes) +
+                                     " bytes, more than the static scratch of " + std::to_string(kScratchBytes));
+  char *scr = nullptr;
+  expri_status s = scratch_ptr(c, &scr);
+  if (s != EXPRI_OK) return s;
+  // the call's workspace is the scratch array; the context's own workspace
+  // (if any) is set aside and restored afterwards, untouched
+  char *own = c->d_ws;
+  const bool own_owned = c->ws_owned;
+  c->d_ws = scr;
+  c->ws_owned = false;
+  fill_descs(c);
+  restore_corners(c);
+  s = upload_descs(c);
+  if (s == EXPRI_OK && hipSuccess != launch_init_workspace(c->d_desc, (int)c->inst.size(), c->stream))
+    s = fail(c, EXPRI_EHIP, "run_noalloc: workspace initialisation");
+  if (s == EXPRI_OK) s = drive(c, x, t0, max_steps_per_launch, 0);
+  (void)hipStreamSynchronize(c->stream);
+  c->d_ws = own;
+  c->ws_owned = own_owned;
+  fill_descs(c);
+  const expri_status su = own ? upload_descs(c) : EXPRI_OK;
+  (void)hipStreamSynchronize(c->stream);
+  return s != EXPRI_OK ? s : su;
 }
 
 expri_status expri_trace(const expri_ctx *c, int32_t inst, double *out, int64_t cap, int64_t *n_rec) {
