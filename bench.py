@@ -15,8 +15,8 @@ instance, the paper's control), the roofline figures of the transient kernel
 (algorithmic bytes per launch / its HIP-event duration), and the oracle's CPU
 throughput on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--workload batch|chain|mesh]
-                    [--controller learned|plain]
+    python bench.py [--steps K] [--warmup W] [--workload batch|chain|mesh|grid]
+                    [--controller learned|plain] [--grid-steps K]
 """
 from __future__ import annotations
 
@@ -174,6 +174,60 @@ def cpu_baseline(n_inst=32, steps=100):
                       f"NumPy/SciPy FP64, one thread per process"}
 
 
+def grid_measurement(k_steps, log):
+    """The single post-layout power grid (2 x 512 x 512 layers + 2,000 inverter
+    drivers, 528,288 unknowns) on the multifrontal engine: DC (untimed), then
+    k_steps adaptive ER steps of Algorithm 2 from t = 0 timed one by one
+    (expri_step with its own h_next); building blocks timed by HIP events:
+    one solve pair (forward + backward over the fronts), one numeric
+    refactorisation, one C SpMV.  The solve's algorithmic bytes are the
+    stored factor entries read once (8 B each) plus the solution and update
+    vectors; the refactor's work is its flop count."""
+    import numpy as np
+    import torch
+    import netgen
+    import paper_1511_04515_amd as E
+    net = netgen.config(3)
+    fa = E.frontal_analysis(net, leaf=16)["stats"]
+    s = E.Solver(net, probes=[np.zeros(0, np.int32)])
+    xs = s.zeros()
+    s.dc(xs)
+    torch.cuda.synchronize()
+    t, h = 0.0, s.opts.h_init
+    per, ms_used = [], []
+    for _ in range(k_steps):
+        t0 = time.perf_counter()
+        st = s.step(xs, t, h)[0]
+        per.append(time.perf_counter() - t0)
+        t, h = st["t"], st["h_next"]
+        ms_used.append(st["m"])
+    solve_s = s.diag_time(0, reps=10)
+    refac_s = s.diag_time(7, reps=3)
+    spmv_s = s.diag_time(2, reps=50)
+    s.close()
+    n = net.n
+    solve_bytes = 8.0 * fa["lu_entries"] + 8.0 * 4 * n
+    spmv_bytes = 12.0 * net.C.nnz + 16.0 * n
+    med = float(np.median(per))
+    log(f"grid: {k_steps} steps, median {1e3 * med:.1f} ms/step; solve pair {1e3 * solve_s:.2f} ms, "
+        f"refactor {1e3 * refac_s:.1f} ms, C SpMV {1e3 * spmv_s:.3f} ms")
+    return {"workload": "power grid 2 x 512 x 512 + 2,000 level-1 inverter drivers (528,288 unknowns, "
+                        "4,000 MOSFETs), T = 2 ns, E_rr = 1e-6 V, multifrontal engine",
+            "steps_timed": k_steps, "t_reached": t, "steps_per_s": 1.0 / med, "ms_per_step_median": 1e3 * med,
+            "krylov_m": ms_used,
+            "factor_entries": fa["lu_entries"], "fronts": fa["fronts"], "refactor_flops": fa["flops"],
+            "solve_pair_ms": 1e3 * solve_s,
+            "solve_roofline": {"bound": "hbm", "bytes": solve_bytes, "achieved": solve_bytes / solve_s / 1e9,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": solve_bytes / solve_s / 1e9 / HBM_PEAK_GBS},
+            "spmv_ms": 1e3 * spmv_s,
+            "spmv_roofline": {"bound": "hbm", "bytes": spmv_bytes, "achieved": spmv_bytes / spmv_s / 1e9,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": spmv_bytes / spmv_s / 1e9 / HBM_PEAK_GBS},
+            "refactor_ms": 1e3 * refac_s,
+            "refactor_roofline": {"bound": "mfma", "achieved": fa["flops"] / refac_s / 1e12, "peak": 78.6,
+                                  "unit": "TFLOP/s", "frac": fa["flops"] / refac_s / 1e12 / 78.6}}
+
+
 def controller_training_set():
     """Circuits for the learned controller's training traces, disjoint from
     every benchmarked circuit (seeds 7000+): 16 variants of a 100-stage chain
@@ -224,6 +278,8 @@ def main():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--grid-steps", type=int, default=20,
+                    help="adaptive steps of the single 528,288-node power grid (config 3) to time; 0 = skip")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-control run of the same batch")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only copy one device buffer of this many bytes to another (twice) and exit: the "
@@ -253,6 +309,16 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.workload == "grid":
+        # the single 528,288-node power grid alone (its own JSON line)
+        g = grid_measurement(args.grid_steps or 20, log)
+        print(json.dumps({"metric": "Rosenbrock-Euler steps/s (single power grid, multifrontal engine)",
+                          "value": g["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+                          "steps": g["steps_timed"], "warmup": 0, "ms_per_step": g["ms_per_step_median"],
+                          "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic (seeded netgen power grid)",
+                          "config": {"workload": g["workload"]}, "grid": g}), flush=True)
+        return
     nets, desc = workload(args.workload)
     syms = {}
     for net in nets:
@@ -412,6 +478,8 @@ def main():
                             "value": inf2[0]["steps"] / el2, "unit": "steps/s", "seconds": el2,
                             "accepted_steps": inf2[0]["steps"], "rejected_trials": inf2[0]["rejects"]}
         s2.close()
+    if args.workload == "batch" and args.grid_steps > 0:
+        out["grid"] = grid_measurement(args.grid_steps, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

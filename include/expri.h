@@ -127,7 +127,12 @@ typedef struct {
    * at a time, each taking the batch's instances in turn (0 = one per compute
    * unit; fewer leave compute units to other work) */
   int32_t max_workgroups;
-  int32_t reserved;  /* 0 */
+  /* engine: 0 = automatic (a single circuit with n > 9216 goes to the
+   * multifrontal engine, everything else to the one-workgroup engine),
+   * 1 = one-workgroup engine only, 2 = the multifrontal engine (one circuit;
+   * no ER-C, no learned controller, no expri_set_values / bind_workspace /
+   * run_noalloc / lu_pattern) */
+  int32_t engine;
   double gamma;
 } expri_opts;
 

@@ -70,7 +70,7 @@ class Opts(C.Structure):
                 ("grow_if_rejects_lt", C.c_int32), ("m_max", C.c_int32),
                 ("block_size", C.c_int32), ("trace_cap", C.c_int32),
                 ("erc", C.c_int32), ("solve_slots", C.c_int32),
-                ("max_workgroups", C.c_int32), ("reserved", C.c_int32), ("gamma", C.c_double)]
+                ("max_workgroups", C.c_int32), ("engine", C.c_int32), ("gamma", C.c_double)]
 
 
 class RunInfo(C.Structure):
@@ -281,10 +281,12 @@ class Solver:
         size = C.c_size_t()
         self._check(self.lib.expri_workspace_size(self.ctx, C.byref(size)))
         self.ws_bytes = int(size.value)
-        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self._ws.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        self._check(self.lib.expri_bind_workspace(self.ctx, C.c_void_p(aligned), C.c_size_t(self.ws_bytes)))
+        self._ws = None
+        if self.ws_bytes > 0:  # (the multifrontal engine owns its memory and reports none)
+            self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            self._check(self.lib.expri_bind_workspace(self.ctx, C.c_void_p(aligned), C.c_size_t(self.ws_bytes)))
         bs = C.c_int32()
         self._check(self.lib.expri_block_size(self.ctx, C.byref(bs)))
         self.bs = bs.value

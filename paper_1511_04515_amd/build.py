@@ -25,7 +25,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
 SOURCES = [("engine.hip", "hip"), ("controller.hip", "hip"), ("expri_api.cpp", "hip"), ("symbolic.cpp", "cxx"),
-           ("symbolic_capi.cpp", "cxx"), ("frontal.cpp", "cxx")]
+           ("symbolic_capi.cpp", "cxx"), ("frontal.cpp", "cxx"), ("grid.hip", "hip"), ("grid_engine.cpp", "hip")]
 
 
 def _run(cmd):

@@ -18,6 +18,7 @@
 
 #include "layout.hpp"
 #include "mlp.hpp"
+#include "grid_engine.hpp"
 #include "symbolic.hpp"
 
 // Workspace of expri_run_noalloc: a file-scope device array, so that the
@@ -147,6 +148,9 @@ struct expri_ctx {
   double run_kernel_s = 0.0;  // summed duration of the k_run launches of the last call
   int32_t run_launches = 0;
   bool factors_stale = false;  // values replaced since the last expri_factor
+  // one large circuit: the multifrontal engine (no launch classes, no
+  // workspace of the per-instance layout)
+  std::unique_ptr<GridEngine> grid;
   std::string err;
 };
 
@@ -569,6 +573,73 @@ expri_status scratch_ptr(expri_ctx *c, char **out) {
   return EXPRI_OK;
 }
 
+// The largest circuit the one-workgroup engine holds (12 rows per thread at
+// 512 threads, 9 at 1,024); beyond it a single circuit goes to the
+// multifrontal engine.
+constexpr int32_t kMaxWorkgroupRows = 9216;
+
+expri_status grid_status(expri_ctx *c, int st) {
+  if (st != 0) c->err = c->grid->err;
+  return (expri_status)st;
+}
+
+// the run summary and trace of the multifrontal engine's last call
+void grid_info(expri_ctx *c, int st) {
+  GridEngine &G = *c->grid;
+  Inst &I = c->inst[0];
+  I.info = expri_run_info{};
+  I.info.t = G.t_reached;
+  I.info.steps = G.steps;
+  I.info.lu_count = (int32_t)G.lu_count;
+  I.info.rejects = (int32_t)G.rejects;
+  I.info.arnoldi = (int32_t)G.arnoldi;
+  I.info.status = st;
+  I.info.trials = (int32_t)G.trials;
+  I.info.mgs_terms = G.mgs_terms;
+  I.info.comb_terms = G.comb_terms;
+  I.trace_host = G.trace;
+  c->run_kernel_s = G.kernel_s;
+  c->run_launches = 1;
+}
+
+expri_status setup_grid(expri_ctx *c, const expri_circuit *ckt, int32_t n_inst) {
+  const expri_opts &op = c->opts;
+  if (n_inst != 1) return fail(c, EXPRI_EINVAL, "the multifrontal engine takes one circuit");
+  if (op.erc != 0) return fail(c, EXPRI_EINVAL, "ER-C is not available in the multifrontal engine");
+  expri_status s;
+  if ((s = validate_circuit(c, ckt[0], 0)) != EXPRI_OK) return s;
+  const expri_circuit &K = ckt[0];
+  const PatternInput pin = pattern_input(K);
+  std::vector<double> kind(K.dev.n);
+  for (int i = 0; i < K.dev.n; ++i) kind[i] = K.dev.type[i];
+  std::vector<int32_t> npts(K.n_src);
+  std::vector<const double *> ts(K.n_src), vs(K.n_src);
+  for (int q = 0; q < K.n_src; ++q) {
+    npts[q] = K.src[q].npts;
+    ts[q] = K.src[q].t;
+    vs[q] = K.src[q].v;
+  }
+  GridValues val{K.G.val, K.C.val, K.B.val, kind.data(), K.dev.kp, K.dev.wl, K.dev.vth, K.dev.lam,
+                 K.n_src, npts.data(), ts.data(), vs.data(), K.vdd, K.T};
+  GridOpts go{op.E_rr, op.eps_krylov, op.alpha, op.beta, op.h_init, op.h_min, op.h_max, op.breakdown, op.piv_tol,
+              op.grow_if_rejects_lt, op.m_max, op.trace_cap};
+  c->grid.reset(new (std::nothrow) GridEngine());
+  if (!c->grid) return fail(c, EXPRI_ENOMEM, "engine allocation");
+  const int st = c->grid->setup(pin, val, K.probe, K.n_probe, go, c->stream, 16);
+  if (st != 0) return grid_status(c, st);
+  Inst I;
+  I.n = K.n;
+  I.n_dev = K.dev.n;
+  I.n_src = K.n_src;
+  I.n_probe = K.n_probe;
+  I.vdd = K.vdd;
+  I.T = K.T;
+  I.h_max = c->grid->h_max;
+  c->inst.push_back(std::move(I));
+  c->h_desc.resize(1);
+  return EXPRI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -591,7 +662,7 @@ expri_status expri_default_opts(expri_opts *o) {
   o->erc = 0;
   o->solve_slots = 0;
   o->max_workgroups = 0;
-  o->reserved = 0;
+  o->engine = 0;
   o->gamma = 0.1;
   return EXPRI_OK;
 }
@@ -612,13 +683,21 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       (op.erc != 0 && op.erc != 1) || !std::isfinite(op.gamma) ||
       (op.solve_slots != 0 && op.solve_slots != 1 && op.solve_slots != 2 && op.solve_slots != 4 &&
        op.solve_slots != 8) ||
-      op.max_workgroups < 0 || op.reserved != 0 ||
+      op.max_workgroups < 0 || op.engine < 0 || op.engine > 2 ||
       (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
     *out = c.release();
     (*out)->err = "invalid options";
     return EXPRI_EINVAL;
   }
   expri_status s;
+  if (op.engine == 2 || (op.engine == 0 && n_inst == 1 && ckt[0].n > kMaxWorkgroupRows)) {
+    if ((s = setup_grid(c.get(), ckt, n_inst)) != EXPRI_OK) {
+      *out = c.release();
+      return s;
+    }
+    *out = c.release();
+    return EXPRI_OK;
+  }
   std::map<uint64_t, int> by_hash;
   for (int k = 0; k < n_inst; ++k) {
     if ((s = validate_circuit(c.get(), ckt[k], k)) != EXPRI_OK) {
@@ -867,6 +946,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
 
 expri_status expri_set_values(expri_ctx *c, int32_t inst, const expri_circuit *ckt) {
   if (!c) return EXPRI_EINVAL;
+  if (c->grid) return fail(c, EXPRI_EINVAL, "set_values: not available in the multifrontal engine");
   if (!ckt || inst < 0 || inst >= (int32_t)c->inst.size())
     return fail(c, EXPRI_EINVAL, "set_values: instance out of range or null circuit");
   expri_status s;
@@ -919,6 +999,7 @@ expri_status expri_workspace_size(const expri_ctx *c, size_t *bytes) {
 
 expri_status expri_bind_workspace(expri_ctx *c, void *dev_ptr, size_t bytes) {
   if (!c) return EXPRI_EINVAL;
+  if (c->grid) return fail(c, EXPRI_EINVAL, "bind_workspace: the multifrontal engine owns its memory");
   if (!dev_ptr || bytes < c->ws_bytes) return fail(c, EXPRI_EINVAL, "workspace too small");
   if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign) return fail(c, EXPRI_EINVAL, "workspace not 256-byte aligned");
   if (c->d_ws && c->ws_owned) (void)hipFree(c->d_ws);
@@ -934,6 +1015,11 @@ expri_status expri_bind_workspace(expri_ctx *c, void *dev_ptr, size_t bytes) {
 
 expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {
   if (!c || !x) return EXPRI_EINVAL;
+  if (c->grid) {
+    const int st = c->grid->dc(x[0], t0);
+    grid_info(c, st);
+    return grid_status(c, st);
+  }
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();
@@ -958,6 +1044,7 @@ expri_status expri_dc(expri_ctx *c, double *const *x, double t0) {
 
 expri_status expri_factor(expri_ctx *c, const double *const *x) {
   if (!c || !x) return EXPRI_EINVAL;
+  if (c->grid) return grid_status(c, c->grid->factor(x[0]));
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();
@@ -976,6 +1063,7 @@ expri_status expri_factor(expri_ctx *c, const double *const *x) {
 
 expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y) {
   if (!c || !b || !y) return EXPRI_EINVAL;
+  if (c->grid) return grid_status(c, c->grid->solve(b[0], y[0]));
   if (c->factors_stale) return fail(c, EXPRI_EINVAL, "solve: values replaced since the last expri_factor");
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
@@ -994,6 +1082,13 @@ expri_status expri_solve(expri_ctx *c, const double *const *b, double *const *y)
 expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out, double h, double eps,
                         int32_t *m, double *rho) {
   if (!c || !v || !out || !(h > 0) || !(eps > 0)) return EXPRI_EINVAL;
+  if (c->grid) {
+    const int st = c->grid->mevp(v[0], out[0], h, eps, m, rho);
+    c->inst[0].info = expri_run_info{};
+    c->inst[0].info.arnoldi = (int32_t)c->grid->arnoldi;
+    c->inst[0].info.status = st;
+    return grid_status(c, st);
+  }
   if (c->factors_stale) return fail(c, EXPRI_EINVAL, "mevp: values replaced since the last expri_factor");
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
@@ -1020,6 +1115,12 @@ expri_status expri_mevp(expri_ctx *c, const double *const *v, double *const *out
 
 expri_status expri_run(expri_ctx *c, double *const *x, double t0, int32_t max_steps_per_launch) {
   if (!c || !x) return EXPRI_EINVAL;
+  if (c->grid) {
+    const int st = c->grid->run(x[0], t0, nullptr, 0, INT32_MAX, c->opts.E_rr, c->opts.eps_krylov, c->opts.h_init,
+                                nullptr);
+    grid_info(c, st);
+    return grid_status(c, st);
+  }
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   restore_corners(c);
@@ -1029,6 +1130,15 @@ expri_status expri_run(expri_ctx *c, double *const *x, double t0, int32_t max_st
 expri_status expri_run_schedule(expri_ctx *c, double *const *x, double t0, const double *const *t_seq,
                                 const int32_t *n_steps) {
   if (!c || !x || !t_seq || !n_steps) return EXPRI_EINVAL;
+  if (c->grid) {
+    for (int i = 0; i < n_steps[0]; ++i)
+      if (!(t_seq[0][i] > (i ? t_seq[0][i - 1] : t0)) || !std::isfinite(t_seq[0][i]))
+        return fail(c, EXPRI_EINVAL, "schedule not increasing");
+    const int st = c->grid->run(x[0], t0, t_seq[0], n_steps[0], INT32_MAX, c->opts.E_rr, c->opts.eps_krylov,
+                                c->opts.h_init, nullptr);
+    grid_info(c, st);
+    return grid_status(c, st);
+  }
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();
@@ -1069,6 +1179,27 @@ expri_status expri_run_schedule(expri_ctx *c, double *const *x, double t0, const
 
 expri_status expri_step(expri_ctx *c, double *const *x, double t, double h, double tol, expri_step_info *info) {
   if (!c || !x || !(h > 0) || !std::isfinite(t) || !(tol >= 0)) return EXPRI_EINVAL;
+  if (c->grid) {
+    GridStepRec rec{};
+    const double E = tol > 0 ? tol : c->opts.E_rr, eps = tol > 0 ? 0.1 * tol : c->opts.eps_krylov;
+    const int st = c->grid->run(x[0], t, nullptr, 0, 1, E, eps, h, &rec);
+    grid_info(c, st);
+    if (info) {
+      info[0] = expri_step_info{};
+      info[0].t = c->grid->t_reached;
+      info[0].h_next = c->grid->next_h;
+      info[0].status = st;
+      if (c->grid->steps > 0) {
+        info[0].h_used = rec.h;
+        info[0].err_inf = rec.err;
+        info[0].krylov_res = rec.rho;
+        info[0].m = rec.m;
+        info[0].m_err = rec.m_err;
+        info[0].n_reject = rec.rejects;
+      }
+    }
+    return grid_status(c, st);
+  }
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
   const int n = (int)c->inst.size();
@@ -1153,6 +1284,7 @@ expri_status expri_step_fixed(expri_ctx *c, double *const *x, double t, double h
 
 expri_status expri_run_noalloc(expri_ctx *c, double *const *x, double t0, int32_t max_steps_per_launch) {
   if (!c || !x) return EXPRI_EINVAL;
+  if (c->grid) return fail(c, EXPRI_EINVAL, "run_noalloc: not available in the multifrontal engine");
   if (c->ws_bytes > kScratchBytes)
     return fail(c, EXPRI_EINVAL, "run_noalloc: the context needs a workspace of " + std::to_string(c->ws_bytes) +
                                      " bytes, more than the static scratch of " + std::to_string(kScratchBytes));
@@ -1199,6 +1331,7 @@ expri_status expri_get_run_info(const expri_ctx *c, int32_t inst, expri_run_info
 expri_status expri_lu_pattern(const expri_ctx *c, int32_t inst, int32_t *rowptr, int32_t *col, int32_t *perm,
                               int64_t *nnz, int32_t *n_lev, int32_t *n_ulev, int64_t *flops) {
   if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return EXPRI_EINVAL;
+  if (c->grid) return EXPRI_EINVAL;
   const Symbolic &S = c->pats[c->inst[inst].pat].sym;
   if (rowptr) std::memcpy(rowptr, S.lu_rowptr.data(), sizeof(int32_t) * S.lu_rowptr.size());
   if (col) std::memcpy(col, S.lu_col.data(), sizeof(int32_t) * S.lu_col.size());
@@ -1212,6 +1345,7 @@ expri_status expri_lu_pattern(const expri_ctx *c, int32_t inst, int32_t *rowptr,
 
 expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
   if (!c || !out || inst < 0 || inst >= (int32_t)c->inst.size() || !c->d_ws) return EXPRI_EINVAL;
+  if (c->grid) return EXPRI_EINVAL;
   const Inst &I = c->inst[inst];
   const size_t nnz = c->pats[I.pat].sym.lu_col.size();
   if (hipMemcpy(out, c->d_ws + I.lu, sizeof(double) * nnz, hipMemcpyDeviceToHost) != hipSuccess)
@@ -1221,6 +1355,7 @@ expri_status expri_lu_values(const expri_ctx *c, int32_t inst, double *out) {
 
 expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, int32_t arg, double *seconds) {
   if (!c || !seconds || what < 0 || what > 11 || reps < 1) return EXPRI_EINVAL;
+  if (c->grid) return grid_status(c, c->grid->diag(what, reps, seconds));
   if (arg < 0 || arg > c->opts.m_max - 1 || (what == 6 && arg < 1)) return EXPRI_EINVAL;
   expri_status s;
   if ((s = ensure_ws(c)) != EXPRI_OK) return s;
@@ -1239,7 +1374,7 @@ expri_status expri_diag_time(expri_ctx *c, int32_t what, int32_t reps, int32_t a
 
 expri_status expri_block_size(const expri_ctx *c, int32_t *bs) {
   if (!c || !bs) return EXPRI_EINVAL;
-  *bs = c->bs;
+  *bs = c->grid ? 256 : c->bs;
   return EXPRI_OK;
 }
 
@@ -1254,6 +1389,17 @@ expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *bloc
                                   int32_t *workgroups, double *kernel_s, int32_t *inst_class,
                                   int32_t *n_classes) {
   if (!c || !n_classes || cap < 0) return EXPRI_EINVAL;
+  if (c->grid) {  // one "class": the multifrontal engine's kernels (256 threads), grid-wide launches
+    *n_classes = 1;
+    if (inst_class) inst_class[0] = 0;
+    if (cap >= 1) {
+      if (block_size) block_size[0] = 256;
+      if (n_inst) n_inst[0] = 1;
+      if (workgroups) workgroups[0] = 0;
+      if (kernel_s) kernel_s[0] = c->run_kernel_s;
+    }
+    return EXPRI_OK;
+  }
   *n_classes = (int32_t)c->cls.size();
   if (inst_class)
     for (size_t k = 0; k < c->inst_class.size(); ++k) inst_class[k] = c->inst_class[k];
@@ -1270,6 +1416,7 @@ const char *expri_last_error(const expri_ctx *c) { return c ? c->err.c_str() : "
 
 expri_status expri_controller_load(expri_ctx *c, const float *params, const float *norm, double safety) {
   if (!c) return EXPRI_EINVAL;
+  if (c->grid) return fail(c, EXPRI_EINVAL, "the learned controller is not available in the multifrontal engine");
   if (!params) {
     c->ctrl_on = false;
     return EXPRI_OK;

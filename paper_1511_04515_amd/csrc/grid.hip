@@ -1,0 +1,876 @@
+// gfx950 kernels of the multifrontal engine: the exponential Rosenbrock-Euler
+// step (Algorithm 2, Algorithm 1 inside) for one circuit too large for one
+// workgroup, with the whole GPU working on it.
+//
+//   * LU_decompose(G_k) is a multifrontal factorisation over the separator
+//     tree of frontal.hpp, one tree height at a time (the fronts of a height
+//     are independent): assembly of G_k into zeroed dense fronts, extend-add of
+//     the children's Schur complements, then a blocked right-looking partial
+//     LU of every front (32-wide pivot blocks: one workgroup factorises the
+//     diagonal block and both panels, and the trailing update runs as 64 x 64
+//     FP64 MFMA tiles over all fronts of the height).  No pivoting (static
+//     order); a pivot below piv_tol times its row's largest |G_k| entry is
+//     reported as singular.
+//   * The solves G_k y = b walk the same tree: forward (L, bottom-up), each
+//     front gathering its children's update vectors, solving its unit-lower
+//     pivot block in 32-wide blocks (a wave solves the block triangle, the
+//     workgroup updates the rows below) and passing its own update vector up;
+//     backward (U, top-down), each front gathering the solution on its row
+//     structure.
+//   * Vector work (C SpMV, Gram-Schmidt products, norms, combinations) is
+//     element-strided over the grid; reductions are two-pass with a fixed
+//     summation order, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "devcommon.hpp"
+#include "layout.hpp"
+#include "mosfet.hpp"
+
+namespace expri {
+
+namespace {
+
+constexpr int kNB = 32;   // pivot block of the partial factorisation
+constexpr int kGT = 64;   // output tile of the trailing update
+constexpr int kET = 32;   // tile of the extend-add
+constexpr int kRB = 512;  // blocks of the two-pass reductions
+
+__device__ __forceinline__ double node_volt(const double *x, int v, double vdd) {
+  return v >= 0 ? x[v] : (v == -2 ? vdd : 0.0);
+}
+
+}  // namespace
+
+// p[0..n) = v
+__global__ void k_g_fill(double *p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// y[i] = x[map[i]] (gather; map = perm takes the caller's order to the new one)
+__global__ void k_g_gather(int n, const int *map, const double *x, double *y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = x[map[i]];
+}
+
+// y[map[i]] = x[i] (scatter back to the caller's order)
+__global__ void k_g_scatter(int n, const int *map, const double *x, double *y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[map[i]] = x[i];
+}
+
+// device currents I_k (into the drain) and dI_k/dV_{d,g,s} at x
+__global__ void k_g_stamp(int n_dev, const int *dev_node, const double *par, const double *x, double vdd,
+                          double *devI, double *devD) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_dev; k += gridDim.x * blockDim.x) {
+    const double *q = par + 4 * k;
+    double I, dd, dg, ds;
+    mos_eval(q[0], node_volt(x, dev_node[3 * k], vdd), node_volt(x, dev_node[3 * k + 1], vdd),
+             node_volt(x, dev_node[3 * k + 2], vdd), q[1], q[2], q[3], I, dd, dg, ds);
+    devI[k] = I;
+    devD[3 * k] = dd;
+    devD[3 * k + 1] = dg;
+    devD[3 * k + 2] = ds;
+  }
+}
+
+// G_k = G_lin + J_dev at its front positions (the fronts are zero); rowmax
+// receives max_j |G_k(i, j)| per row as the bit pattern of a non-negative
+// double (ordered like unsigned integers)
+__global__ void k_g_assemble(int n_ent, const int64_t *ent_pos, const int *ent_row, const int *ent_g,
+                             const int *ent_jptr, const int *ent_jcode, const double *g_val, const double *devD,
+                             double *F, unsigned long long *rowmax) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_ent; e += gridDim.x * blockDim.x) {
+    double v = ent_g[e] >= 0 ? g_val[ent_g[e]] : 0.0;
+    for (int q = ent_jptr[e]; q < ent_jptr[e + 1]; ++q) {
+      const int code = ent_jcode[q], k = code >> 3, eq = (code >> 2) & 1, var = code & 3;
+      const double d = devD[3 * k + var];
+      v += eq ? -d : d;
+    }
+    F[ent_pos[e]] = v;
+    atomicMax(rowmax + ent_row[e], (unsigned long long)__double_as_longlong(fabs(v)));
+  }
+}
+
+// One pass of the extend-add: item = (child c, tile (ti, tj)); adds the
+// child's Schur complement S_c (rows / columns nc_c.. of its front) into its
+// parent's front at the relative indices rel.  A pass holds at most one child
+// per parent, so no two items of a pass write the same entry.
+__global__ void __launch_bounds__(256) k_g_extend(const int *items, const int *nc, const int *fsz,
+                                                  const int *parent, const int64_t *f_off, const int *r_ptr,
+                                                  const int *rel, double *F) {
+  const int c = items[2 * blockIdx.x], tile = items[2 * blockIdx.x + 1];
+  const int ti = tile & 0xFFFF, tj = tile >> 16;
+  const int p = parent[c];
+  const int fc = fsz[c], ncc = nc[c], r = fc - ncc, fp = fsz[p];
+  const double *S = F + f_off[c] + (int64_t)ncc * fc + ncc;
+  double *P = F + f_off[p];
+  const int *rl = rel + r_ptr[c];
+  const int a = ti * kET + (threadIdx.x & 31);
+  if (a >= r) return;
+  const int ra = rl[a];
+#pragma unroll
+  for (int q = 0; q < kET / 8; ++q) {
+    const int b = tj * kET + (threadIdx.x >> 5) + 8 * q;
+    if (b < r) P[ra + (int64_t)rl[b] * fp] += S[a + (int64_t)b * fc];
+  }
+}
+
+// Step k0 of the partial factorisation, part 1, one workgroup per front: LU
+// of the diagonal block D = F[k0.., k0..] (kb x kb, kb = min(32, nc - k0))
+// without pivoting, stored in place.  A pivot with |u| <= piv_tol * rowmax
+// sets *bad (1 + the pivot's row).
+__global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const int *c0, const int *nc,
+                                               const int *fsz, const int64_t *f_off, const unsigned long long *rowmax,
+                                               double piv_tol, double *F, int *bad) {
+  __shared__ double Dm[kNB][kNB + 1];
+  const int s = fronts[blockIdx.x];
+  const int f = fsz[s], kb = min(kNB, nc[s] - k0);
+  double *A = F + f_off[s];
+  const int t = threadIdx.x;
+  for (int e = t; e < kNB * kNB; e += 64) {
+    const int i = e % kNB, j = e / kNB;
+    Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
+  }
+  wfence();
+  // lane t keeps row t of the block in registers; at step p lane p publishes
+  // its (final) row through LDS, and the lanes below eliminate with it.  A
+  // wave's LDS operations complete in order, so no barrier is needed.
+  double rw[kNB];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) rw[j] = Dm[min(t, kNB - 1)][j];
+#pragma unroll
+  for (int p = 0; p < kNB; ++p) {
+    if (p < kb) {
+      if (t == p) {
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) Dm[p][j] = rw[j];
+      }
+      wfence();
+      const double piv = Dm[p][p];
+      if (t == 0) {
+        const double rm = __longlong_as_double((long long)rowmax[c0[s] + k0 + p]);
+        if (!(fabs(piv) > piv_tol * rm)) atomicCAS(bad, 0, 1 + c0[s] + k0 + p);
+      }
+      if (t > p && t < kb) {
+        const double l = rw[p] / piv;
+        rw[p] = l;
+#pragma unroll
+        for (int j = p + 1; j < kNB; ++j) rw[j] -= l * Dm[p][j];
+      }
+    }
+  }
+  wfence();
+  if (t < kb) {
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) Dm[t][j] = rw[j];
+  }
+  wfence();
+  for (int e = t; e < kb * kb; e += 64) {
+    const int i = e % kb, j = e / kb;
+    A[(k0 + i) + (int64_t)(k0 + j) * f] = Dm[i][j];
+  }
+}
+
+// Part 2, item = (front s, chunk c): with the factored diagonal block, C rows
+// of the panel L21 = F[o.., k0..] U_D^{-1} and C columns of
+// U12 = L_D^{-1} F[k0.., o..], o = k0 + kb + c C.  When the whole trailing
+// block fits in one chunk and has at most fuse rows, the same workgroup also
+// applies the trailing update S -= L21 U12.  Dynamic LDS: 2 C (kNB + 1)
+// doubles (C <= 128).
+__global__ void __launch_bounds__(256) k_g_panel(const int *items, int k0, int C, int fuse, const int *nc,
+                                                 const int *fsz, const int64_t *f_off, double *F) {
+  __shared__ double Dm[kNB][kNB + 1];
+  extern __shared__ double pn[];
+  double (*Pn)[kNB + 1] = reinterpret_cast<double (*)[kNB + 1]>(pn);
+  const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
+  const int f = fsz[s], kb = min(kNB, nc[s] - k0);
+  double *A = F + f_off[s];
+  const int t = threadIdx.x;
+  const int rem = f - k0 - kb;
+  const int o = k0 + kb + chunk * C;
+  const int cnt = min(C, f - o);
+  if (cnt <= 0) return;  // the whole workgroup
+  for (int e = t; e < kNB * kNB; e += 256) {
+    const int i = e % kNB, j = e / kNB;
+    Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
+  }
+  // C rows of L21 in Pn[0..C), C columns of U12 in Pn[C..2C)
+  for (int e = t; e < C * kNB; e += 256) {
+    const int i = e % C, j = e / C;
+    if (i < cnt && j < kb) Pn[i][j] = A[(o + i) + (int64_t)(k0 + j) * f];
+    const int jj = e % kNB, c = e / kNB;
+    if (c < cnt && jj < kb) Pn[C + c][jj] = A[(k0 + jj) + (int64_t)(o + c) * f];
+  }
+  __syncthreads();
+  // each row of L21 (l U_D = a) and column of U12 (L_D u = a) is solved
+  // right-looking: after entry j is final, the later entries of the same row
+  // are updated with it (independent LDS updates, so they overlap)
+  if (t < cnt) {
+    for (int j = 0; j < kb; ++j) {
+      const double l = Pn[t][j] / Dm[j][j];
+      Pn[t][j] = l;
+      for (int jj = j + 1; jj < kb; ++jj) Pn[t][jj] -= l * Dm[j][jj];
+    }
+  } else if (t >= C && t - C < cnt) {
+    const int q = t - C;
+    for (int j = 0; j < kb - 1; ++j) {
+      const double u = Pn[C + q][j];
+      for (int jj = j + 1; jj < kb; ++jj) Pn[C + q][jj] -= Dm[jj][j] * u;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < C * kNB; e += 256) {
+    const int i = e % C, j = e / C;
+    if (i < cnt && j < kb) A[(o + i) + (int64_t)(k0 + j) * f] = Pn[i][j];
+    const int jj = e % kNB, c = e / kNB;
+    if (c < cnt && jj < kb) A[(k0 + jj) + (int64_t)(o + c) * f] = Pn[C + c][jj];
+  }
+  if (rem <= C && rem <= fuse) {  // the trailing update of a small front, in place
+    for (int e = t; e < rem * rem; e += 256) {
+      const int i = e % rem, j = e / rem;
+      double acc = A[(o + i) + (int64_t)(o + j) * f];
+      for (int k = 0; k < kb; ++k) acc -= Pn[i][k] * Pn[C + j][k];
+      A[(o + i) + (int64_t)(o + j) * f] = acc;
+    }
+  }
+}
+
+// Trailing update of step k0: item = (front s, tile (ti, tj)); the 64 x 64
+// tile of F[o.., o..] (o = k0 + kb) gets -= L21 U12 over the kb pivot
+// columns, on FP64 MFMA 16x16x4 (four waves, a 32 x 32 quadrant each).
+// MFMA lane layout: operand A lane i + 16 k holds A[i][k]; operand B lane
+// j + 16 k holds B[k][j]; result element v of lane j + 16 q is C[q + 4 v][j].
+__global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, const int *nc, const int *fsz,
+                                                  const int64_t *f_off, double *F) {
+  __shared__ double As[kGT][kNB + 1];
+  __shared__ double Bs[kNB][kGT + 1];
+  const int s = items[2 * blockIdx.x], tile = items[2 * blockIdx.x + 1];
+  const int f = fsz[s], kb = min(kNB, nc[s] - k0), o = k0 + kb;
+  const int i0 = o + (tile & 0xFFFF) * kGT, j0 = o + (tile >> 16) * kGT;
+  double *A = F + f_off[s];
+  const int t = threadIdx.x;
+  for (int e = t; e < kGT * kNB; e += 256) {
+    const int i = e % kGT, k = e / kGT;
+    As[i][k] = (i0 + i < f && k < kb) ? A[(i0 + i) + (int64_t)(k0 + k) * f] : 0.0;
+  }
+  for (int e = t; e < kNB * kGT; e += 256) {
+    const int k = e % kNB, j = e / kNB;
+    Bs[k][j] = (j0 + j < f && k < kb) ? A[(k0 + k) + (int64_t)(j0 + j) * f] : 0.0;
+  }
+  __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wi + 16 * mi + q + 4 * v, j = j0 + wj + 16 * ni + r;
+        acc[mi][ni][v] = (i < f && j < f) ? A[i + (int64_t)j * f] : 0.0;
+      }
+#pragma unroll
+  for (int k = 0; k < kNB; k += 4) {
+    double a[2], b[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) a[mi] = -As[wi + 16 * mi + r][k + q];
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) b[ni] = Bs[k + q][wj + 16 * ni + r];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wi + 16 * mi + q + 4 * v, j = j0 + wj + 16 * ni + r;
+        if (i < f && j < f) A[i + (int64_t)j * f] = acc[mi][ni][v];
+      }
+}
+
+// Forward solve of one tree height (L y = b, unit lower), part 1, one
+// workgroup per front: v = [x(cols s); 0] + the children's update vectors at
+// their relative indices; the unit-lower pivot block L11 is solved in 32-wide
+// blocks (a wave solves the block triangle, the workgroup updates the pivot
+// rows below it); y goes to x, the rest of v (the children's contributions to
+// the update vector) to upd.  Part 2 (k_g_fwd_gemv) subtracts L21 y.
+__global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
+                                                   const int64_t *f_off, const int *ch_ptr, const int *ch,
+                                                   const int *r_ptr, const int *rel, const int *u_off,
+                                                   const double *F, double *x, double *upd) {
+  extern __shared__ double v[];
+  const int s = fronts[blockIdx.x];
+  const int f = fsz[s], p = nc[s], b = c0[s];
+  const double *A = F + f_off[s];
+  const int t = threadIdx.x;
+  for (int i = t; i < f; i += 256) v[i] = i < p ? x[b + i] : 0.0;
+  __syncthreads();
+  for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
+    const int c = ch[q], rc = fsz[c] - nc[c];
+    const int *rl = rel + r_ptr[c];
+    const double *uc = upd + u_off[c];
+    for (int a = t; a < rc; a += 256) v[rl[a]] += uc[a];
+    __syncthreads();
+  }
+  for (int b0 = 0; b0 < p; b0 += kNB) {
+    const int bw = min(kNB, p - b0);
+    if (t < 64) {
+      // lane t holds row t of the block (indices clamped into the block, so
+      // every load is in bounds and issued before the sequential part)
+      double col[kNB];
+      const int rt = b0 + min(t, bw - 1);
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
+      double vl = t < bw ? v[b0 + t] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        if (j < bw) {
+          const double z = readlane_d(vl, j);
+          if (t > j) vl -= col[j] * z;
+        }
+      }
+      if (t < bw) v[b0 + t] = vl;
+    }
+    __syncthreads();
+    for (int i = b0 + bw + t; i < p; i += 256) {
+      double acc = v[i];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        const double a = A[i + (int64_t)(b0 + min(j, bw - 1)) * f];
+        acc -= a * (j < bw ? v[b0 + j] : 0.0);
+      }
+      v[i] = acc;
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < f; i += 256) {
+    if (i < p) x[b + i] = v[i];
+    else upd[u_off[s] + i - p] = v[i];
+  }
+}
+
+// Forward solve, part 2: item = (front s, chunk of 64 update rows):
+// upd_s[a] -= L21[a, :] y_s.  Each wave sums a quarter of the pivot columns
+// for the chunk's 64 rows (one row per lane); the quarters are added in order.
+__global__ void __launch_bounds__(256) k_g_fwd_gemv(const int *items, const int *c0, const int *nc, const int *fsz,
+                                                    const int64_t *f_off, const int *u_off, const double *F,
+                                                    const double *x, double *upd) {
+  extern __shared__ double ys[];
+  __shared__ double red[4][64];
+  const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
+  const int f = fsz[s], p = nc[s], r = f - p;
+  const double *A = F + f_off[s];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int j = t; j < p; j += 256) ys[j] = x[c0[s] + j];
+  __syncthreads();
+  const int a = chunk * 64 + lane;
+  const int ra = p + min(a, r - 1);
+  const int q = (p + 3) / 4, j0 = w * q, j1 = min(p, j0 + q);
+  double acc = 0.0;
+#pragma unroll 16
+  for (int j = j0; j < j1; ++j) acc += A[ra + (int64_t)j * f] * ys[j];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && a < r) upd[u_off[s] + a] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// Forward solve of the small fronts of a height (f <= 64), one wave per
+// front and four fronts per workgroup, with no workgroup barrier: lane l
+// holds v[l]; the children's update vectors are added through the wave's own
+// LDS slice; then for each pivot column j the lanes below j subtract
+// L[l, j] y_j (pivot rows and update rows alike).
+__global__ void __launch_bounds__(256) k_g_fwd_small(const int *fronts, int count, const int *c0, const int *nc,
+                                                     const int *fsz, const int64_t *f_off, const int *ch_ptr,
+                                                     const int *ch, const int *r_ptr, const int *rel,
+                                                     const int *u_off, const double *F, double *x, double *upd) {
+  __shared__ double sv[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + w;
+  if (idx >= count) return;  // the whole wave
+  const int s = fronts[idx];
+  const int f = fsz[s], p = nc[s], b = c0[s];
+  const double *A = F + f_off[s];
+  double *vs = sv[w];
+  vs[l] = l < p ? x[b + l] : 0.0;
+  wfence();
+  for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
+    const int c = ch[q], rc = fsz[c] - nc[c];  // rc <= f <= 64
+    if (l < rc) vs[rel[r_ptr[c] + l]] += upd[u_off[c] + l];
+    wfence();
+  }
+  double v = vs[l];
+  const int lr = min(l, f - 1);
+  double a_next = A[lr];
+  for (int j = 0; j < p; ++j) {
+    const double a = a_next;
+    a_next = A[lr + (int64_t)min(j + 1, p - 1) * f];
+    const double z = readlane_d(v, j);
+    if (l > j && l < f) v -= a * z;
+  }
+  if (l < p) x[b + l] = v;
+  else if (l < f) upd[u_off[s] + l - p] = v;
+}
+
+// Backward solve of the small fronts (f <= 64), one wave per front: lane l
+// holds y[l] (pivot rows) or x(R_s) (update rows); U12 x(R_s) is subtracted
+// column by column, then the upper pivot block is solved from the last row.
+__global__ void __launch_bounds__(256) k_g_bwd_small(const int *fronts, int count, const int *c0, const int *nc,
+                                                     const int *fsz, const int64_t *f_off, const int *r_ptr,
+                                                     const int *r_idx, const double *F, double *x) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + w;
+  if (idx >= count) return;
+  const int s = fronts[idx];
+  const int f = fsz[s], p = nc[s], b = c0[s], r = f - p;
+  const double *A = F + f_off[s];
+  double v = l < p ? x[b + l] : (l < f ? x[r_idx[r_ptr[s] + l - p]] : 0.0);
+  const int lr = min(l, p - 1);
+  for (int a = 0; a < r; ++a) {
+    const double u = A[lr + (int64_t)(p + a) * f];
+    const double z = readlane_d(v, p + a);
+    if (l < p) v -= u * z;
+  }
+  for (int j = p - 1; j >= 0; --j) {
+    const double u = A[lr + (int64_t)j * f];
+    if (l == j) v = v / u;
+    const double z = readlane_d(v, j);
+    if (l < j) v -= u * z;
+  }
+  if (l < p) x[b + l] = v;
+}
+
+// Backward solve (U x = y), part 1: item = (front s, chunk of 64 pivot rows):
+// x(cols s)[i] = y[i] - U12[i, :] x(R_s), x(R_s) being final (the ancestors
+// are done).  Waves split R_s in quarters, added in order.
+__global__ void __launch_bounds__(256) k_g_bwd_gemv(const int *items, const int *c0, const int *nc, const int *fsz,
+                                                    const int64_t *f_off, const int *r_ptr, const int *r_idx,
+                                                    const double *F, double *x) {
+  extern __shared__ double xr[];
+  __shared__ double red[4][64];
+  const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
+  const int f = fsz[s], p = nc[s], r = f - p;
+  const double *A = F + f_off[s];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int k = t; k < r; k += 256) xr[k] = x[r_idx[r_ptr[s] + k]];
+  __syncthreads();
+  const int i = chunk * 64 + lane;
+  const int ri = min(i, p - 1);
+  const int q = (r + 3) / 4, k0 = w * q, k1 = min(r, k0 + q);
+  double acc = 0.0;
+#pragma unroll 16
+  for (int k = k0; k < k1; ++k) acc += A[ri + (int64_t)(p + k) * f] * xr[k];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < p) x[c0[s] + i] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// Backward solve, part 2, one workgroup per front: the upper pivot block U11
+// in 32-wide blocks from the last, each block updating the pivot rows above.
+__global__ void __launch_bounds__(256) k_g_bwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
+                                                   const int64_t *f_off, const double *F, double *x) {
+  extern __shared__ double v[];
+  const int s = fronts[blockIdx.x];
+  const int f = fsz[s], p = nc[s], b = c0[s];
+  const double *A = F + f_off[s];
+  const int t = threadIdx.x;
+  for (int i = t; i < p; i += 256) v[i] = x[b + i];
+  __syncthreads();
+  for (int b0 = ((p - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
+    const int bw = min(kNB, p - b0);
+    if (t < 64) {
+      double col[kNB];  // row t of the block of U (clamped, as in the forward solve)
+      const int rt = b0 + min(t, bw - 1);
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
+      double vl = t < bw ? v[b0 + t] : 0.0;
+#pragma unroll
+      for (int j = kNB - 1; j >= 0; --j) {
+        if (j < bw) {
+          if (t == j) vl = vl / col[j];
+          const double z = readlane_d(vl, j);
+          if (t < j) vl -= col[j] * z;
+        }
+      }
+      if (t < bw) v[b0 + t] = vl;
+    }
+    __syncthreads();
+    for (int i = t; i < b0; i += 256) {
+      double acc = v[i];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        const double a = A[i + (int64_t)(b0 + min(j, bw - 1)) * f];
+        acc -= a * (j < bw ? v[b0 + j] : 0.0);
+      }
+      v[i] = acc;
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < p; i += 256) x[b + i] = v[i];
+}
+
+// PWL sources: u(t) and the slope on the piece holding tm
+__global__ void k_g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t,
+                            double tm, double *u, double *slope) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_src; q += gridDim.x * blockDim.x) {
+    const int lo = src_ptr[q], hi = src_ptr[q + 1] - 1;
+    double val, sl = 0.0;
+    if (t <= src_t[lo]) val = src_v[lo];
+    else if (t >= src_t[hi]) val = src_v[hi];
+    else {
+      int a = lo, b = hi;
+      while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (src_t[mid] <= t) a = mid; else b = mid;
+      }
+      val = src_v[a] + (t - src_t[a]) * ((src_v[a + 1] - src_v[a]) / (src_t[a + 1] - src_t[a]));
+    }
+    if (hi > lo && tm >= src_t[lo] && tm < src_t[hi]) {
+      int a = lo, b = hi;
+      while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (src_t[mid] <= tm) a = mid; else b = mid;
+      }
+      sl = (src_v[a + 1] - src_v[a]) / (src_t[a + 1] - src_t[a]);
+    }
+    u[q] = val;
+    slope[q] = sl;
+  }
+}
+
+// r = B u - G_lin x - I_dev(x) and bs = B s (the right-hand sides of w and p)
+__global__ void k_g_rhs(int n, const int *g_rowptr, const int *g_col, const double *g_val, const int *b_rowptr,
+                        const int *b_col, const double *b_val, const int *node_ptr, const int *node_code,
+                        const double *devI, const double *x, const double *u, const double *sl, double *r,
+                        double *bs) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double bu = 0.0, bsl = 0.0;
+    for (int e = b_rowptr[i]; e < b_rowptr[i + 1]; ++e) {
+      bu += b_val[e] * u[b_col[e]];
+      bsl += b_val[e] * sl[b_col[e]];
+    }
+    double gx = 0.0;
+    for (int e = g_rowptr[i]; e < g_rowptr[i + 1]; ++e) gx += g_val[e] * x[g_col[e]];
+    double id = 0.0;
+    for (int c = node_ptr[i]; c < node_ptr[i + 1]; ++c) {
+      const int code = node_code[c];
+      id += (code & 1) ? -devI[code >> 1] : devI[code >> 1];
+    }
+    r[i] = (bu - gx) - id;
+    bs[i] = bsl;
+  }
+}
+
+// y = alpha C x
+__global__ void k_g_spmv(int n, const int *rp, const int *ci, const double *val, const double *x, double alpha,
+                         double *y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) acc += val[e] * x[ci[e]];
+    y[i] = alpha * acc;
+  }
+}
+
+// partial[blk * ncol + c] = sum over the block's rows of V[:, c] . w (first
+// pass of V^T w over kRB blocks; the second pass adds the blocks in order)
+__global__ void __launch_bounds__(256) k_g_dots(int n, const double *V, int64_t ldv, int ncol, const double *w,
+                                                double *partial) {
+  __shared__ double red[4][64];
+  const int t = threadIdx.x;
+  for (int c0 = 0; c0 < ncol; c0 += 64) {
+    const int cw = min(64, ncol - c0);
+    for (int cc = 0; cc < cw; ++cc) {
+      double acc = 0.0;
+      const double *col = V + (int64_t)(c0 + cc) * ldv;
+      for (int i = blockIdx.x * 256 + t; i < n; i += gridDim.x * 256) acc += col[i] * w[i];
+      acc = wave_sum(acc);
+      if ((t & 63) == 0) red[t >> 6][cc] = acc;
+    }
+    __syncthreads();
+    if (t < cw) partial[(int64_t)blockIdx.x * ncol + c0 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    __syncthreads();
+  }
+}
+
+// out[c] = sum over blocks b (in order) of partial[b * ncol + c]
+__global__ void k_g_reduce(const double *partial, int nblk, int ncol, double *out) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * ncol + c];
+    out[c] = acc;
+  }
+}
+
+// partial[blk] = max over the block's rows of |x[i]| (NaN propagates)
+__global__ void __launch_bounds__(256) k_g_absmax(int n, const double *x, double *partial) {
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) m = nmax(m, fabs(x[i]));
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = nmax(nmax(red[0], red[1]), nmax(red[2], red[3]));
+}
+
+__global__ void k_g_maxreduce(const double *partial, int nblk, double *out) {
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int b = 0; b < nblk; ++b) m = nmax(m, partial[b]);
+    out[0] = m;
+  }
+}
+
+// w -= V[:, 0..ncol) hcoef
+__global__ void k_g_gemv_sub(int n, const double *V, int64_t ldv, int ncol, const double *hcoef, double *w) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double acc = w[i];
+    for (int c = 0; c < ncol; ++c) acc -= V[i + (int64_t)c * ldv] * hcoef[c];
+    w[i] = acc;
+  }
+}
+
+// Hessenberg column j after two Gram-Schmidt passes: H[0..j, j] = h1 + h2,
+// H[j+1, j] = ||w|| (sc[1] holds ||w||^2); sc[2] = 1 when the new vector is
+// a happy breakdown (||w|| <= breakdown max |H[0..j+1, 0..j]|), else sc[3] =
+// 1 / ||w|| (the scale of v_{j+1})
+__global__ void k_g_hcol(int j, const double *h1, const double *h2, double *H, double breakdown, double *sc) {
+  if (threadIdx.x != 0) return;
+  double hmax = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    const double v = h1[i] + h2[i];
+    H[i + j * kHLd] = v;
+  }
+  const double nrm = sqrt(sc[1]);
+  H[j + 1 + j * kHLd] = nrm;
+  for (int c = 0; c <= j; ++c)
+    for (int i = 0; i <= c + 1; ++i) hmax = nmax(hmax, fabs(H[i + c * kHLd]));
+  if (!(nrm > breakdown * hmax)) {
+    sc[2] = 1.0;
+    H[j + 1 + j * kHLd] = 0.0;
+  } else {
+    sc[2] = 0.0;
+    sc[3] = 1.0 / nrm;
+  }
+}
+
+// out = x * sc[idx]
+__global__ void k_g_scale(int n, const double *x, const double *sc, int idx, double *out) {
+  const double a = sc[idx];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = x[i] * a;
+}
+
+// sc[0] = ||v||_2 = sqrt(sc[1]); v_1 = v / sc[0] (zero vector: sc[0] = 0)
+__global__ void k_g_start(int n, const double *v, double *sc, double *v1) {
+  const double beta = sqrt(sc[1]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[0] = beta;
+  const double a = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v1[i] = v[i] * a;
+}
+
+// out = base + h p + beta V[:, 0..m) d   (p may be null: no h p term)
+__global__ void k_g_combine(int n, const double *base, const double *p, double h, const double *V, int64_t ldv,
+                            int m, const double *beta, const double *d, double *out) {
+  const double bt = beta[0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < m; ++c) acc += V[i + (int64_t)c * ldv] * d[c];
+    double v = base ? base[i] : 0.0;
+    if (p) v += h * p[i];
+    out[i] = v + bt * acc;
+  }
+}
+
+// y += a x
+__global__ void k_g_axpy(int n, double a, const double *x, double *y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] += a * x[i];
+}
+
+// out = a - b
+__global__ void k_g_sub(int n, const double *a, const double *b, double *out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = a[i] - b[i];
+}
+
+// dF = J_dev(x_k)(x1 - x_k) - (I_dev(x1) - I_dev(x_k)) per node
+__global__ void k_g_dF(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,
+                       const double *devI0, const double *devI1, const double *xk, const double *x1, double *out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int c = node_ptr[i]; c < node_ptr[i + 1]; ++c) {
+      const int code = node_code[c], k = code >> 1;
+      double lin = 0.0;
+      for (int v = 0; v < 3; ++v) {
+        const int nd = dev_node[3 * k + v];
+        if (nd >= 0) lin += devD[3 * k + v] * (x1[nd] - xk[nd]);
+      }
+      const double term = lin - (devI1[k] - devI0[k]);
+      acc += (code & 1) ? -term : term;
+    }
+    out[i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr int kTB = 256;
+int blocks_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + kTB - 1) / kTB, 1), 4096); }
+}  // namespace
+
+hipError_t g_fill(double *p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_fill, dim3(blocks_for(n)), dim3(kTB), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t g_gather(int n, const int *map, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_gather, dim3(blocks_for(n)), dim3(kTB), 0, s, n, map, x, y);
+  return hipGetLastError();
+}
+hipError_t g_scatter(int n, const int *map, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_scatter, dim3(blocks_for(n)), dim3(kTB), 0, s, n, map, x, y);
+  return hipGetLastError();
+}
+hipError_t g_stamp(int n_dev, const int *dev_node, const double *par, const double *x, double vdd, double *devI,
+                   double *devD, hipStream_t s) {
+  if (n_dev == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_stamp, dim3(blocks_for(n_dev)), dim3(kTB), 0, s, n_dev, dev_node, par, x, vdd, devI, devD);
+  return hipGetLastError();
+}
+hipError_t g_assemble(int n_ent, const int64_t *ent_pos, const int *ent_row, const int *ent_g, const int *ent_jptr,
+                      const int *ent_jcode, const double *g_val, const double *devD, double *F,
+                      unsigned long long *rowmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_assemble, dim3(blocks_for(n_ent)), dim3(kTB), 0, s, n_ent, ent_pos, ent_row, ent_g,
+                     ent_jptr, ent_jcode, g_val, devD, F, rowmax);
+  return hipGetLastError();
+}
+hipError_t g_extend(int n_items, const int *items, const int *nc, const int *fsz, const int *parent,
+                    const int64_t *f_off, const int *r_ptr, const int *rel, double *F, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_extend, dim3(n_items), dim3(256), 0, s, items, nc, fsz, parent, f_off, r_ptr, rel, F);
+  return hipGetLastError();
+}
+hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *items, int k0, int C, int fuse,
+                   const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
+                   const unsigned long long *rowmax, double piv_tol, double *F, int *bad, hipStream_t s) {
+  if (n_fronts == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_diag, dim3(n_fronts), dim3(64), 0, s, fronts, k0, c0, nc, fsz, f_off, rowmax, piv_tol, F,
+                     bad);
+  hipLaunchKernelGGL(k_g_panel, dim3(n_items), dim3(256), sizeof(double) * 2 * (size_t)C * (kNB + 1), s, items, k0,
+                     C, fuse, nc, fsz, f_off, F);
+  return hipGetLastError();
+}
+hipError_t g_set_limits() {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(k_g_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * 2 * 128 * (kNB + 1)));
+}
+hipError_t g_update(int n_items, const int *items, int k0, const int *nc, const int *fsz, const int64_t *f_off,
+                    double *F, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_update, dim3(n_items), dim3(256), 0, s, items, k0, nc, fsz, f_off, F);
+  return hipGetLastError();
+}
+hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
+                 int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
+                 const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
+                 double *x, double *upd, hipStream_t s) {
+  if (n_small > 0)
+    hipLaunchKernelGGL(k_g_fwd_small, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz, f_off,
+                       ch_ptr, ch, r_ptr, rel, u_off, F, x, upd);
+  if (n_big > 0)
+    hipLaunchKernelGGL(k_g_fwd_tri, dim3(n_big), dim3(256), sizeof(double) * (size_t)max_f, s, big, c0, nc, fsz,
+                       f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, upd);
+  if (n_items > 0)
+    hipLaunchKernelGGL(k_g_fwd_gemv, dim3(n_items), dim3(256), sizeof(double) * (size_t)max_nc, s, items, c0, nc,
+                       fsz, f_off, u_off, F, x, upd);
+  return hipGetLastError();
+}
+hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
+                 int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
+                 const int *r_ptr, const int *r_idx, const double *F, double *x, hipStream_t s) {
+  if (n_small > 0)
+    hipLaunchKernelGGL(k_g_bwd_small, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz, f_off,
+                       r_ptr, r_idx, F, x);
+  if (n_items > 0)
+    hipLaunchKernelGGL(k_g_bwd_gemv, dim3(n_items), dim3(256), sizeof(double) * (size_t)max_f, s, items, c0, nc, fsz,
+                       f_off, r_ptr, r_idx, F, x);
+  if (n_big > 0)
+    hipLaunchKernelGGL(k_g_bwd_tri, dim3(n_big), dim3(256), sizeof(double) * (size_t)max_nc, s, big, c0, nc, fsz,
+                       f_off, F, x);
+  return hipGetLastError();
+}
+hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,
+                     double *u, double *slope, hipStream_t s) {
+  if (n_src == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_sources, dim3(blocks_for(n_src)), dim3(kTB), 0, s, n_src, src_ptr, src_t, src_v, t, tm, u,
+                     slope);
+  return hipGetLastError();
+}
+hipError_t g_rhs(int n, const int *g_rowptr, const int *g_col, const double *g_val, const int *b_rowptr,
+                 const int *b_col, const double *b_val, const int *node_ptr, const int *node_code, const double *devI,
+                 const double *x, const double *u, const double *sl, double *r, double *bs, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_rhs, dim3(blocks_for(n)), dim3(kTB), 0, s, n, g_rowptr, g_col, g_val, b_rowptr, b_col,
+                     b_val, node_ptr, node_code, devI, x, u, sl, r, bs);
+  return hipGetLastError();
+}
+hipError_t g_spmv(int n, const int *rp, const int *ci, const double *val, const double *x, double alpha, double *y,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_g_spmv, dim3(blocks_for(n)), dim3(kTB), 0, s, n, rp, ci, val, x, alpha, y);
+  return hipGetLastError();
+}
+// out[0..ncol) = V[:, 0..ncol)^T w, fixed summation order; partial: kRB * ncol doubles
+hipError_t g_dots(int n, const double *V, int64_t ldv, int ncol, const double *w, double *partial, double *out,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_g_dots, dim3(kRB), dim3(256), 0, s, n, V, ldv, ncol, w, partial);
+  hipLaunchKernelGGL(k_g_reduce, dim3(1), dim3(64), 0, s, partial, kRB, ncol, out);
+  return hipGetLastError();
+}
+hipError_t g_absmax(int n, const double *x, double *partial, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_absmax, dim3(kRB), dim3(256), 0, s, n, x, partial);
+  hipLaunchKernelGGL(k_g_maxreduce, dim3(1), dim3(64), 0, s, partial, kRB, out);
+  return hipGetLastError();
+}
+hipError_t g_gemv_sub(int n, const double *V, int64_t ldv, int ncol, const double *hcoef, double *w, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_gemv_sub, dim3(blocks_for(n)), dim3(kTB), 0, s, n, V, ldv, ncol, hcoef, w);
+  return hipGetLastError();
+}
+hipError_t g_hcol(int j, const double *h1, const double *h2, double *H, double breakdown, double *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_hcol, dim3(1), dim3(64), 0, s, j, h1, h2, H, breakdown, sc);
+  return hipGetLastError();
+}
+hipError_t g_scale(int n, const double *x, const double *sc, int idx, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_scale, dim3(blocks_for(n)), dim3(kTB), 0, s, n, x, sc, idx, out);
+  return hipGetLastError();
+}
+hipError_t g_start(int n, const double *v, double *sc, double *v1, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_start, dim3(blocks_for(n)), dim3(kTB), 0, s, n, v, sc, v1);
+  return hipGetLastError();
+}
+hipError_t g_combine(int n, const double *base, const double *p, double h, const double *V, int64_t ldv, int m,
+                     const double *beta, const double *d, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_combine, dim3(blocks_for(n)), dim3(kTB), 0, s, n, base, p, h, V, ldv, m, beta, d, out);
+  return hipGetLastError();
+}
+hipError_t g_axpy(int n, double a, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_axpy, dim3(blocks_for(n)), dim3(kTB), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+hipError_t g_sub(int n, const double *a, const double *b, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_sub, dim3(blocks_for(n)), dim3(kTB), 0, s, n, a, b, out);
+  return hipGetLastError();
+}
+hipError_t g_dF(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,
+                const double *devI0, const double *devI1, const double *xk, const double *x1, double *out,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_g_dF, dim3(blocks_for(n)), dim3(kTB), 0, s, n, node_ptr, node_code, dev_node, devD, devI0,
+                     devI1, xk, x1, out);
+  return hipGetLastError();
+}
+
+}  // namespace expri

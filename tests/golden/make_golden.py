@@ -108,6 +108,24 @@ def make_grid(name: str):
           f"total {t_all:.1f} s -> {path}")
 
 
+# the fresh circuit of the learned-controller test: the oracle's adaptive run
+# at a 10x tighter budget (E_rr = 1e-7 V), its final state the accuracy
+# reference of the GPU runs at E_rr = 1e-6 V
+def make_tight(name: str = "fresh120_tight"):
+    net = netgen.inverter_chain(seed=6000, n_stages=120)
+    t0 = time.time()
+    o = Oracle(net, Options(tol=1e-7))
+    x0 = o.dc()
+    run = o.run(x0, keep=None)
+    out = dict(x0=x0, t_final=run.t[-1], steps=len(run.t), x_final=run.x_final, seconds=time.time() - t0)
+    path = os.path.join(HERE, f"{name}.npz")
+    np.savez_compressed(path, **out)
+    print(f"{name}: {len(run.t)} steps at E_rr = 1e-7 V, {time.time() - t0:.1f} s -> {path}")
+
+
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(WORKLOADS) + list(GRIDS)):
-        (make_grid if name in GRIDS else make)(name)
+    for name in (sys.argv[1:] or list(WORKLOADS) + list(GRIDS) + ["fresh120_tight"]):
+        if name == "fresh120_tight":
+            make_tight(name)
+        else:
+            (make_grid if name in GRIDS else make)(name)

@@ -5,8 +5,11 @@ circuit it has not seen.
 Gain is time to solution at equal accuracy: the kernel time of the whole
 transient with the learned controller against the paper's alpha/beta rule on
 the same fresh circuit, both with E_rr = 1e-6 V; accuracy is the final state
-against a run with a 10x tighter budget (the local error test judges every
-step in both modes, so both land within a few E_rr of it)."""
+against the oracle's adaptive run with a 10x tighter budget (a stored result
+of tests/golden/make_golden.py); the local error test judges every step in
+both modes."""
+import os
+
 import numpy as np
 import pytest
 
@@ -66,7 +69,10 @@ def test_learned_controller_beats_plain_control_on_a_fresh_circuit():
     params, norm, losses = control.train(X, T, epochs=40, batch=4096, lr=1e-3)
     assert losses[-1] < 0.2 * losses[0]
     fresh = netgen.inverter_chain(seed=6000, n_stages=120)
-    _, _, ref, _ = _run(E, fresh, E_rr=1e-7)
+    # the oracle's run at a 10x tighter budget (E_rr = 1e-7 V) to T
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "fresh120_tight.npz"), allow_pickle=False)
+    assert g["t_final"] == fresh.T
+    ref = g["x_final"]
     plain, t_plain, x_plain, _ = _run(E, fresh)
     learned, t_learned, x_learned, tr = _run(E, fresh, (params, norm), safety=1.0)
     e_plain = np.abs(x_plain - ref).max()
@@ -77,4 +83,6 @@ def test_learned_controller_beats_plain_control_on_a_fresh_circuit():
     assert learned["status"] == 0 and tr["t"][-1] == fresh.T
     assert learned["rejects"] < 0.5 * plain["rejects"]
     assert t_learned < 0.95 * t_plain
-    assert e_learned <= max(3.0 * e_plain, 2e-5)
+    # equal accuracy: the learned run is no further from the tight oracle
+    # reference than the paper's control, up to where each grid falls
+    assert e_learned <= max(1.5 * e_plain, 1e-6)

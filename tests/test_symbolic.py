@@ -269,3 +269,109 @@ def test_schedule_rejects_bad_slot_count():
     from paper_1511_04515_amd import ExpriError
     with pytest.raises(ExpriError):
         symbolic_analysis(netgen.config(2), block_size=512, solve_slots=3)
+
+
+def _frontal_lu_emulated(net, x, leaf):
+    """The multifrontal factorisation the GPU runs, emulated in NumPy on the
+    host analysis: assembly of G_k through the entry map, extend-add of the
+    children's Schur complements through rel, partial LU of every front.
+    Returns (L, U, G_k in the new order)."""
+    import paper_1511_04515_amd as E
+    from oracle import device_currents
+    fa = E.frontal_analysis(net, leaf=leaf)
+    n = net.n
+    perm = fa["perm"]
+    I, Jd = device_currents(net, x)
+    Gk = (net.G + Jd).toarray()[np.ix_(perm, perm)]
+    T = len(fa["c0"])
+    c0, nc, fsz, f_off = fa["c0"], fa["nc"], fa["fsz"], fa["f_off"]
+    r_ptr, r_idx, rel = fa["r_ptr"], fa["r_idx"], fa["rel"]
+
+    def index_set(s):
+        return np.concatenate([np.arange(c0[s], c0[s] + nc[s]), r_idx[r_ptr[s]:r_ptr[s + 1]]])
+
+    # the assembly map covers every nonzero of G_k exactly once
+    F = np.zeros(int(f_off[-1] + fsz[-1] ** 2))
+    pos = fa["ent_pos"]
+    assert len(np.unique(pos)) == len(pos)
+    s_of = np.searchsorted(f_off, pos, side="right") - 1
+    covered = np.zeros((n, n), bool)
+    for e in range(len(pos)):
+        s = s_of[e]
+        loc = pos[e] - f_off[s]
+        li, lj = loc % fsz[s], loc // fsz[s]
+        Is = index_set(s)
+        i, j = Is[li], Is[lj]
+        assert fa["ent_row"][e] == i
+        F[pos[e]] = Gk[i, j]
+        covered[i, j] = True
+    assert np.all(covered[Gk != 0])
+    L = np.eye(n)
+    U = np.zeros((n, n))
+    S = {}
+    children = [[] for _ in range(T)]
+    for s in range(T):
+        if fa["parent"][s] >= 0:
+            children[fa["parent"][s]].append(s)
+    for s in range(T):  # postorder: children first
+        f, p = fsz[s], nc[s]
+        Fs = F[f_off[s]:f_off[s] + f * f].reshape(f, f, order="F").copy()
+        for c in children[s]:
+            rl = rel[r_ptr[c]:r_ptr[c + 1]]
+            Fs[np.ix_(rl, rl)] += S.pop(c)
+        for k in range(p):
+            Fs[k + 1:, k] /= Fs[k, k]
+            Fs[k + 1:, k + 1:] -= np.outer(Fs[k + 1:, k], Fs[k, k + 1:])
+        Is = index_set(s)
+        cols = Is[:p]
+        L[np.ix_(Is, cols)] = np.tril(Fs[:, :p], -1) + np.vstack([np.eye(p), np.zeros((f - p, p))])
+        U[np.ix_(cols, Is)] = np.triu(Fs[:p, :])
+        S[s] = Fs[p:, p:]
+    assert not S or all(v.size == 0 for v in S.values())
+    return L, U, Gk, fa
+
+
+@pytest.mark.parametrize("which,leaf", [("grid", 4), ("grid", 16), ("chain", 3)])
+def test_multifrontal_analysis_reproduces_lu_of_gk(which, leaf):
+    # the fronts, their row structures, the extend-add indices and the
+    # assembly map give L U = P G_k P^T (LU_decompose(G_k) of Algorithm 2)
+    if which == "grid":
+        net = netgen.power_grid(side=10, n_drivers=6, T=1e-9)
+    else:
+        net = netgen.inverter_chain(seed=3, n_stages=8)
+    x = np.random.default_rng(4).uniform(0.0, 1.0, net.n)
+    L, U, Gk, fa = _frontal_lu_emulated(net, x, leaf)
+    assert np.linalg.norm(L @ U - Gk) <= 1e-12 * np.linalg.norm(Gk)
+    # the fronts' heights order the tree: a parent is higher than each child
+    par, hgt = fa["parent"], fa["height"]
+    for s, p in enumerate(par):
+        if p >= 0:
+            assert hgt[p] > hgt[s] and p > s
+    # stored factor entries: sum over fronts of nc (2 f - nc)
+    assert fa["stats"]["lu_entries"] == int(np.sum(fa["nc"] * (2 * fa["fsz"] - fa["nc"])))
+
+
+def test_multifrontal_analysis_of_the_full_power_grid():
+    # 2 x 512 x 512 layers + 2,000 drivers: 528,288 unknowns.  The analysis is
+    # a permutation, every front's row structure lies in its ancestors, and
+    # the stored factor entries stay within the nested-dissection fill scale
+    import paper_1511_04515_amd as E
+    net = netgen.config(3)
+    fa = E.frontal_analysis(net, leaf=16)
+    assert net.n == 528288 and np.array_equal(np.sort(fa["perm"]), np.arange(net.n))
+    st = fa["stats"]
+    assert st["lu_entries"] < 80e6 and st["max_front"] < 2000
+    c0, nc, par = fa["c0"], fa["nc"], fa["parent"]
+    assert c0[0] == 0 and np.all(c0[1:] == c0[:-1] + nc[:-1]) and c0[-1] + nc[-1] == net.n
+    r_ptr, r_idx = fa["r_ptr"], fa["r_idx"]
+    owner = fa["owner"]
+    rng = np.random.default_rng(0)
+    for s in rng.choice(len(c0), 200, replace=False):
+        R = r_idx[r_ptr[s]:r_ptr[s + 1]]
+        assert np.all(np.diff(R) > 0) and (R.size == 0 or R[0] >= c0[s] + nc[s])
+        anc = set()
+        a = par[s]
+        while a >= 0:
+            anc.add(int(a))
+            a = par[a]
+        assert all(int(owner[j]) in anc for j in R)
