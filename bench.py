@@ -40,11 +40,12 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 1 GiB device copy (--copy-bytes).  It is reported
 # only while the kernel sources hash to the value it was measured on.
 PMC_TRAFFIC = {"sources": ("paper_1511_04515_amd/csrc/engine.hip", "paper_1511_04515_amd/csrc/layout.hpp",
-                           "paper_1511_04515_amd/csrc/mlp.hpp"),
-               "sha256_16": "93e43cfa50f128aa", "workload": "batch", "controller": "learned",
+                           "paper_1511_04515_amd/csrc/mlp.hpp", "paper_1511_04515_amd/csrc/devcommon.hpp",
+                           "paper_1511_04515_amd/csrc/mosfet.hpp"),
+               "sha256_16": "711ec3c419adeed2", "workload": "batch", "controller": "learned",
                "kernel": "k_run<512>",
-               "fetch_kib": 12574483506.5, "fetch_factor": 2.0,
-               "write_kib": 1849895201.9375, "write_factor": 1.0}
+               "fetch_kib": 12580346293.5, "fetch_factor": 2.0,
+               "write_kib": 1849126158.0625, "write_factor": 1.0}
 
 
 def pmc_traffic_bytes(workload, learned, nlaunch, kernel):
@@ -66,6 +67,10 @@ def workload(name):
         nets = netgen.config(4)
         desc = ("batch: 256 variants of a 200-stage inverter chain (4,201 nodes, shared sparsity) "
                 "+ 64 chains of 50-400 stages; level-1 MOSFETs; T = 4 ns; E_rr = 1e-6 V")
+    elif name == "variants":
+        nets = netgen.config(4)[:256]
+        desc = ("the batch's 256 variants of a 200-stage inverter chain (4,201 nodes, shared sparsity); "
+                "T = 4 ns; E_rr = 1e-6 V")
     elif name == "chain":
         nets = [netgen.config(2)]
         desc = "one 200-stage inverter chain (4,201 nodes, 400 MOSFETs); T = 4 ns; E_rr = 1e-6 V"
@@ -276,6 +281,8 @@ def main():
     ap.add_argument("--controller", default="learned", choices=("learned", "plain"))
     ap.add_argument("--safety", type=float, default=1.0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--private-patterns", action="store_true",
+                    help="give every instance its own copy of the symbolic data (index arrays not shared)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--grid-steps", type=int, default=20,
@@ -330,7 +337,7 @@ def main():
         params, norm, ctrl_info = train_controller(log)
         ctrl = (params, norm)
     s = E.Solver(nets, probes=[np.zeros(0, np.int32)] * len(nets), trace_cap=8192,
-                 block_size=args.block_size)
+                 block_size=args.block_size, private_patterns=int(args.private_patterns))
     x0 = s.zeros()
     s.dc(x0)
     xs = [x.clone() for x in x0]

@@ -134,6 +134,10 @@ typedef struct {
    * run_noalloc / lu_pattern) */
   int32_t engine;
   double gamma;
+  /* 1: every instance gets its own copy of the symbolic data even when it
+   * shares its pattern with another (a measurement aid: the same batch with
+   * and without one shared copy of the index arrays); default 0 */
+  int32_t private_patterns;
 } expri_opts;
 
 /* Counters of the last transient or DC call of one instance. */

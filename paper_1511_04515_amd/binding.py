@@ -70,7 +70,8 @@ class Opts(C.Structure):
                 ("grow_if_rejects_lt", C.c_int32), ("m_max", C.c_int32),
                 ("block_size", C.c_int32), ("trace_cap", C.c_int32),
                 ("erc", C.c_int32), ("solve_slots", C.c_int32),
-                ("max_workgroups", C.c_int32), ("engine", C.c_int32), ("gamma", C.c_double)]
+                ("max_workgroups", C.c_int32), ("engine", C.c_int32), ("gamma", C.c_double),
+                ("private_patterns", C.c_int32)]
 
 
 class RunInfo(C.Structure):

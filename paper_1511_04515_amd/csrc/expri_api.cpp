@@ -663,6 +663,7 @@ expri_status expri_default_opts(expri_opts *o) {
   o->solve_slots = 0;
   o->max_workgroups = 0;
   o->engine = 0;
+  o->private_patterns = 0;
   o->gamma = 0.1;
   return EXPRI_OK;
 }
@@ -683,7 +684,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       (op.erc != 0 && op.erc != 1) || !std::isfinite(op.gamma) ||
       (op.solve_slots != 0 && op.solve_slots != 1 && op.solve_slots != 2 && op.solve_slots != 4 &&
        op.solve_slots != 8) ||
-      op.max_workgroups < 0 || op.engine < 0 || op.engine > 2 ||
+      op.max_workgroups < 0 || op.engine < 0 || op.engine > 2 || (op.private_patterns != 0 && op.private_patterns != 1) ||
       (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
     *out = c.release();
     (*out)->err = "invalid options";
@@ -708,7 +709,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     const PatternInput pin = pattern_input(K);
     const uint64_t h = pattern_hash(pin);
     int pid;
-    auto it = by_hash.find(h);
+    auto it = op.private_patterns ? by_hash.end() : by_hash.find(h);
     if (it != by_hash.end()) {
       pid = it->second;
       const Symbolic &S = c->pats[pid].sym;
