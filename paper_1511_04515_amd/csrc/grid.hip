@@ -117,6 +117,31 @@ __global__ void __launch_bounds__(256) k_g_extend(const int *items, const int *n
   }
 }
 
+// The extend-add of the small children (update matrices of at most 32 x 32):
+// one workgroup per parent adds its small children's Schur complements in
+// order, with a barrier between children (two children may reach the same
+// parent entry).  The larger children go through k_g_extend passes.
+__global__ void __launch_bounds__(256) k_g_extend_small(const int *parents, const int *nc, const int *fsz,
+                                                        const int64_t *f_off, const int *ch_ptr, const int *ch,
+                                                        const int *r_ptr, const int *rel, double *F) {
+  const int p = parents[blockIdx.x];
+  const int fp = fsz[p];
+  double *P = F + f_off[p];
+  const int t = threadIdx.x;
+  for (int q = ch_ptr[p]; q < ch_ptr[p + 1]; ++q) {
+    const int c = ch[q];
+    const int fc = fsz[c], ncc = nc[c], r = fc - ncc;
+    if (r > kET) continue;
+    const double *S = F + f_off[c] + (int64_t)ncc * fc + ncc;
+    const int *rl = rel + r_ptr[c];
+    for (int e = t; e < r * r; e += 256) {
+      const int a = e % r, b = e / r;
+      P[rl[a] + (int64_t)rl[b] * fp] += S[a + (int64_t)b * fc];
+    }
+    __syncthreads();
+  }
+}
+
 // Step k0 of the partial factorisation, part 1, one workgroup per front: LU
 // of the diagonal block D = F[k0.., k0..] (kb x kb, kb = min(32, nc - k0))
 // without pivoting, stored in place.  A pivot with |u| <= piv_tol * rowmax
@@ -129,6 +154,8 @@ __global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const 
   const int f = fsz[s], kb = min(kNB, nc[s] - k0);
   double *A = F + f_off[s];
   const int t = threadIdx.x;
+  // the row maxima of the block's rows, for the pivot test after the loop
+  const double rm = t < kb ? __longlong_as_double((long long)rowmax[c0[s] + k0 + t]) : 0.0;
   for (int e = t; e < kNB * kNB; e += 64) {
     const int i = e % kNB, j = e / kNB;
     Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
@@ -149,10 +176,6 @@ __global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const 
       }
       wfence();
       const double piv = Dm[p][p];
-      if (t == 0) {
-        const double rm = __longlong_as_double((long long)rowmax[c0[s] + k0 + p]);
-        if (!(fabs(piv) > piv_tol * rm)) atomicCAS(bad, 0, 1 + c0[s] + k0 + p);
-      }
       if (t > p && t < kb) {
         const double l = rw[p] / piv;
         rw[p] = l;
@@ -167,6 +190,10 @@ __global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const 
     for (int j = 0; j < kNB; ++j) Dm[t][j] = rw[j];
   }
   wfence();
+  // pivot test (static pivoting): |u_tt| must exceed piv_tol times the row's
+  // largest assembled magnitude; the first failing row of the block is kept
+  const unsigned long long weak = __ballot(t < kb && !(fabs(Dm[t][t]) > piv_tol * rm));
+  if (weak != 0ull && t == __ffsll((long long)weak) - 1) atomicCAS(bad, 0, 1 + c0[s] + k0 + t);
   for (int e = t; e < kb * kb; e += 64) {
     const int i = e % kb, j = e / kb;
     A[(k0 + i) + (int64_t)(k0 + j) * f] = Dm[i][j];
@@ -192,33 +219,44 @@ __global__ void __launch_bounds__(256) k_g_panel(const int *items, int k0, int C
   const int o = k0 + kb + chunk * C;
   const int cnt = min(C, f - o);
   if (cnt <= 0) return;  // the whole workgroup
+  // the factored diagonal block, padded to kNB x kNB with the identity so
+  // that the solves below run over all kNB columns with fixed bounds (the
+  // padding columns of the panels are zero and stay zero)
   for (int e = t; e < kNB * kNB; e += 256) {
     const int i = e % kNB, j = e / kNB;
-    Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
+    Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : (i == j ? 1.0 : 0.0);
   }
   // C rows of L21 in Pn[0..C), C columns of U12 in Pn[C..2C)
   for (int e = t; e < C * kNB; e += 256) {
     const int i = e % C, j = e / C;
-    if (i < cnt && j < kb) Pn[i][j] = A[(o + i) + (int64_t)(k0 + j) * f];
+    Pn[i][j] = (i < cnt && j < kb) ? A[(o + i) + (int64_t)(k0 + j) * f] : 0.0;
     const int jj = e % kNB, c = e / kNB;
-    if (c < cnt && jj < kb) Pn[C + c][jj] = A[(k0 + jj) + (int64_t)(o + c) * f];
+    Pn[C + c][jj] = (c < cnt && jj < kb) ? A[(k0 + jj) + (int64_t)(o + c) * f] : 0.0;
   }
   __syncthreads();
-  // each row of L21 (l U_D = a) and column of U12 (L_D u = a) is solved
-  // right-looking: after entry j is final, the later entries of the same row
-  // are updated with it (independent LDS updates, so they overlap)
-  if (t < cnt) {
-    for (int j = 0; j < kb; ++j) {
-      const double l = Pn[t][j] / Dm[j][j];
-      Pn[t][j] = l;
-      for (int jj = j + 1; jj < kb; ++jj) Pn[t][jj] -= l * Dm[j][jj];
+  // each row of L21 (l U_D = a) and column of U12 (L_D u = a) is solved by
+  // one thread in registers, right-looking: once entry j is final the later
+  // entries are updated with it; the block's entries are LDS broadcasts
+  if (t < cnt || (t >= C && t - C < cnt)) {
+    const bool row = t < C;
+    double r[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) r[j] = Pn[t][j];
+    if (row) {
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        r[j] /= Dm[j][j];
+#pragma unroll
+        for (int jj = j + 1; jj < kNB; ++jj) r[jj] -= r[j] * Dm[j][jj];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kNB - 1; ++j)
+#pragma unroll
+        for (int jj = j + 1; jj < kNB; ++jj) r[jj] -= Dm[jj][j] * r[j];
     }
-  } else if (t >= C && t - C < cnt) {
-    const int q = t - C;
-    for (int j = 0; j < kb - 1; ++j) {
-      const double u = Pn[C + q][j];
-      for (int jj = j + 1; jj < kb; ++jj) Pn[C + q][jj] -= Dm[jj][j] * u;
-    }
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) Pn[t][j] = r[j];
   }
   __syncthreads();
   for (int e = t; e < C * kNB; e += 256) {
@@ -251,18 +289,11 @@ __global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, cons
   const int i0 = o + (tile & 0xFFFF) * kGT, j0 = o + (tile >> 16) * kGT;
   double *A = F + f_off[s];
   const int t = threadIdx.x;
-  for (int e = t; e < kGT * kNB; e += 256) {
-    const int i = e % kGT, k = e / kGT;
-    As[i][k] = (i0 + i < f && k < kb) ? A[(i0 + i) + (int64_t)(k0 + k) * f] : 0.0;
-  }
-  for (int e = t; e < kNB * kGT; e += 256) {
-    const int k = e % kNB, j = e / kNB;
-    Bs[k][j] = (j0 + j < f && k < kb) ? A[(k0 + k) + (int64_t)(j0 + j) * f] : 0.0;
-  }
-  __syncthreads();
   const int lane = t & 63, wave = t >> 6;
   const int r = lane & 15, q = lane >> 4;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // the tile's loads are issued first, so that their latency overlaps the
+  // staging of the panels
   dbl4 acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -273,6 +304,15 @@ __global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, cons
         const int i = i0 + wi + 16 * mi + q + 4 * v, j = j0 + wj + 16 * ni + r;
         acc[mi][ni][v] = (i < f && j < f) ? A[i + (int64_t)j * f] : 0.0;
       }
+  for (int e = t; e < kGT * kNB; e += 256) {
+    const int i = e % kGT, k = e / kGT;
+    As[i][k] = (i0 + i < f && k < kb) ? A[(i0 + i) + (int64_t)(k0 + k) * f] : 0.0;
+  }
+  for (int e = t; e < kNB * kGT; e += 256) {
+    const int k = e % kNB, j = e / kNB;
+    Bs[k][j] = (j0 + j < f && k < kb) ? A[(k0 + k) + (int64_t)(j0 + j) * f] : 0.0;
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < kNB; k += 4) {
     double a[2], b[2];
@@ -754,6 +794,13 @@ hipError_t g_extend(int n_items, const int *items, const int *nc, const int *fsz
                     const int64_t *f_off, const int *r_ptr, const int *rel, double *F, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   hipLaunchKernelGGL(k_g_extend, dim3(n_items), dim3(256), 0, s, items, nc, fsz, parent, f_off, r_ptr, rel, F);
+  return hipGetLastError();
+}
+hipError_t g_extend_small(int n_parents, const int *parents, const int *nc, const int *fsz, const int64_t *f_off,
+                          const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, double *F, hipStream_t s) {
+  if (n_parents == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_extend_small, dim3(n_parents), dim3(256), 0, s, parents, nc, fsz, f_off, ch_ptr, ch, r_ptr,
+                     rel, F);
   return hipGetLastError();
 }
 hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *items, int k0, int C, int fuse,

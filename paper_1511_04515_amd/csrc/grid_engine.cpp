@@ -19,6 +19,8 @@ hipError_t g_assemble(int n_ent, const int64_t *ent_pos, const int *ent_row, con
                       unsigned long long *rowmax, hipStream_t s);
 hipError_t g_extend(int n_items, const int *items, const int *nc, const int *fsz, const int *parent,
                     const int64_t *f_off, const int *r_ptr, const int *rel, double *F, hipStream_t s);
+hipError_t g_extend_small(int n_parents, const int *parents, const int *nc, const int *fsz, const int64_t *f_off,
+                          const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, double *F, hipStream_t s);
 hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *items, int k0, int C, int fuse,
                    const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                    const unsigned long long *rowmax, double piv_tol, double *F, int *bad, hipStream_t s);
@@ -213,13 +215,37 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       maxch = std::max(maxch, fs.ch_ptr[s_ + 1] - fs.ch_ptr[s_]);
       maxnc = std::max(maxnc, fs.nc[s_]);
     }
+    // children with update matrices of at most 32 x 32 are added by one
+    // workgroup per parent; the larger ones in passes of 32 x 32 tiles, the
+    // pass-th large child of every parent in pass `pass`
+    auto big_child = [&](int c) { return fs.fsz[c] - fs.nc[c] > 32; };
+    {
+      const size_t at = pool.size();
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int s_ = fs.lev_front[q];
+        bool any = false;
+        for (int e = fs.ch_ptr[s_]; e < fs.ch_ptr[s_ + 1]; ++e) any = any || !big_child(fs.ch[e]);
+        if (any) pool.push_back(s_);
+      }
+      L.n_small_parents = (int32_t)(pool.size() - at);
+      fix.push_back({at, nullptr});
+    }
+    maxch = 0;
+    for (int q = L.first; q < L.first + L.count; ++q) {
+      const int s_ = fs.lev_front[q];
+      int nb = 0;
+      for (int e = fs.ch_ptr[s_]; e < fs.ch_ptr[s_ + 1]; ++e) nb += big_child(fs.ch[e]);
+      maxch = std::max(maxch, nb);
+    }
     L.extend.resize(maxch);
     for (int pass = 0; pass < maxch; ++pass) {
       const size_t at = pool.size();
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int s_ = fs.lev_front[q];
-        if (fs.ch_ptr[s_ + 1] - fs.ch_ptr[s_] <= pass) continue;
-        const int c = fs.ch[fs.ch_ptr[s_] + pass];
+        int c = -1;
+        for (int e = fs.ch_ptr[s_], k = 0; e < fs.ch_ptr[s_ + 1]; ++e)
+          if (big_child(fs.ch[e]) && k++ == pass) { c = fs.ch[e]; break; }
+        if (c < 0) continue;
         const int r = fs.fsz[c] - fs.nc[c];
         const int nt = (r + 31) / 32;
         for (int tj = 0; tj < nt; ++tj)
@@ -324,6 +350,7 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
   {
     size_t f = 0;
     for (int h = 0; h < H; ++h) {
+      levels[h].small_parents = d_pool + fix[f++].first;
       for (auto &e : levels[h].extend) e.second = d_pool + fix[f++].first;
       levels[h].small = d_pool + fix[f++].first;
       levels[h].big = d_pool + fix[f++].first;
@@ -385,6 +412,8 @@ int GridEngine::factor_internal(const double *x) {
   GCHK(g_assemble((int)fs.ent_pos.size(), d_ent_pos, d_ent_row, d_ent_g, d_ent_jptr, d_ent_jcode, d_g_val, d_devD,
                   d_F, d_rowmax, stream));
   for (const Level &L : levels) {
+    GCHK(g_extend_small(L.n_small_parents, L.small_parents, d_nc, d_fsz, d_f_off, d_ch_ptr, d_ch, d_r_ptr, d_rel, d_F,
+                        stream));
     for (const auto &e : L.extend)
       GCHK(g_extend(e.first, e.second, d_nc, d_fsz, d_parent, d_f_off, d_r_ptr, d_rel, d_F, stream));
     for (const Step &S : L.steps) {

@@ -67,6 +67,8 @@ struct GridEngine {
   };
   struct Level {
     int32_t first, count;  // into lev_front
+    int32_t n_small_parents = 0;  // fronts with children whose update matrices are <= 32 x 32
+    int32_t *small_parents = nullptr;
     std::vector<std::pair<int32_t, int32_t *>> extend;  // (items, device list) per pass
     int32_t n_small = 0, n_big = 0;  // solve: fronts with f <= 64 (a wave each) and the rest
     int32_t *small = nullptr, *big = nullptr;
