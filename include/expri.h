@@ -192,10 +192,11 @@ expri_status expri_default_opts(expri_opts *o);
  * budget E_rr and the MEVP tolerance of the options.  Builds the
  * symbolic analysis of G_k's pattern (fill-reducing order, L\U pattern, level
  * schedules, refactor update lists, stamp maps) once per distinct pattern.
- * Each instance runs in one workgroup of 256 threads when n <= 2048, 512
- * when n <= 6144 and 1024 up to n = 9216 (or opts.block_size, which must
- * then satisfy n <= 12 x 512 at 512 threads and n <= 9 block_size
- * otherwise); instances of one block size form a launch class.
+ * Each instance runs in one workgroup of 256 threads when n <= 2048 and
+ * 512 up to n = 9216 (or opts.block_size, which must then satisfy
+ * n <= 18 x 512 at 512 threads and n <= 9 block_size otherwise); the
+ * instances of one block size and one rows-per-thread bound of the transient
+ * kernel (9, or 18 at 512 threads when n > 4608) form a launch class.
  * hip_stream: the hipStream_t all work is queued on (NULL = default stream).
  * EINVAL for malformed input; ENOMEM / EHIP on allocation failure. */
 expri_status expri_setup(expri_ctx **ctx, const expri_circuit *ckt, int32_t n_inst,
@@ -312,16 +313,18 @@ expri_status expri_trace(const expri_ctx *ctx, int32_t inst, double *out, int64_
  * number. */
 expri_status expri_kernel_time(const expri_ctx *ctx, double *seconds, int32_t *launches);
 
-/* The launch classes, block size descending: *n_classes receives their
- * number; for the first min(cap, n) classes block_size[q], n_inst[q],
- * workgroups[q] (the transient kernel's grid; its workgroups take the
- * class's instances in turn) and kernel_s[q] (the summed duration of that
- * class's transient-kernel launches in the last transient call, HIP events on
- * the stream it runs on) are written where the array is not NULL, and
- * inst_class (host, n_inst entries, may be NULL) receives the class of every
- * instance. */
-expri_status expri_launch_classes(const expri_ctx *ctx, int32_t cap, int32_t *block_size, int32_t *n_inst,
-                                  int32_t *workgroups, double *kernel_s, int32_t *inst_class,
+/* The launch classes, (block size, rows-per-thread bound of the transient
+ * kernel) descending: *n_classes receives their number; for the first
+ * min(cap, n) classes block_size[q], max_rows[q] (the bound: 9, or 18 for the
+ * 512-thread kernel of circuits with n > 4608; 0 for the multifrontal
+ * engine), n_inst[q], workgroups[q] (the transient kernel's grid; its
+ * workgroups take the class's instances in turn) and kernel_s[q] (the summed
+ * duration of that class's transient-kernel launches in the last transient
+ * call, HIP events on the stream it runs on) are written where the array is
+ * not NULL, and inst_class (host, n_inst entries, may be NULL) receives the
+ * class of every instance. */
+expri_status expri_launch_classes(const expri_ctx *ctx, int32_t cap, int32_t *block_size, int32_t *max_rows,
+                                  int32_t *n_inst, int32_t *workgroups, double *kernel_s, int32_t *inst_class,
                                   int32_t *n_classes);
 
 /* Diagnostic: device time (seconds per repetition, GPU wall clock) of one

@@ -133,7 +133,7 @@ def load_library(path: str = LIB_PATH):
                               C.POINTER(C.c_int64)], C.c_int),
         "expri_lu_values": ([_p, C.c_int32, _f64p], C.c_int),
         "expri_kernel_time": ([_p, _f64p, _i32p], C.c_int),
-        "expri_launch_classes": ([_p, C.c_int32, _i32p, _i32p, _i32p, _f64p, _i32p, _i32p], C.c_int),
+        "expri_launch_classes": ([_p, C.c_int32, _i32p, _i32p, _i32p, _i32p, _f64p, _i32p, _i32p], C.c_int),
         "expri_block_size": ([_p, _i32p], C.c_int),
         "expri_diag_time": ([_p, C.c_int32, C.c_int32, C.c_int32, _f64p], C.c_int),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
@@ -422,20 +422,22 @@ class Solver:
 
     def classes(self):
         """(classes, inst_class): the launch classes of the batch as
-        [{"block_size", "n_inst", "workgroups", "kernel_s"}], block size
-        descending (workgroups: the transient kernel's grid; kernel_s: the
-        last transient call's summed duration of that class's launches), and
-        the class index of every instance."""
+        [{"block_size", "max_rows", "n_inst", "workgroups", "kernel_s"}],
+        (block size, rows-per-thread bound) descending (workgroups: the
+        transient kernel's grid; kernel_s: the last transient call's summed
+        duration of that class's launches), and the class index of every
+        instance."""
         n = C.c_int32()
-        self._check(self.lib.expri_launch_classes(self.ctx, 0, None, None, None, None, None, C.byref(n)))
+        self._check(self.lib.expri_launch_classes(self.ctx, 0, None, None, None, None, None, None, C.byref(n)))
         bs = (C.c_int32 * n.value)()
+        mr = (C.c_int32 * n.value)()
         cnt = (C.c_int32 * n.value)()
         wg = (C.c_int32 * n.value)()
         ks = (C.c_double * n.value)()
         ic = np.zeros(self.n_inst, np.int32)
-        self._check(self.lib.expri_launch_classes(self.ctx, n.value, bs, cnt, wg, ks, _ptr(ic, C.c_int32),
+        self._check(self.lib.expri_launch_classes(self.ctx, n.value, bs, mr, cnt, wg, ks, _ptr(ic, C.c_int32),
                                                   C.byref(n)))
-        return [{"block_size": bs[q], "n_inst": cnt[q], "workgroups": wg[q], "kernel_s": ks[q]}
+        return [{"block_size": bs[q], "max_rows": mr[q], "n_inst": cnt[q], "workgroups": wg[q], "kernel_s": ks[q]}
                 for q in range(n.value)], ic
 
     def kernel_time(self):

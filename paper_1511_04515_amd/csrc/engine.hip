@@ -75,6 +75,17 @@ __device__ __forceinline__ double wg_max(Lds<BS> &L, double v) {
   return r;
 }
 
+// the first thread's v, to every thread of the workgroup
+template <int BS>
+__device__ __forceinline__ double wg_bcast0(Lds<BS> &L, double v) {
+  double *s = L.slots + L.par * (BS / 64);
+  if (tid() == 0) s[0] = v;
+  __syncthreads();
+  const double r = s[0];
+  L.par ^= 1;
+  return r;
+}
+
 // Per-phase wall-clock accounting (every thread keeps the same counters; the
 // first thread stores them).  Phases: 0 stamp + factor, 1 right-hand sides,
 // 2 Arnoldi SpMV + solve, 3 modified Gram-Schmidt, 4 Hessenberg exponential,
@@ -574,9 +585,12 @@ struct InvFact<0> {
 // dimension ld.  Wave w computes output tiles w, w + NW, ...  MFMA f64
 // 16x16x4 lane layout: operand A lane i + 16 k holds A[i][k]; operand B lane
 // j + 16 k holds B[k][j]; result element v of lane j + 16 q is C[q + 4 v][j].
+// With Dout (and add false) the tile also gives
+// Dout = ((d0 I + d1 P1) + d2 P2) + d3 C.
 template <int BS, int NP, class PT>
 __device__ __forceinline__ void mm_mfma(PT A, PT B, PT C, int ld, bool add, double c0, double c1, double c2,
-                                        PT P1, PT P2) {
+                                        PT P1, PT P2, PT Dout = nullptr, double d0 = 0.0, double d1 = 0.0,
+                                        double d2 = 0.0, double d3 = 0.0) {
   constexpr int T = NP / 16, NW = BS / 64;
   const int lane = tid() & 63, wave = tid() >> 6;
   const int r = lane & 15, q = lane >> 4;
@@ -596,6 +610,13 @@ __device__ __forceinline__ void mm_mfma(PT A, PT B, PT C, int ld, bool add, doub
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) C[(i0 + q + 4 * v) * ld + j0 + r] = acc[v];
+    if (Dout) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + q + 4 * v, j = j0 + r, o = i * ld + j;
+        Dout[o] = (((i == j ? d0 : 0.0) + d1 * P1[o]) + d2 * P2[o]) + d3 * acc[v];
+      }
+    }
   }
   __syncthreads();
 }
@@ -713,47 +734,44 @@ __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM do
   PT P1 = base, P2 = base + NP * ld, P3 = base + 2 * NP * ld, Ta = base + 3 * NP * ld, Tb = base + 4 * NP * ld;
   // ---- M = h H^{-1} into P3 (P2 holds the triangular factor) ----
   hess_inverse<BS, NP, IN_LDS>(H, P1, m, h, P2, P3, Ta, ld);
-  double mbad = 0.0;
-  for (int i = tid(); i < m * m; i += BS)
-    if (!isfinite(P3[(i / m) * ld + i % m])) mbad = 1.0;
-  if (wg_max(L, mbad) != 0.0) return INFINITY;  // H_m singular: not converged
-  // ---- A = [[M, e_1], [0, 0]] padded to NP x NP, in P1; with the phi_2
-  // column it is [[M, e_1, 0], [0, 0, 1], [0, 0, 0]] ----
+  // ---- A = [[M, e_1], [0, 0]] padded to NP x NP; with the phi_2 column it
+  // is [[M, e_1, 0], [0, 0, 1], [0, 0, 0]].  ||A||_1 from M's column sums
+  // (a non-finite entry of M, H_m singular, makes it non-finite: not
+  // converged), then A scaled by 2^-s into P1 ----
   const bool two = dout2 != nullptr;
-  for (int i = tid(); i < NP * NP; i += BS) {
-    const int r = i / NP, c = i % NP;
-    double v = (r < m && c < m) ? P3[r * ld + c] : (r == 0 && c == m ? 1.0 : 0.0);
-    if (two && r == m && c == m + 1) v = 1.0;
-    P1[r * ld + c] = v;
-  }
-  __syncthreads();
   double cs = 0.0;
   if (tid() < NP) {
-#pragma unroll 8
-    for (int r = 0; r < NP; ++r) cs += fabs(P1[r * ld + tid()]);
+    const int c = tid();
+    if (c < m) {
+      for (int r = 0; r < m; ++r) cs += fabs(P3[r * ld + c]);
+    } else if (c == m || (two && c == m + 1)) {
+      cs = 1.0;
+    }
+    if (!isfinite(cs)) cs = INFINITY;
   }
   const double nrm = wg_max(L, cs);
+  if (!isfinite(nrm)) return INFINITY;
   // 2^-s ||A||_1 <= 1; beyond 2^64 every entry of exp(A) under- or overflows
-  // anyway and a non-finite norm is caught below
+  // anyway
   int s = 0;
   if (nrm > 1.0) {
     int e;
     const double f = frexp(nrm, &e);
-    s = (!isfinite(nrm) || e > 64) ? 64 : (f == 0.5 ? e - 1 : e);
+    s = e > 64 ? 64 : (f == 0.5 ? e - 1 : e);
   }
-  if (s > 0) {
-    const double sc = ldexp(1.0, -s);
-    for (int i = tid(); i < NP * NP; i += BS) P1[(i / NP) * ld + i % NP] *= sc;
-    __syncthreads();
-  }
-  // ---- Taylor degree 18, Paterson-Stockmeyer with A^3 ----
-  mm_mfma<BS, NP>(P1, P1, P2, ld, false, 0.0, 0.0, 0.0, P1, P1);
-  mm_mfma<BS, NP>(P2, P1, P3, ld, false, 0.0, 0.0, 0.0, P1, P1);
+  const double sc = ldexp(1.0, -s);
   for (int i = tid(); i < NP * NP; i += BS) {
-    const int r = i / NP, c = i % NP, o = r * ld + c;
-    Ta[o] = (((r == c ? InvFact<15>::v : 0.0) + InvFact<16>::v * P1[o]) + InvFact<17>::v * P2[o]) + InvFact<18>::v * P3[o];
+    const int r = i / NP, c = i % NP;
+    double v = (r < m && c < m) ? P3[r * ld + c] : (r == 0 && c == m ? 1.0 : 0.0);
+    if (two && r == m && c == m + 1) v = 1.0;
+    P1[r * ld + c] = v * sc;
   }
   __syncthreads();
+  // ---- Taylor degree 18, Paterson-Stockmeyer with A^3 (the A^3 product
+  // also gives the first term 1/15! I + A/16! + A^2/17! + A^3/18!) ----
+  mm_mfma<BS, NP>(P1, P1, P2, ld, false, 0.0, 0.0, 0.0, P1, P1);
+  mm_mfma<BS, NP>(P2, P1, P3, ld, false, 0.0, 0.0, 0.0, P1, P1, Ta, InvFact<15>::v, InvFact<16>::v,
+                  InvFact<17>::v, InvFact<18>::v);
   mm_mfma<BS, NP>(Ta, P3, Tb, ld, true, InvFact<12>::v, InvFact<13>::v, InvFact<14>::v, P1, P2);
   mm_mfma<BS, NP>(Tb, P3, Ta, ld, true, InvFact<9>::v, InvFact<10>::v, InvFact<11>::v, P1, P2);
   mm_mfma<BS, NP>(Ta, P3, Tb, ld, true, InvFact<6>::v, InvFact<7>::v, InvFact<8>::v, P1, P2);
@@ -768,26 +786,30 @@ __device__ __forceinline__ double hess_phi_np(Lds<BS> &L, PT base, const GMEM do
     Y = tmp;
   }
   // ---- d = -M f and (M y)_{m-1};  M = 2^s A[:m, :m] exactly; with the
-  // phi_2 column also d2 = -M phi_2(M) e_1 ----
-  double bad = 0.0;
-  for (int r = tid(); r < m; r += BS) {
-    double acc = 0.0, acc2 = 0.0;
-    for (int c = 0; c < m; ++c) {
-      const double mrc = ldexp(P1[r * ld + c], s);
-      acc += mrc * E[c * ld + m];
-      if (two) acc2 += mrc * E[c * ld + m + 1];
+  // phi_2 column also d2 = -M phi_2(M) e_1.  m < 64: the first wave does it
+  // and broadcasts rho ----
+  double rho = 0.0;
+  if (tid() < 64) {
+    const int r = tid();
+    double bad = 0.0, part = 0.0;
+    if (r < m) {
+      double acc = 0.0, acc2 = 0.0;
+      for (int c = 0; c < m; ++c) {
+        const double mrc = ldexp(P1[r * ld + c], s);
+        acc += mrc * E[c * ld + m];
+        if (two) acc2 += mrc * E[c * ld + m + 1];
+      }
+      dout[r] = -acc;
+      if (two) dout2[r] = -acc2;
+      if (!isfinite(acc) || !isfinite(acc2)) bad = 1.0;
+      part = ldexp(P1[(m - 1) * ld + r], s) * E[r * ld];
     }
-    dout[r] = -acc;
-    if (two) dout2[r] = -acc2;
-    if (!isfinite(acc) || !isfinite(acc2)) bad = 1.0;
+    const double my = wave_sum(part);
+    const double anybad = wave_max(bad);
+    rho = beta * h_next * fabs(my / h);
+    if (anybad != 0.0 || !isfinite(rho)) rho = INFINITY;
   }
-  double part = 0.0;
-  for (int c = tid(); c < m; c += BS) part += ldexp(P1[(m - 1) * ld + c], s) * E[c * ld];
-  const double my = wg_sum(L, part);
-  const double anybad = wg_max(L, bad);
-  double rho = beta * h_next * fabs(my / h);
-  if (anybad != 0.0 || !isfinite(rho)) rho = INFINITY;
-  return rho;
+  return wg_bcast0(L, rho);
 }
 
 // d -> dout (LDS, m doubles), and -M phi_2(M) e_1 -> dout2 when it is not
@@ -981,16 +1003,17 @@ __device__ __forceinline__ double combine_err(const InstDesc &D, const double *d
   return emax;
 }
 
-// rows per thread: rows_per_thread(n, BS) = 4, 6, 9 or (512 threads) 12;
-// set-up keeps n <= max_rows_per_thread(BS) BS
-template <int BS>
+// rows per thread: rows_per_thread(n, BS) = 4, 6, 9, 12 or 18; set-up keeps
+// n <= EM BS for the kernel's bound EM (12 and 18 only at 512 threads)
+template <int BS, int EM = max_rows_per_thread(BS)>
 __device__ __forceinline__ void arnoldi_step(const InstDesc &D, Lds<BS> &L, double *V, double *H, Basis &B,
                              double breakdown, Prof &pf) {
   const int e = rows_per_thread(D.n, BS);
   if (e == 4) arnoldi_step_e<BS, 4>(D, L, V, H, B, breakdown, pf);
   else if (e == 6) arnoldi_step_e<BS, 6>(D, L, V, H, B, breakdown, pf);
-  else if (BS != 512 || e == 9) arnoldi_step_e<BS, 9>(D, L, V, H, B, breakdown, pf);
-  else arnoldi_step_e<BS, (BS == 512 ? 12 : 9)>(D, L, V, H, B, breakdown, pf);
+  else if (EM <= 9 || e == 9) arnoldi_step_e<BS, 9>(D, L, V, H, B, breakdown, pf);
+  else if (e == 12) arnoldi_step_e<BS, (EM > 9 ? 12 : 9)>(D, L, V, H, B, breakdown, pf);
+  else arnoldi_step_e<BS, (EM > 9 ? 18 : 9)>(D, L, V, H, B, breakdown, pf);
 }
 
 // Start a basis from the vector v (global or the LDS vector area):
@@ -1013,7 +1036,7 @@ __device__ __forceinline__ void basis_start(const InstDesc &D, Lds<BS> &L, const
 }
 
 // grow the basis until rho_m(h) <= eps; d -> dout.  Returns a status code.
-template <int BS>
+template <int BS, int EM = max_rows_per_thread(BS)>
 __device__ __forceinline__ int mevp_converge(const InstDesc &D, Lds<BS> &L, const Opts &o, double *V, double *H,
                              Basis &B, double h, double eps, double *dout, double &rho,
                              int &iters, Prof &pf, Work &wk, int m_first = 1, double *dout2 = nullptr) {
@@ -1039,7 +1062,7 @@ __device__ __forceinline__ int mevp_converge(const InstDesc &D, Lds<BS> &L, cons
       __syncthreads();
     }
     if (B.m >= o.m_max) return kEKRYLOV;
-    arnoldi_step<BS>(D, L, V, H, B, o.breakdown, pf);
+    arnoldi_step<BS, EM>(D, L, V, H, B, o.breakdown, pf);
     ++iters;
     wk.mgs += B.m;
   }
@@ -1125,7 +1148,7 @@ __global__ void k_end(const InstDesc *descs, double *const *xout) {
 // max_steps accepted steps unless the instance is done.  replay != 0: the
 // step ends are taken from gbl(D.bp) (the given grid) and every first trial
 // is accepted.
-template <int BS>
+template <int BS, int EM>
 __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, const Opts &o, int max_steps,
                                              int replay) {
   InstState &S = *D.state;
@@ -1281,7 +1304,7 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
     bool fell_back = false;
     for (;;) {
       ++wk.trials;
-      status = mevp_converge<BS>(D, L, o, D.V, D.H, Bm, h, o.eps_K, L.dmain, rho, iters, pf, wk,
+      status = mevp_converge<BS, EM>(D, L, o, D.V, D.H, Bm, h, o.eps_K, L.dmain, rho, iters, pf, wk,
                                  rej == 0 ? m_first : 1);
       // a learned proposal whose MEVP does not converge within m_max (the
       // invert-Krylov residual grows as h shrinks, so halving would not help)
@@ -1305,10 +1328,12 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
       wk.comb += Bm.m;
       // x_{k+1} = x_k + h p + beta V_m d
       const int rpt = rows_per_thread(n, BS);
-      const double bad = rpt == 4   ? combine_main<BS, 4>(D, L.dmain, Bm.m, Bm.beta, h)
-                         : rpt == 6 ? combine_main<BS, 6>(D, L.dmain, Bm.m, Bm.beta, h)
-                         : rpt == 9 ? combine_main<BS, 9>(D, L.dmain, Bm.m, Bm.beta, h)
-                                    : combine_main<BS, (BS == 512 ? 12 : 9)>(D, L.dmain, Bm.m, Bm.beta, h);
+      constexpr int E12 = EM > 9 ? 12 : 9, E18 = EM > 9 ? 18 : 9;
+      const double bad = rpt == 4    ? combine_main<BS, 4>(D, L.dmain, Bm.m, Bm.beta, h)
+                         : rpt == 6  ? combine_main<BS, 6>(D, L.dmain, Bm.m, Bm.beta, h)
+                         : rpt == 9  ? combine_main<BS, 9>(D, L.dmain, Bm.m, Bm.beta, h)
+                         : rpt == 12 ? combine_main<BS, E12>(D, L.dmain, Bm.m, Bm.beta, h)
+                                     : combine_main<BS, E18>(D, L.dmain, Bm.m, Bm.beta, h);
       if (wg_max(L, bad) != 0.0) { status = kENONFINITE; break; }
       err = 0.0;
       m_err = 0;
@@ -1338,7 +1363,7 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
         double rho_e;
         // under the learned controller the residual tests of the error MEVP
         // start two sizes below the previous step's (every size otherwise)
-        status = mevp_converge<BS>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk,
+        status = mevp_converge<BS, EM>(D, L, o, D.Ve, D.He, Be, h, o.eps_K, L.derr, rho_e, iters, pf, wk,
                                    learned ? max(1, m_err_prev - 2) : 1, o.erc ? L.derr2 : nullptr);
         if (status == kEKRYLOV && learned && !fell_back) {
           fell_back = true;
@@ -1360,12 +1385,13 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
         wk.comb += Be.m;
         // ER-C: x_{k+1} -= gamma h phi_2(hJ) C^{-1} dF = gamma beta_e V_e d2
         const int rpe = rows_per_thread(n, BS);
-        constexpr int E12 = BS == 512 ? 12 : 9;
+        constexpr int F12 = EM > 9 ? 12 : 9, F18 = EM > 9 ? 18 : 9;
         const double emax =
-            rpe == 4   ? combine_err<BS, 4>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
-            : rpe == 6 ? combine_err<BS, 6>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
-            : rpe == 9 ? combine_err<BS, 9>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
-                       : combine_err<BS, E12>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0);
+            rpe == 4    ? combine_err<BS, 4>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+            : rpe == 6  ? combine_err<BS, 6>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+            : rpe == 9  ? combine_err<BS, 9>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+            : rpe == 12 ? combine_err<BS, F12>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0)
+                        : combine_err<BS, F18>(D, L.derr, L.derr2, Be.m, Be.beta, o.gamma, o.erc != 0);
         if (o.erc) wk.comb += Be.m;
         err = wg_max(L, emax);
       }
@@ -1437,8 +1463,13 @@ __device__ __forceinline__ void run_instance(const InstDesc &D, Lds<BS> &L, cons
 // slice is exhausted, so that the classes launched together never wait for
 // one another's compute units.  *next starts at 0; every workgroup leaves once
 // the counter passes count.
-template <int BS>
-__global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *order, int count, int *next,
+// EM bounds the rows per thread (9, or 18 at 512 threads).  With EM = 9 the
+// kernel is held to the registers of two workgroups per compute unit (two
+// waves per SIMD at 256 threads, four at 512), so that a batch with more
+// such instances than free compute units runs in one round; at 512 threads
+// and EM = 18 it keeps one workgroup per compute unit.
+template <int BS, int EM>
+__global__ void __launch_bounds__(BS, BS == 256 ? 2 : (BS == 512 && EM > 9) ? 2 : 4) k_run(const InstDesc *descs, const int *order, int count, int *next,
                                             Opts o, int max_steps, int replay, int R, int NX) {
   Lds<BS> L = lds_setup<BS>(R, NX);
   for (;;) {
@@ -1449,7 +1480,7 @@ __global__ void __launch_bounds__(BS) k_run(const InstDesc *descs, const int *or
     const int idx = __builtin_amdgcn_readfirstlane((int)got);
     if (idx >= count) break;
     const int inst = __builtin_amdgcn_readfirstlane(order[idx]);
-    run_instance<BS>(descs[inst], L, o, max_steps, replay);
+    run_instance<BS, EM>(descs[inst], L, o, max_steps, replay);
     __syncthreads();
   }
 }
@@ -1619,7 +1650,7 @@ hipError_t set_lds_limits(size_t bytes) {
   hipError_t e = hipSuccess;
 #define SETA(K) \
   if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void *>(K), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  SETA(k_run<256>) SETA(k_run<512>) SETA(k_run<1024>)
+  SETA((k_run<256, 9>)) SETA((k_run<512, 9>)) SETA((k_run<512, 18>)) SETA((k_run<1024, 9>))
   SETA(k_dc<256>) SETA(k_dc<512>) SETA(k_dc<1024>)
   SETA(k_factor<256>) SETA(k_factor<512>) SETA(k_factor<1024>)
   SETA(k_solve<256>) SETA(k_solve<512>) SETA(k_solve<1024>)
@@ -1726,10 +1757,14 @@ hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStr
 }
 
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, int grid, int *next, const Opts &o,
-                      int max_steps, int replay, int bs, int R, int NX, hipStream_t s) {
+                      int max_steps, int replay, int bs, int em, int R, int NX, hipStream_t s) {
   const size_t sh = lds_bytes(bs, R);
-  EXPRI_DISPATCH(bs, hipLaunchKernelGGL(k_run<BS>, dim3(grid), dim3(BS), sh, s, d, order, n_inst, next, o,
-                                        max_steps, replay, R, NX));
+  if (bs == 512 && em > 9)
+    hipLaunchKernelGGL((k_run<512, 18>), dim3(grid), dim3(512), sh, s, d, order, n_inst, next, o, max_steps, replay,
+                       R, NX);
+  else
+    EXPRI_DISPATCH(bs, hipLaunchKernelGGL((k_run<BS, 9>), dim3(grid), dim3(BS), sh, s, d, order, n_inst, next, o,
+                                          max_steps, replay, R, NX));
   return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ hipError_t launch_begin(const InstDesc *d, int n_inst, const double *const *xin,
 hipError_t launch_end(const InstDesc *d, int n_inst, double *const *xout, hipStream_t s);
 hipError_t launch_init_workspace(const InstDesc *d, int n_inst, hipStream_t s);
 hipError_t launch_run(const InstDesc *d, const int *order, int n_inst, int grid, int *next, const Opts &o,
-                      int max_steps, int replay, int bs, int R, int NX, hipStream_t s);
+                      int max_steps, int replay, int bs, int em, int R, int NX, hipStream_t s);
 hipError_t launch_zero_counters(int *next, int n, hipStream_t s);
 hipError_t launch_dc(const InstDesc *d, const int *order, int n_inst, const Opts &o, double t0, int max_it,
                      int bs, int R, int NX, hipStream_t s);
@@ -108,7 +108,7 @@ struct Inst {
 // of the transient kernel per class, the classes concurrently on their own
 // streams (class 0 on the caller's stream), larger block sizes first.
 struct LaunchClass {
-  int bs = 512, R = 0, NX = 0;
+  int bs = 512, em = 9, R = 0, NX = 0;  // block size, rows-per-thread bound of its kernel
   int first = 0, count = 0;  // their slice of the launch order
   int grid = 1;              // workgroups of its transient launch (each takes instances in turn)
   hipStream_t stream = nullptr;
@@ -471,7 +471,7 @@ expri_status launch_run_classes(expri_ctx *c, const Opts &ko, int max_steps, int
     if (K.stream != c->stream) HIPCHK(c, hipStreamWaitEvent(K.stream, c->ev_fork, 0));
     HIPCHK(c, hipEventRecord(K.e0, K.stream));
     HIPCHK(c, launch_run(c->d_desc, c->d_order + K.first, K.count, K.grid, c->d_next + q, ko, max_steps, replay,
-                         K.bs, K.R, K.NX, K.stream));
+                         K.bs, K.em, K.R, K.NX, K.stream));
     HIPCHK(c, hipEventRecord(K.e1, K.stream));
   }
   for (auto &K : c->cls)
@@ -573,9 +573,8 @@ expri_status scratch_ptr(expri_ctx *c, char **out) {
   return EXPRI_OK;
 }
 
-// The largest circuit the one-workgroup engine holds (12 rows per thread at
-// 512 threads, 9 at 1,024); beyond it a single circuit goes to the
-// multifrontal engine.
+// The largest circuit the one-workgroup engine holds (18 rows per thread at
+// 512 threads); beyond it a single circuit goes to the multifrontal engine.
 constexpr int32_t kMaxWorkgroupRows = 9216;
 
 expri_status grid_status(expri_ctx *c, int st) {
@@ -750,10 +749,11 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && wall_khz > 0)
     c->wall_hz = 1e3 * wall_khz;
   // ---- launch classes.  A thread keeps at most max_rows_per_thread(bs)
-  // rows of a vector in registers (12 at 512 threads, 9 otherwise): a
-  // pattern takes 256 threads up to n = 2048, 512 up to 12 x 512 = 6144 and
-  // 1024 beyond (or the block size the options force), and the instances of
-  // one block size form a launch class ----
+  // rows of a vector in registers (18 at 512 threads, 9 otherwise): a
+  // pattern takes 256 threads up to n = 2048 and 512 up to 18 x 512 = 9216
+  // (or the block size the options force); the instances of one block size
+  // and one rows-per-thread bound of the transient kernel form a launch
+  // class ----
   for (auto &P : c->pats) {
     P.bs = op.block_size ? op.block_size
                          : (P.sym.n <= 2048 ? 256 : P.sym.n <= max_rows_per_thread(512) * 512 ? 512 : 1024);
@@ -764,10 +764,14 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     }
   }
   const size_t limit = prop.sharedMemPerBlock;
-  for (int bs : {1024, 512, 256}) {
+  // the transient kernel's rows-per-thread bound: 18 at 512 threads beyond
+  // 9 x 512 rows, else 9; the classes are (block size, bound), larger first
+  auto row_bound = [](int bs, int n) { return (bs == 512 && n > 9 * 512) ? 18 : 9; };
+  for (const auto &key : {std::pair<int, int>{1024, 9}, {512, 18}, {512, 9}, {256, 9}}) {
+    const int bs = key.first, em = key.second;
     int nm = 0;
     for (const auto &I : c->inst)
-      if (c->pats[I.pat].bs == bs) nm = std::max(nm, I.n);
+      if (c->pats[I.pat].bs == bs && row_bound(bs, c->pats[I.pat].sym.n) == em) nm = std::max(nm, I.n);
     if (nm == 0) continue;
     // LDS: the vector area (solve vector / current Arnoldi basis vector, NX
     // doubles) and behind it the small dense matrices of the Hessenberg
@@ -784,6 +788,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     }
     LaunchClass K;
     K.bs = bs;
+    K.em = em;
     K.NX = (int)NX;
     K.R = (int)(NX + RD);
     c->cls.push_back(K);
@@ -792,7 +797,9 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   c->inst_class.resize(n_inst);
   for (int k = 0; k < n_inst; ++k)
     for (size_t q = 0; q < c->cls.size(); ++q)
-      if (c->cls[q].bs == c->pats[c->inst[k].pat].bs) c->inst_class[k] = (int)q;
+      if (c->cls[q].bs == c->pats[c->inst[k].pat].bs &&
+          c->cls[q].em == row_bound(c->cls[q].bs, c->pats[c->inst[k].pat].sym.n))
+        c->inst_class[k] = (int)q;
   // flattened solve schedules and the C ELL pattern for the pattern's block size
   for (auto &P : c->pats) {
     P.u_slot_base = -1;
@@ -902,9 +909,11 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     }
     // transient grids: the first class (largest block size) one workgroup per
     // instance; the compute units it leaves are shared by the other classes in
-    // proportion to their instance counts (at least one workgroup each), so
-    // that every workgroup of every class finds a compute unit at once.  With
-    // max_workgroups the first class is capped as well.
+    // proportion to their instance counts (at least one workgroup each), two
+    // workgroups per compute unit at 256 and 512 threads (the kernel's
+    // register bound), so that every workgroup of every class finds a place
+    // at once.  With max_workgroups the first class is capped as well and the
+    // others get one workgroup per compute unit.
     const int ncls = (int)c->cls.size();
     const int cus = op.max_workgroups > 0 ? op.max_workgroups : std::max(prop.multiProcessorCount, 1);
     int rest = 0;
@@ -914,7 +923,8 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
     const int left = std::max(cus - c->cls[0].grid, 0);
     for (size_t q = 1; q < c->cls.size(); ++q) {
       LaunchClass &K = c->cls[q];
-      K.grid = std::max(1, std::min(K.count, (int)((long long)left * K.count / std::max(rest, 1))));
+      const int per_cu = (op.max_workgroups == 0 && K.bs <= 512 && K.em <= 9) ? 2 : 1;
+      K.grid = std::max(1, std::min(K.count, (int)((long long)per_cu * left * K.count / std::max(rest, 1))));
     }
     e = hipMalloc(reinterpret_cast<void **>(&c->d_next), sizeof(int) * c->cls.size());
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_order), sizeof(int) * n_inst);
@@ -1386,8 +1396,8 @@ expri_status expri_kernel_time(const expri_ctx *c, double *seconds, int32_t *lau
   return EXPRI_OK;
 }
 
-expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *block_size, int32_t *n_inst,
-                                  int32_t *workgroups, double *kernel_s, int32_t *inst_class,
+expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *block_size, int32_t *max_rows,
+                                  int32_t *n_inst, int32_t *workgroups, double *kernel_s, int32_t *inst_class,
                                   int32_t *n_classes) {
   if (!c || !n_classes || cap < 0) return EXPRI_EINVAL;
   if (c->grid) {  // one "class": the multifrontal engine's kernels (256 threads), grid-wide launches
@@ -1395,6 +1405,7 @@ expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *bloc
     if (inst_class) inst_class[0] = 0;
     if (cap >= 1) {
       if (block_size) block_size[0] = 256;
+      if (max_rows) max_rows[0] = 0;
       if (n_inst) n_inst[0] = 1;
       if (workgroups) workgroups[0] = 0;
       if (kernel_s) kernel_s[0] = c->run_kernel_s;
@@ -1406,6 +1417,7 @@ expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *bloc
     for (size_t k = 0; k < c->inst_class.size(); ++k) inst_class[k] = c->inst_class[k];
   for (int32_t q = 0; q < std::min<int32_t>(cap, *n_classes); ++q) {
     if (block_size) block_size[q] = c->cls[q].bs;
+    if (max_rows) max_rows[q] = c->cls[q].em;
     if (n_inst) n_inst[q] = c->cls[q].count;
     if (workgroups) workgroups[q] = c->cls[q].grid;
     if (kernel_s) kernel_s[q] = c->cls[q].kernel_s;

@@ -14,11 +14,13 @@ constexpr int kHLd = kMaxKrylov + 1;  // leading dimension of stored Hessenbergs
 // Rows of a length-n vector one thread of a bs-thread workgroup keeps in
 // registers (rows t + e bs, e < E).  The basis columns and C's ELL columns
 // are padded with zeros to E bs rows so that these rows load without a
-// bound test.  n <= max_rows_per_thread(bs) bs: 12 rows at 512 threads, 9
-// otherwise.
-constexpr int max_rows_per_thread(int bs) { return bs == 512 ? 12 : 9; }
+// bound test.  n <= max_rows_per_thread(bs) bs: 18 rows at 512 threads, 9
+// otherwise.  The transient kernel is compiled for a bound EM on E (9, or 18
+// at 512 threads): the smaller bound keeps it to the registers of two
+// workgroups per compute unit.
+constexpr int max_rows_per_thread(int bs) { return bs == 512 ? 18 : 9; }
 constexpr int rows_per_thread(int n, int bs) {
-  return n <= 4 * bs ? 4 : n <= 6 * bs ? 6 : n <= 9 * bs ? 9 : 12;
+  return n <= 4 * bs ? 4 : n <= 6 * bs ? 6 : n <= 9 * bs ? 9 : n <= 12 * bs ? 12 : 18;
 }
 constexpr int kRecFixed = 16;         // fixed doubles per trace record (8 + 8 step features)
 constexpr int kFeat = 8;              // step features seen by the learned controller

@@ -37,7 +37,8 @@ WORKLOADS = {
 }
 # chains sized into each band of the kernel's (threads, rows per thread)
 # variants: 841 -> (256, 4), 1,051 -> (256, 6), 1,891 -> (256, 9),
-# 2,521 -> (512, 6), 4,201 -> (512, 9), 5,251 -> (512, 12), 6,301 -> (1024, 9)
+# 2,521 -> (512, 6), 4,201 -> (512, 9), 5,251 -> (512, 12), 6,301 -> (512, 18)
+# (and (1024, 9) when that block size is forced)
 VARIANT_STAGES = (40, 50, 90, 120, 200, 250, 300)
 
 

@@ -268,13 +268,14 @@ def test_set_values_matches_a_fresh_setup():
 
 
 def test_mixed_size_batch_runs_as_concurrent_classes_and_matches_single_runs():
-    # chains of 841, 2521 and 6301 nodes take block sizes 256, 512 and 1024:
-    # three launch classes, the transient kernels concurrent on three streams
+    # chains of 841, 2521 and 6301 nodes take 256 threads, 512 threads with
+    # up to 9 rows per thread and 512 threads with up to 18: three launch
+    # classes, the transient kernels concurrent on three streams
     nets = [netgen.inverter_chain(seed=40 + i, n_stages=L, T=0.3e-9, t_ramp=0.1e-9)
             for i, L in enumerate((300, 40, 120, 40, 300))]
     sb = Solver(nets)
     classes, ic = sb.classes()
-    assert [c["block_size"] for c in classes] == [1024, 512, 256]
+    assert [(c["block_size"], c["max_rows"]) for c in classes] == [(512, 18), (512, 9), (256, 9)]
     assert [c["n_inst"] for c in classes] == [2, 1, 2]
     assert ic.tolist() == [0, 2, 1, 2, 0]
     xb = sb.zeros()
@@ -289,7 +290,8 @@ def test_mixed_size_batch_runs_as_concurrent_classes_and_matches_single_runs():
     assert all(c["kernel_s"] > 0 for c in sb.classes()[0])
     for i, net in enumerate(nets):
         s1 = Solver(net)
-        assert s1.classes()[0][0]["block_size"] == classes[ic[i]]["block_size"]
+        c1 = s1.classes()[0][0]
+        assert (c1["block_size"], c1["max_rows"]) == (classes[ic[i]]["block_size"], classes[ic[i]]["max_rows"])
         x1 = s1.zeros()
         s1.dc(x1)
         assert np.array_equal(x1[0].cpu().numpy(), x_dc[i].cpu().numpy())

@@ -2,8 +2,9 @@
 adaptive single step, and call-order independence (run on an MI355X).
 
 A transient workgroup keeps E rows of each vector per thread; the rule is
-256 threads up to n = 2,048, 512 up to 6,144, 1,024 up to 9,216, and E the
-smallest of 4, 6, 9 (12 at 512 threads only) with n <= E x threads.  One
+256 threads up to n = 2,048 and 512 up to 9,216, and E the smallest of 4,
+6, 9, 12, 18 (the last two at 512 threads only) with n <= E x threads; the
+1,024-thread kernel runs when the options force that block size.  One
 chain is sized into each band, and its replay on the oracle's accepted grid
 must meet the relative waveform bar at every accepted time point:
     max_k ||x_gpu(t_k) - x_ref(t_k)||_inf / max(max_k ||x_ref(t_k)||_inf, 1 V) <= 1e-6.
@@ -20,15 +21,15 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
-# (threads, rows per thread, stages): n = 21 stages + 1
-VARIANTS = [(256, 4, 40), (256, 6, 50), (256, 9, 90), (512, 6, 120), (512, 9, 200), (512, 12, 250),
-            (1024, 9, 300)]
+# (threads, rows per thread, stages, forced block size): n = 21 stages + 1
+VARIANTS = [(256, 4, 40, 0), (256, 6, 50, 0), (256, 9, 90, 0), (512, 6, 120, 0), (512, 9, 200, 0),
+            (512, 12, 250, 0), (512, 18, 300, 0), (1024, 9, 300, 1024)]
 
 
-def _expected_variant(n):
-    bs = 256 if n <= 2048 else 512 if n <= 6144 else 1024
-    for e in (4, 6, 9, 12):
-        if n <= e * bs and (e < 12 or bs == 512):
+def _expected_variant(n, forced=0):
+    bs = forced or (256 if n <= 2048 else 512)
+    for e in (4, 6, 9, 12, 18):
+        if n <= e * bs and (e <= 9 or bs == 512):
             return bs, e
     raise AssertionError(n)
 
@@ -41,15 +42,16 @@ def rel_wave_err(x, ref):
     return np.max(np.abs(np.asarray(x) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1.0)
 
 
-@pytest.mark.parametrize("bs,E,L", VARIANTS)
-def test_every_kernel_variant_matches_oracle_replay(bs, E, L):
+@pytest.mark.parametrize("bs,E,L,forced", VARIANTS)
+def test_every_kernel_variant_matches_oracle_replay(bs, E, L, forced):
     import paper_1511_04515_amd as X
     g = np.load(os.path.join(GOLDEN, f"variant{L}.npz"), allow_pickle=False)
     net = variant_chain(L)
-    assert _expected_variant(net.n) == (bs, E)
+    assert _expected_variant(net.n, forced) == (bs, E)
     print(f"variant ({bs}, {E}): chain of {L} stages, n = {net.n}, {len(g['t'])} steps", flush=True)
-    s = X.Solver(net, trace_cap=4096)
-    assert s.classes()[0][0]["block_size"] == bs
+    s = X.Solver(net, trace_cap=4096, block_size=forced)
+    cls = s.classes()[0][0]
+    assert cls["block_size"] == bs and cls["max_rows"] == (18 if E > 9 else 9)
     xs = s.to_device([g["x0"]])
     info = s.run_schedule(xs, [g["t"]])
     assert info[0]["status"] == 0 and info[0]["steps"] == len(g["t"])

@@ -3,8 +3,8 @@ times (run on an MI355X).
 
 320 instances, 1.39M nodes: 256 variants of a 200-stage inverter chain
 (shared sparsity) and 64 chains of 50-400 stages. They run as three
-concurrent launch classes (1,024 / 512 / 256 threads), each a work queue
-over its instances. The oracle cannot run the whole batch in a test, so the
+concurrent launch classes (512 threads with up to 18 rows per thread, 512
+threads with up to 9, 256 threads), each a work queue over its instances. The oracle cannot run the whole batch in a test, so the
 checks are:
   * invariants of every instance: status OK, t = T, one LU per accepted step,
     a finite state;
@@ -39,18 +39,19 @@ def test_full_batch_in_the_benchmark_launch_configuration():
     import torch
     nets = netgen.config(4)
     assert len(nets) == 320
-    # one instance per class: the smallest of the 1,024 class, instance 0 (a
-    # shared-pattern variant) and the largest of the 256 class
-    by_bs = {}
+    # one instance per class: the smallest of the 18-rows class, instance 0 (a
+    # shared-pattern variant) and the largest of the 256-thread class
+    by_cls = {}
     for i, net in enumerate(nets):
-        bs = 256 if net.n <= 2048 else 512 if net.n <= 6144 else 1024
-        by_bs.setdefault(bs, []).append(i)
-    picks = [min(by_bs[1024], key=lambda i: nets[i].n), 0, max(by_bs[256], key=lambda i: nets[i].n)]
+        key = 256 if net.n <= 2048 else 512 if net.n <= 4608 else 1024
+        by_cls.setdefault(key, []).append(i)
+    picks = [min(by_cls[1024], key=lambda i: nets[i].n), 0, max(by_cls[256], key=lambda i: nets[i].n)]
     ref_x0 = {i: Oracle(nets[i]).dc() for i in picks}
 
     s = E.Solver(nets, trace_cap=8192)
     classes, _ = s.classes()
-    assert [(c["block_size"], c["n_inst"]) for c in classes] == [(1024, 22), (512, 289), (256, 9)]
+    assert [(c["block_size"], c["max_rows"], c["n_inst"]) for c in classes] == [(512, 18, 36), (512, 9, 275),
+                                                                                  (256, 9, 9)]
     xs = s.zeros()
     s.dc(xs)
     for i in picks:
