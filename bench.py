@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--controller", default="learned", choices=("learned", "plain"))
     ap.add_argument("--safety", type=float, default=1.0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure each pattern's launch configuration at set-up (untimed) instead of the rule")
     ap.add_argument("--private-patterns", action="store_true",
                     help="give every instance its own copy of the symbolic data (index arrays not shared)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -336,8 +338,17 @@ def main():
     if args.controller == "learned":
         params, norm, ctrl_info = train_controller(log)
         ctrl = (params, norm)
+    t_setup = time.perf_counter()
     s = E.Solver(nets, probes=[np.zeros(0, np.int32)] * len(nets), trace_cap=8192,
-                 block_size=args.block_size, private_patterns=int(args.private_patterns))
+                 block_size=args.block_size, private_patterns=int(args.private_patterns),
+                 autotune=int(args.autotune))
+    t_setup = time.perf_counter() - t_setup
+    launch_cfg = {}
+    for k in range(len(nets)):
+        c = s.config(k)
+        key = f"{c['block_size']}x{c['max_rows']} slots {c['slots_l']}/{c['slots_u']}"
+        launch_cfg[key] = launch_cfg.get(key, 0) + 1
+    log(f"set-up {t_setup:.1f} s ({'autotuned' if args.autotune else 'rule'}); launch configurations {launch_cfg}")
     x0 = s.zeros()
     s.dc(x0)
     xs = [x.clone() for x in x0]
@@ -396,7 +407,7 @@ def main():
     per_launch_bytes = cbytes[q] / max(nlaunch, 1)
     per_launch_s = class_s[q] / max(nlaunch, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9
-    kname = f"k_run<{classes[q]['block_size']}>"
+    kname = f"k_run<{classes[q]['block_size']}, {classes[q]['max_rows']}>"
     traffic = pmc_traffic_bytes(args.workload, ctrl is not None, nlaunch, kname)
     # the SpTRSV/SpMV phase (Arnoldi C SpMV + L/U solves) from the in-kernel
     # phase timers: its time summed over instances, spread over the resident
@@ -408,7 +419,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "launches_per_step": nlaunch, "bytes_per_launch": per_launch_bytes,
             "launch_ms": 1e3 * per_launch_s, "timing": f"median of {len(times)} runs (run {med})",
-            "classes": [{"kernel": f"k_run<{c['block_size']}>", "instances": c["n_inst"],
+            "classes": [{"kernel": f"k_run<{c['block_size']}, {c['max_rows']}>", "instances": c["n_inst"],
                          "workgroups": c["workgroups"],
                          "launch_ms": 1e3 * cs / max(nlaunch, 1),
                          "bytes_per_launch": b / max(nlaunch, 1),
@@ -438,7 +449,9 @@ def main():
                    "controller": (f"learned: MLP 8-64-64-2, bfloat16 inference in the transient kernel, "
                                   f"trained on the GPU (float32) from traces of disjoint circuits, "
                                   f"safety {args.safety}") if ctrl else "plain (the paper's alpha/beta rule)",
-                   "block_sizes": {f"k_run<{c['block_size']}>": c["n_inst"] for c in classes}},
+                   "block_sizes": {f"k_run<{c['block_size']}, {c['max_rows']}>": c["n_inst"] for c in classes},
+                   "launch_configurations": launch_cfg, "autotuned": bool(args.autotune),
+                   "setup_s": t_setup},
         "time_to_solution_s": times[med],
         "run_seconds": times,
         "roofline": roof,

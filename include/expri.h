@@ -138,7 +138,28 @@ typedef struct {
    * shares its pattern with another (a measurement aid: the same batch with
    * and without one shared copy of the index arrays); default 0 */
   int32_t private_patterns;
+  /* 1: the launch configuration of every distinct pattern (block size and
+   * rows-per-thread bound, solve slots) is measured instead of taken from
+   * the rule: each candidate runs the pattern's first instance for a short
+   * transient from its DC point on this GPU and the fastest per accepted
+   * step is kept (the rule's choice unless another is 3 % faster).  The
+   * choice is cached for the life of the process by pattern hash, so a
+   * pattern is measured once; expri_instance_config reports it.  The trial
+   * runs make expri_setup take longer (seconds for tens of patterns) and
+   * allocate device memory.  Default 0 (the rule; block_size and
+   * solve_slots as given). */
+  int32_t autotune;
 } expri_opts;
+
+/* The launch configuration of instance inst: cfg[0] block size, cfg[1] the
+ * transient kernel's rows-per-thread bound, cfg[2] and cfg[3] the slots per
+ * lane of the L and U solve passes.  EINVAL for a bad index or a context of
+ * the multifrontal engine. */
+expri_status expri_instance_config(const expri_ctx *ctx, int32_t inst, int32_t cfg[4]);
+
+/* Number of trial contexts the autotuner has run in this process (each
+ * measures one candidate configuration on a set of patterns). */
+int64_t expri_autotune_runs(void);
 
 /* Counters of the last transient or DC call of one instance. */
 typedef struct {

@@ -35,7 +35,7 @@ ENTRY_POINTS = ("expri_default_opts", "expri_setup", "expri_set_values", "expri_
                 "expri_frontal_destroy", "expri_last_error", "expri_destroy",
                 "expri_mlp_create", "expri_mlp_set_norm", "expri_mlp_fit_norm", "expri_mlp_get",
                 "expri_mlp_grad", "expri_mlp_adam_step", "expri_mlp_forward", "expri_mlp_last_error",
-                "expri_mlp_destroy", "expri_controller_load")
+                "expri_mlp_destroy", "expri_controller_load", "expri_instance_config", "expri_autotune_runs")
 
 _p = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
@@ -71,7 +71,7 @@ class Opts(C.Structure):
                 ("block_size", C.c_int32), ("trace_cap", C.c_int32),
                 ("erc", C.c_int32), ("solve_slots", C.c_int32),
                 ("max_workgroups", C.c_int32), ("engine", C.c_int32), ("gamma", C.c_double),
-                ("private_patterns", C.c_int32)]
+                ("private_patterns", C.c_int32), ("autotune", C.c_int32)]
 
 
 class RunInfo(C.Structure):
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH):
         "expri_launch_classes": ([_p, C.c_int32, _i32p, _i32p, _i32p, _i32p, _f64p, _i32p, _i32p], C.c_int),
         "expri_block_size": ([_p, _i32p], C.c_int),
         "expri_diag_time": ([_p, C.c_int32, C.c_int32, C.c_int32, _f64p], C.c_int),
+        "expri_instance_config": ([_p, C.c_int32, _i32p], C.c_int),
+        "expri_autotune_runs": ([], C.c_int64),
         "expri_symbolic_create": ([C.POINTER(_p), C.POINTER(Circuit)], C.c_int),
         "expri_frontal_create": ([C.POINTER(_p), C.POINTER(Circuit), C.c_int32], C.c_int),
         "expri_frontal_array": ([_p, C.c_char_p, C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_int64)], C.c_int),
@@ -440,6 +442,14 @@ class Solver:
         return [{"block_size": bs[q], "max_rows": mr[q], "n_inst": cnt[q], "workgroups": wg[q], "kernel_s": ks[q]}
                 for q in range(n.value)], ic
 
+    def config(self, inst: int) -> dict:
+        """Launch configuration of instance inst: block size, the transient
+        kernel's rows-per-thread bound and the solve passes' slots per lane
+        (L and U), as the rule or the autotuner chose them."""
+        cfg = (C.c_int32 * 4)()
+        self._check(self.lib.expri_instance_config(self.ctx, int(inst), cfg))
+        return {"block_size": cfg[0], "max_rows": cfg[1], "slots_l": cfg[2], "slots_u": cfg[3]}
+
     def kernel_time(self):
         """(seconds, launches) of the transient kernel in the last run call."""
         sec = C.c_double()
@@ -504,6 +514,11 @@ SYMBOLIC_ARRAYS = ("perm", "lu_rowptr", "lu_col", "lu_diag", "lev_ptr", "lev_row
 
 
 SCHEDULE_ARRAYS = ("lsched", "usched", "slot_pos", "slot_col", "row_of", "pass_code", "c_ell_col")
+
+
+def autotune_runs() -> int:
+    """Trial contexts the autotuner has run in this process."""
+    return int(load_library().expri_autotune_runs())
 
 
 def symbolic_analysis(net, block_size: int | None = None, solve_slots: int = 0) -> dict:

@@ -77,7 +77,10 @@ struct Packer {
 
 struct PatternDev {
   Symbolic sym;
+  uint64_t hash = 0;
   int bs = 512;  // block size of its launch class
+  bool tuned = false;  // bs and slots come from the autotuner
+  int slots = 0;       // solve slots asked of the schedule builder (0: its cost model)
   // flattened solve schedules and C ELL pattern (depend on the block size)
   std::vector<SolveLevel> lsched, usched;
   std::vector<int32_t> slot_pos, slot_col, row_of, c_ell_col, pass_code, rdv_pos, jpos;
@@ -601,6 +604,167 @@ void grid_info(expri_ctx *c, int st) {
   c->run_launches = 1;
 }
 
+// ---- autotuning of the per-pattern launch configuration ----
+
+// the block size the rule gives a circuit of n rows
+int rule_block_size(int n) { return n <= 2048 ? 256 : n <= max_rows_per_thread(512) * 512 ? 512 : 1024; }
+
+// Patterns analysed before (by hash); set only while the autotuner creates
+// its trial contexts, so that they copy the analysis instead of redoing it.
+thread_local const std::map<uint64_t, const Symbolic *> *t_presym = nullptr;
+
+struct TuneChoice {
+  int bs = 0, slots = 0;
+};
+std::mutex g_tune_mu;                       // one autotuning at a time in the process
+std::map<uint64_t, TuneChoice> g_tune_cache;  // pattern hash -> measured choice
+int64_t g_tune_runs = 0;
+
+// slots per lane the schedule builder takes for (bs, slots) in each direction
+bool effective_slots(const Symbolic &S, int bs, int slots, int &pl, int &pu) {
+  std::vector<SolveLevel> ls, us;
+  std::vector<int32_t> a, b, r;
+  if (!build_solve_schedule(S, bs, true, ls, a, b, r, slots)) return false;
+  if (!build_solve_schedule(S, bs, false, us, a, b, r, slots)) return false;
+  pl = ls.empty() ? 1 : ls[0].P;
+  pu = us.empty() ? 1 : us[0].P;
+  return true;
+}
+
+// Per-instance device time per accepted step (wall-clock ticks) of a trial
+// context: the instances start from x at t = 0, run k_steps accepted steps
+// untimed (caches and step sizes settle), then k_steps more, measured by the
+// kernel's own phase clocks.  Infinite for an instance that fails.
+expri_status trial_cost(expri_ctx *t, double *const *x, int k_steps, std::vector<double> &cost) {
+  const int n = (int)t->inst.size();
+  cost.assign(n, INFINITY);
+  expri_status s;
+  if ((s = ensure_ws(t)) != EXPRI_OK) return s;
+  if ((s = upload_descs(t)) != EXPRI_OK) return s;
+  if ((s = put_ptrs(t, 0, reinterpret_cast<const void *const *>(x))) != EXPRI_OK) return s;
+  const Opts ko = kernel_opts(t->opts);
+  HIPCHK(t, launch_begin(t->d_desc, n, reinterpret_cast<const double *const *>(t->d_ptrs), 0.0, t->opts.h_init,
+                         t->stream));
+  std::vector<InstState> st0, st1;
+  if ((s = launch_run_classes(t, ko, k_steps, 0)) != EXPRI_OK) return s;
+  if ((s = read_states(t, st0)) != EXPRI_OK) return s;
+  if ((s = launch_run_classes(t, ko, k_steps, 0)) != EXPRI_OK) return s;
+  if ((s = read_states(t, st1)) != EXPRI_OK) return s;
+  for (int k = 0; k < n; ++k) {
+    if (st1[k].status != kOK) continue;
+    double ticks = 0.0;
+    for (int p = 0; p < kPhases; ++p) ticks += st1[k].ph[p] - st0[k].ph[p];
+    int steps = st1[k].steps - st0[k].steps;
+    if (steps <= 0) {  // finished within the first launch: its whole run
+      ticks = 0.0;
+      for (int p = 0; p < kPhases; ++p) ticks += st1[k].ph[p];
+      steps = st1[k].steps;
+    }
+    if (steps > 0) cost[k] = ticks / steps;
+  }
+  return EXPRI_OK;
+}
+
+// Chooses (block size, solve slots) for every pattern of c: from the
+// process-wide cache, else by trial contexts, one per candidate
+// configuration, each holding the first instance of every pattern that
+// configuration applies to.
+expri_status autotune(expri_ctx *c, const expri_circuit *ckt, int32_t n_inst) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const int np = (int)c->pats.size();
+  std::vector<int> rep(np, -1);
+  for (int k = 0; k < n_inst; ++k)
+    if (rep[c->inst[k].pat] < 0) rep[c->inst[k].pat] = k;
+  // candidates of the patterns not in the cache: every feasible block size
+  // with each slot count that gives a distinct schedule
+  std::map<std::pair<int, int>, std::vector<int>> trials;  // (bs, slots) -> patterns
+  std::vector<std::map<std::pair<int, int>, double>> cost(np);
+  std::map<uint64_t, const Symbolic *> presym;
+  for (int p = 0; p < np; ++p) {
+    PatternDev &P = c->pats[p];
+    const auto hit = g_tune_cache.find(P.hash);
+    if (hit != g_tune_cache.end()) {
+      P.bs = hit->second.bs;
+      P.slots = hit->second.slots;
+      P.tuned = true;
+      continue;
+    }
+    presym[P.hash] = &P.sym;
+    const int n = P.sym.n;
+    for (int bs : {256, 512, 1024}) {
+      if (n > max_rows_per_thread(bs) * bs || (bs == 1024 && n <= 2048)) continue;
+      std::vector<std::pair<int, int>> seen;
+      for (int slots : {0, 1, 2, 4, 8}) {
+        int pl = 0, pu = 0;
+        if (!effective_slots(P.sym, bs, slots, pl, pu)) continue;
+        if (std::find(seen.begin(), seen.end(), std::make_pair(pl, pu)) != seen.end()) continue;
+        seen.push_back({pl, pu});
+        trials[{bs, slots}].push_back(p);
+      }
+    }
+  }
+  constexpr int kTuneSteps = 24;
+  for (const auto &tr : trials) {
+    const std::vector<int> &pats = tr.second;
+    std::vector<expri_circuit> cs;
+    for (int p : pats) cs.push_back(ckt[rep[p]]);
+    expri_opts o2 = c->opts;
+    o2.autotune = 0;
+    o2.block_size = tr.first.first;
+    o2.solve_slots = tr.first.second;
+    o2.private_patterns = 0;
+    o2.max_workgroups = 0;
+    o2.trace_cap = kTuneSteps;
+    expri_ctx *t = nullptr;
+    t_presym = &presym;
+    expri_status s = expri_setup(&t, cs.data(), (int32_t)cs.size(), &o2, c->stream);
+    t_presym = nullptr;
+    ++g_tune_runs;
+    std::vector<double *> xs(cs.size(), nullptr);
+    std::vector<double> tc;
+    bool ok = s == EXPRI_OK;
+    for (size_t q = 0; q < cs.size() && ok; ++q)
+      ok = hipMalloc(reinterpret_cast<void **>(&xs[q]), sizeof(double) * cs[q].n) == hipSuccess &&
+           hipMemsetAsync(xs[q], 0, sizeof(double) * cs[q].n, c->stream) == hipSuccess;
+    if (ok) ok = expri_dc(t, xs.data(), 0.0) == EXPRI_OK;
+    if (ok) ok = trial_cost(t, xs.data(), kTuneSteps, tc) == EXPRI_OK;
+    for (double *x : xs)
+      if (x) (void)hipFree(x);
+    expri_destroy(t);
+    if (!ok) continue;  // this configuration stays unmeasured (infinite cost)
+    for (size_t q = 0; q < pats.size(); ++q) cost[pats[q]][tr.first] = tc[q];
+  }
+  // the rule's configuration unless another is 3 % faster
+  for (int p = 0; p < np; ++p) {
+    PatternDev &P = c->pats[p];
+    if (P.tuned) continue;
+    TuneChoice ch{rule_block_size(P.sym.n), c->opts.solve_slots};
+    double best = INFINITY;
+    for (const auto &kv : cost[p])
+      if (kv.first.first == ch.bs && kv.first.second == ch.slots) best = kv.second;
+    if (!(best < INFINITY)) {  // the rule's slot count may have been folded into another candidate
+      int pl0 = 0, pu0 = 0;
+      if (effective_slots(P.sym, ch.bs, ch.slots, pl0, pu0))
+        for (const auto &kv : cost[p]) {
+          int pl = 0, pu = 0;
+          if (kv.first.first == ch.bs && effective_slots(P.sym, ch.bs, kv.first.second, pl, pu) && pl == pl0 &&
+              pu == pu0)
+            best = kv.second;
+        }
+    }
+    for (const auto &kv : cost[p])
+      if (kv.second < 0.97 * best) {
+        best = kv.second;
+        ch = TuneChoice{kv.first.first, kv.first.second};
+      }
+    P.bs = ch.bs;
+    P.slots = ch.slots;
+    P.tuned = true;
+    g_tune_cache[P.hash] = ch;
+  }
+  return EXPRI_OK;
+}
+
 expri_status setup_grid(expri_ctx *c, const expri_circuit *ckt, int32_t n_inst) {
   const expri_opts &op = c->opts;
   if (n_inst != 1) return fail(c, EXPRI_EINVAL, "the multifrontal engine takes one circuit");
@@ -663,6 +827,7 @@ expri_status expri_default_opts(expri_opts *o) {
   o->max_workgroups = 0;
   o->engine = 0;
   o->private_patterns = 0;
+  o->autotune = 0;
   o->gamma = 0.1;
   return EXPRI_OK;
 }
@@ -684,6 +849,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       (op.solve_slots != 0 && op.solve_slots != 1 && op.solve_slots != 2 && op.solve_slots != 4 &&
        op.solve_slots != 8) ||
       op.max_workgroups < 0 || op.engine < 0 || op.engine > 2 || (op.private_patterns != 0 && op.private_patterns != 1) ||
+      (op.autotune != 0 && op.autotune != 1) ||
       (op.block_size != 0 && op.block_size != 256 && op.block_size != 512 && op.block_size != 1024)) {
     *out = c.release();
     (*out)->err = "invalid options";
@@ -718,7 +884,11 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       if (!same) { *out = c.release(); (*out)->err = "pattern hash collision"; return EXPRI_EPATTERN; }
     } else {
       PatternDev P;
-      if (!analyse(pin, P.sym)) {
+      P.hash = h;
+      const auto pre = t_presym ? t_presym->find(h) : std::map<uint64_t, const Symbolic *>::const_iterator();
+      if (t_presym && pre != t_presym->end()) {
+        P.sym = *pre->second;
+      } else if (!analyse(pin, P.sym)) {
         *out = c.release();
         (*out)->err = "instance " + std::to_string(k) + ": " + P.sym.error;
         return EXPRI_EINVAL;
@@ -754,9 +924,17 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   // (or the block size the options force); the instances of one block size
   // and one rows-per-thread bound of the transient kernel form a launch
   // class ----
+  if (op.autotune) {
+    if ((s = autotune(c.get(), ckt, n_inst)) != EXPRI_OK) {
+      *out = c.release();
+      return s;
+    }
+  }
   for (auto &P : c->pats) {
-    P.bs = op.block_size ? op.block_size
-                         : (P.sym.n <= 2048 ? 256 : P.sym.n <= max_rows_per_thread(512) * 512 ? 512 : 1024);
+    if (!P.tuned) {
+      P.bs = op.block_size ? op.block_size : rule_block_size(P.sym.n);
+      P.slots = op.solve_slots;
+    }
     if (P.sym.n > max_rows_per_thread(P.bs) * P.bs) {
       *out = c.release();
       (*out)->err = "block size " + std::to_string(P.bs) + " too small for n = " + std::to_string(P.sym.n);
@@ -803,10 +981,10 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   // flattened solve schedules and the C ELL pattern for the pattern's block size
   for (auto &P : c->pats) {
     P.u_slot_base = -1;
-    if (build_solve_schedule(P.sym, P.bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots)) {
+    if (build_solve_schedule(P.sym, P.bs, true, P.lsched, P.slot_pos, P.slot_col, P.row_of, P.slots)) {
       P.u_slot_base = (int32_t)P.slot_pos.size();
       P.u_row_base = (int32_t)P.row_of.size();
-      if (!build_solve_schedule(P.sym, P.bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of, op.solve_slots))
+      if (!build_solve_schedule(P.sym, P.bs, false, P.usched, P.slot_pos, P.slot_col, P.row_of, P.slots))
         P.u_slot_base = -1;
     }
     if (P.u_slot_base < 0) {
@@ -908,23 +1086,28 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
       ++K.count;
     }
     // transient grids: the first class (largest block size) one workgroup per
-    // instance; the compute units it leaves are shared by the other classes in
-    // proportion to their instance counts (at least one workgroup each), two
-    // workgroups per compute unit at 256 and 512 threads (the kernel's
-    // register bound), so that every workgroup of every class finds a place
-    // at once.  With max_workgroups the first class is capped as well and the
-    // others get one workgroup per compute unit.
+    // instance; the compute units it leaves go to the other classes by the
+    // compute units their instances need (two workgroups per compute unit for
+    // the 9-row kernels at 256 and 512 threads, whose register bound allows
+    // it, one otherwise): every instance gets a workgroup when they all fit,
+    // else the shares are in proportion to the need (at least one workgroup
+    // each), so that every workgroup of every class finds a place at once.
+    // With max_workgroups the first class is capped as well and the others
+    // get one workgroup per compute unit.
     const int ncls = (int)c->cls.size();
     const int cus = op.max_workgroups > 0 ? op.max_workgroups : std::max(prop.multiProcessorCount, 1);
-    int rest = 0;
-    for (int q = 1; q < ncls; ++q) rest += c->cls[q].count;
     c->cls[0].grid = op.max_workgroups > 0 ? std::min(c->cls[0].count, std::max(1, cus - (ncls - 1)))
                                            : c->cls[0].count;
-    const int left = std::max(cus - c->cls[0].grid, 0);
-    for (size_t q = 1; q < c->cls.size(); ++q) {
+    const long long left = std::max(cus - c->cls[0].grid, 0);
+    auto per_cu = [&](const LaunchClass &K) { return (op.max_workgroups == 0 && K.bs <= 512 && K.em <= 9) ? 2 : 1; };
+    long long need = 0;
+    for (int q = 1; q < ncls; ++q) need += (c->cls[q].count + per_cu(c->cls[q]) - 1) / per_cu(c->cls[q]);
+    for (int q = 1; q < ncls; ++q) {
       LaunchClass &K = c->cls[q];
-      const int per_cu = (op.max_workgroups == 0 && K.bs <= 512 && K.em <= 9) ? 2 : 1;
-      K.grid = std::max(1, std::min(K.count, (int)((long long)per_cu * left * K.count / std::max(rest, 1))));
+      const int pc = per_cu(K);
+      const long long nq = (K.count + pc - 1) / pc;
+      K.grid = need <= left ? K.count
+                            : std::max(1, std::min(K.count, (int)(pc * (left * nq / std::max(need, 1LL)))));
     }
     e = hipMalloc(reinterpret_cast<void **>(&c->d_next), sizeof(int) * c->cls.size());
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_order), sizeof(int) * n_inst);
@@ -1426,6 +1609,22 @@ expri_status expri_launch_classes(const expri_ctx *c, int32_t cap, int32_t *bloc
 }
 
 const char *expri_last_error(const expri_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+expri_status expri_instance_config(const expri_ctx *c, int32_t inst, int32_t cfg[4]) {
+  if (!c || !cfg || c->grid || inst < 0 || inst >= (int32_t)c->inst.size()) return EXPRI_EINVAL;
+  const int q = c->inst_class[inst];
+  const PatternDev &P = c->pats[c->inst[inst].pat];
+  cfg[0] = P.bs;
+  cfg[1] = c->cls[q].em;
+  cfg[2] = P.pl;
+  cfg[3] = P.pu;
+  return EXPRI_OK;
+}
+
+int64_t expri_autotune_runs(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return g_tune_runs;
+}
 
 expri_status expri_controller_load(expri_ctx *c, const float *params, const float *norm, double safety) {
   if (!c) return EXPRI_EINVAL;
