@@ -42,10 +42,10 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {"sources": ("paper_1511_04515_amd/csrc/engine.hip", "paper_1511_04515_amd/csrc/layout.hpp",
                            "paper_1511_04515_amd/csrc/mlp.hpp", "paper_1511_04515_amd/csrc/devcommon.hpp",
                            "paper_1511_04515_amd/csrc/mosfet.hpp"),
-               "sha256_16": "711ec3c419adeed2", "workload": "batch", "controller": "learned",
-               "kernel": "k_run<512>",
-               "fetch_kib": 12580346293.5, "fetch_factor": 2.0,
-               "write_kib": 1849126158.0625, "write_factor": 1.0}
+               "sha256_16": "783f2eb571a083d8", "workload": "batch", "controller": "learned",
+               "kernel": "k_run<512, 9>",
+               "fetch_kib": 12462941406.8, "fetch_factor": 2.0,
+               "write_kib": 2402835445.7, "write_factor": 1.0}
 
 
 def pmc_traffic_bytes(workload, learned, nlaunch, kernel):
