@@ -142,28 +142,17 @@ __global__ void __launch_bounds__(256) k_g_extend_small(const int *parents, cons
   }
 }
 
-// Step k0 of the partial factorisation, part 1, one workgroup per front: LU
-// of the diagonal block D = F[k0.., k0..] (kb x kb, kb = min(32, nc - k0))
-// without pivoting, stored in place.  A pivot with |u| <= piv_tol * rowmax
-// sets *bad (1 + the pivot's row).
-__global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const int *c0, const int *nc,
-                                               const int *fsz, const int64_t *f_off, const unsigned long long *rowmax,
-                                               double piv_tol, double *F, int *bad) {
-  __shared__ double Dm[kNB][kNB + 1];
-  const int s = fronts[blockIdx.x];
-  const int f = fsz[s], kb = min(kNB, nc[s] - k0);
-  double *A = F + f_off[s];
-  const int t = threadIdx.x;
-  // the row maxima of the block's rows, for the pivot test after the loop
-  const double rm = t < kb ? __longlong_as_double((long long)rowmax[c0[s] + k0 + t]) : 0.0;
-  for (int e = t; e < kNB * kNB; e += 64) {
-    const int i = e % kNB, j = e / kNB;
-    Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
-  }
-  wfence();
-  // lane t keeps row t of the block in registers; at step p lane p publishes
-  // its (final) row through LDS, and the lanes below eliminate with it.  A
-  // wave's LDS operations complete in order, so no barrier is needed.
+// LU without pivoting of the kb x kb block in Dm (entries outside the block
+// zero), by one wave: on return Dm holds the unit-lower L below the diagonal
+// and U on and above it.  Lane t keeps row t in registers; at step p lane p
+// publishes its (final) row through LDS and the lanes below eliminate with
+// it.  A wave's LDS operations complete in order, so no barrier is needed.
+// Pivot test (static pivoting): |u_tt| must exceed piv_tol times rm, lane t's
+// row maximum; the first failing row of the block is kept in *bad as
+// 1 + row0 + t.
+__device__ __forceinline__ void lu_block_wave(double (*Dm)[kNB + 1], int kb, double rm, double piv_tol, int row0,
+                                              int *bad) {
+  const int t = threadIdx.x & 63;
   double rw[kNB];
 #pragma unroll
   for (int j = 0; j < kNB; ++j) rw[j] = Dm[min(t, kNB - 1)][j];
@@ -190,10 +179,31 @@ __global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const 
     for (int j = 0; j < kNB; ++j) Dm[t][j] = rw[j];
   }
   wfence();
-  // pivot test (static pivoting): |u_tt| must exceed piv_tol times the row's
-  // largest assembled magnitude; the first failing row of the block is kept
   const unsigned long long weak = __ballot(t < kb && !(fabs(Dm[t][t]) > piv_tol * rm));
-  if (weak != 0ull && t == __ffsll((long long)weak) - 1) atomicCAS(bad, 0, 1 + c0[s] + k0 + t);
+  if (weak != 0ull && t == __ffsll((long long)weak) - 1) atomicCAS(bad, 0, 1 + row0 + t);
+}
+
+// Step k0 of the partial factorisation, part 1, one wave per front: LU of the
+// 32 x 32 diagonal block at (k0, k0).  Only a level's first step and the
+// fronts whose previous step's trailing update ran inside the panel kernel
+// need it; otherwise the previous step's update tile (0, 0) has factored the
+// block (k_g_update).
+__global__ void __launch_bounds__(64) k_g_diag(const int *fronts, int k0, const int *c0, const int *nc,
+                                               const int *fsz, const int64_t *f_off, const unsigned long long *rowmax,
+                                               double piv_tol, double *F, int *bad) {
+  __shared__ double Dm[kNB][kNB + 1];
+  const int s = fronts[blockIdx.x];
+  const int f = fsz[s], kb = min(kNB, nc[s] - k0);
+  double *A = F + f_off[s];
+  const int t = threadIdx.x;
+  // the row maxima of the block's rows, for the pivot test
+  const double rm = t < kb ? __longlong_as_double((long long)rowmax[c0[s] + k0 + t]) : 0.0;
+  for (int e = t; e < kNB * kNB; e += 64) {
+    const int i = e % kNB, j = e / kNB;
+    Dm[i][j] = (i < kb && j < kb) ? A[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
+  }
+  wfence();
+  lu_block_wave(Dm, kb, rm, piv_tol, c0[s] + k0, bad);
   for (int e = t; e < kb * kb; e += 64) {
     const int i = e % kb, j = e / kb;
     A[(k0 + i) + (int64_t)(k0 + j) * f] = Dm[i][j];
@@ -280,8 +290,13 @@ __global__ void __launch_bounds__(256) k_g_panel(const int *items, int k0, int C
 // columns, on FP64 MFMA 16x16x4 (four waves, a 32 x 32 quadrant each).
 // MFMA lane layout: operand A lane i + 16 k holds A[i][k]; operand B lane
 // j + 16 k holds B[k][j]; result element v of lane j + 16 q is C[q + 4 v][j].
-__global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, const int *nc, const int *fsz,
-                                                  const int64_t *f_off, double *F) {
+// Tile (0, 0)'s first quadrant is the next step's diagonal block: when the
+// front has pivots left, its wave factors that block (lu_block_wave) before
+// storing it, so the next step needs no k_g_diag launch for this front.
+__global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, const int *c0, const int *nc,
+                                                  const int *fsz, const int64_t *f_off,
+                                                  const unsigned long long *rowmax, double piv_tol, double *F,
+                                                  int *bad) {
   __shared__ double As[kGT][kNB + 1];
   __shared__ double Bs[kNB][kGT + 1];
   const int s = items[2 * blockIdx.x], tile = items[2 * blockIdx.x + 1];
@@ -292,6 +307,10 @@ __global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, cons
   const int lane = t & 63, wave = t >> 6;
   const int r = lane & 15, q = lane >> 4;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // the next step's pivot block: rows / columns o .. o + kb2 (uniform per workgroup)
+  const int kb2 = tile == 0 ? min(kNB, nc[s] - o) : 0;
+  const double rm = (kb2 > 0 && wave == 0 && lane < kb2)
+                        ? __longlong_as_double((long long)rowmax[c0[s] + o + lane]) : 0.0;
   // the tile's loads are issued first, so that their latency overlaps the
   // staging of the panels
   dbl4 acc[2][2];
@@ -325,15 +344,29 @@ __global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, cons
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
   }
+  if (kb2 > 0) __syncthreads();  // As is free: it becomes the pivot block (uniform branch)
+  double (*Dm)[kNB + 1] = As;
+  const bool lu = kb2 > 0 && wave == 0;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wi + 16 * mi + q + 4 * v, j = j0 + wj + 16 * ni + r;
-        if (i < f && j < f) A[i + (int64_t)j * f] = acc[mi][ni][v];
+        const int li = wi + 16 * mi + q + 4 * v, lj = wj + 16 * ni + r;
+        const int i = i0 + li, j = j0 + lj;
+        const bool pivot = lu && li < kb2 && lj < kb2;
+        if (lu) Dm[li][lj] = pivot ? acc[mi][ni][v] : 0.0;
+        if (!pivot && i < f && j < f) A[i + (int64_t)j * f] = acc[mi][ni][v];
       }
+  if (lu) {
+    wfence();
+    lu_block_wave(Dm, kb2, rm, piv_tol, c0[s] + o, bad);
+    for (int e = lane; e < kb2 * kb2; e += 64) {
+      const int i = e % kb2, j = e / kb2;
+      A[(o + i) + (int64_t)(o + j) * f] = Dm[i][j];
+    }
+  }
 }
 
 // Forward solve of one tree height (L y = b, unit lower), part 1, one
@@ -806,21 +839,24 @@ hipError_t g_extend_small(int n_parents, const int *parents, const int *nc, cons
 hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *items, int k0, int C, int fuse,
                    const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                    const unsigned long long *rowmax, double piv_tol, double *F, int *bad, hipStream_t s) {
-  if (n_fronts == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_g_diag, dim3(n_fronts), dim3(64), 0, s, fronts, k0, c0, nc, fsz, f_off, rowmax, piv_tol, F,
-                     bad);
-  hipLaunchKernelGGL(k_g_panel, dim3(n_items), dim3(256), sizeof(double) * 2 * (size_t)C * (kNB + 1), s, items, k0,
-                     C, fuse, nc, fsz, f_off, F);
+  if (n_fronts > 0)
+    hipLaunchKernelGGL(k_g_diag, dim3(n_fronts), dim3(64), 0, s, fronts, k0, c0, nc, fsz, f_off, rowmax, piv_tol, F,
+                       bad);
+  if (n_items > 0)
+    hipLaunchKernelGGL(k_g_panel, dim3(n_items), dim3(256), sizeof(double) * 2 * (size_t)C * (kNB + 1), s, items,
+                       k0, C, fuse, nc, fsz, f_off, F);
   return hipGetLastError();
 }
 hipError_t g_set_limits() {
   return hipFuncSetAttribute(reinterpret_cast<const void *>(k_g_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * 2 * 128 * (kNB + 1)));
 }
-hipError_t g_update(int n_items, const int *items, int k0, const int *nc, const int *fsz, const int64_t *f_off,
-                    double *F, hipStream_t s) {
+hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const int *nc, const int *fsz,
+                    const int64_t *f_off, const unsigned long long *rowmax, double piv_tol, double *F, int *bad,
+                    hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_g_update, dim3(n_items), dim3(256), 0, s, items, k0, nc, fsz, f_off, F);
+  hipLaunchKernelGGL(k_g_update, dim3(n_items), dim3(256), 0, s, items, k0, c0, nc, fsz, f_off, rowmax, piv_tol, F,
+                     bad);
   return hipGetLastError();
 }
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,

@@ -25,8 +25,9 @@ hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *item
                    const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                    const unsigned long long *rowmax, double piv_tol, double *F, int *bad, hipStream_t s);
 hipError_t g_set_limits();
-hipError_t g_update(int n_items, const int *items, int k0, const int *nc, const int *fsz, const int64_t *f_off,
-                    double *F, hipStream_t s);
+hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const int *nc, const int *fsz,
+                    const int64_t *f_off, const unsigned long long *rowmax, double piv_tol, double *F, int *bad,
+                    hipStream_t s);
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
@@ -298,6 +299,9 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       L.n_bwd = (int32_t)((pool.size() - at_b) / 2);
       fix.push_back({at_b, nullptr});
     }
+    // fronts whose trailing update of the previous step ran as tiles: tile
+    // (0, 0) of that update has factored this step's diagonal block
+    std::vector<char> tiled(fs.nc.size(), 0);
     for (int k0 = 0; k0 < maxnc; k0 += 32) {
       Step S{};
       S.k0 = k0;
@@ -311,7 +315,7 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       S.chunk = std::min(128, std::max(8, (maxrem + 7) / 8 * 8));
       const size_t at_d = pool.size();
       for (int q = L.first; q < L.first + L.count; ++q)
-        if (fs.nc[fs.lev_front[q]] > k0) pool.push_back(fs.lev_front[q]);
+        if (fs.nc[fs.lev_front[q]] > k0 && !tiled[fs.lev_front[q]]) pool.push_back(fs.lev_front[q]);
       S.n_diag = (int32_t)(pool.size() - at_d);
       fix.push_back({at_d, nullptr});
       const size_t at_p = pool.size();
@@ -331,7 +335,9 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
         const int s_ = fs.lev_front[q];
         if (fs.nc[s_] <= k0) continue;
         const int kb = std::min(32, fs.nc[s_] - k0), rem = fs.fsz[s_] - k0 - kb;
+        tiled[s_] = 0;
         if (rem <= S.chunk && rem <= kFuse) continue;  // updated inside the panel kernel
+        tiled[s_] = 1;
         const int nt = (rem + 63) / 64;
         for (int tj = 0; tj < nt; ++tj)
           for (int ti = 0; ti < nt; ++ti) {
@@ -419,7 +425,7 @@ int GridEngine::factor_internal(const double *x) {
     for (const Step &S : L.steps) {
       GCHK(g_panel(S.n_diag, S.diag, S.n_panel, S.panel, S.k0, S.chunk, kFuse, d_c0, d_nc, d_fsz, d_f_off, d_rowmax,
                    o.piv_tol, d_F, d_bad, stream));
-      GCHK(g_update(S.n_tiles, S.tiles, S.k0, d_nc, d_fsz, d_f_off, d_F, stream));
+      GCHK(g_update(S.n_tiles, S.tiles, S.k0, d_c0, d_nc, d_fsz, d_f_off, d_rowmax, o.piv_tol, d_F, d_bad, stream));
     }
   }
   int32_t bad = 0;
