@@ -369,28 +369,40 @@ __global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, cons
   }
 }
 
+// The triangular solves with the factors of G_k, for NR right-hand sides at
+// once (NR = 1 or 2): vector r of x starts at x + r ldx and its update
+// vectors at upd + r ldu.  The factor entries are loaded once for all NR.
+
 // Forward solve of one tree height (L y = b, unit lower), part 1, one
 // workgroup per front: v = [x(cols s); 0] + the children's update vectors at
 // their relative indices; the unit-lower pivot block L11 is solved in 32-wide
 // blocks (a wave solves the block triangle, the workgroup updates the pivot
 // rows below it); y goes to x, the rest of v (the children's contributions to
 // the update vector) to upd.  Part 2 (k_g_fwd_gemv) subtracts L21 y.
+// Dynamic LDS: NR f doubles.
+template <int NR>
 __global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
                                                    const int64_t *f_off, const int *ch_ptr, const int *ch,
                                                    const int *r_ptr, const int *rel, const int *u_off,
-                                                   const double *F, double *x, double *upd) {
+                                                   const double *F, double *x, int64_t ldx, double *upd,
+                                                   int64_t ldu) {
   extern __shared__ double v[];
   const int s = fronts[blockIdx.x];
   const int f = fsz[s], p = nc[s], b = c0[s];
   const double *A = F + f_off[s];
   const int t = threadIdx.x;
-  for (int i = t; i < f; i += 256) v[i] = i < p ? x[b + i] : 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int i = t; i < f; i += 256) v[r * f + i] = i < p ? x[r * ldx + b + i] : 0.0;
   __syncthreads();
   for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
     const int c = ch[q], rc = fsz[c] - nc[c];
     const int *rl = rel + r_ptr[c];
-    const double *uc = upd + u_off[c];
-    for (int a = t; a < rc; a += 256) v[rl[a]] += uc[a];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double *uc = upd + r * ldu + u_off[c];
+      for (int a = t; a < rc; a += 256) v[r * f + rl[a]] += uc[a];
+    }
     __syncthreads();
   }
   for (int b0 = 0; b0 < p; b0 += kNB) {
@@ -402,57 +414,86 @@ __global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int 
       const int rt = b0 + min(t, bw - 1);
 #pragma unroll
       for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
-      double vl = t < bw ? v[b0 + t] : 0.0;
+      double vl[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) vl[r] = t < bw ? v[r * f + b0 + t] : 0.0;
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         if (j < bw) {
-          const double z = readlane_d(vl, j);
-          if (t > j) vl -= col[j] * z;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double z = readlane_d(vl[r], j);
+            if (t > j) vl[r] -= col[j] * z;
+          }
         }
       }
-      if (t < bw) v[b0 + t] = vl;
+      if (t < bw) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r * f + b0 + t] = vl[r];
+      }
     }
     __syncthreads();
     for (int i = b0 + bw + t; i < p; i += 256) {
-      double acc = v[i];
+      double acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = v[r * f + i];
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         const double a = A[i + (int64_t)(b0 + min(j, bw - 1)) * f];
-        acc -= a * (j < bw ? v[b0 + j] : 0.0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] -= a * (j < bw ? v[r * f + b0 + j] : 0.0);
       }
-      v[i] = acc;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[r * f + i] = acc[r];
     }
     __syncthreads();
   }
-  for (int i = t; i < f; i += 256) {
-    if (i < p) x[b + i] = v[i];
-    else upd[u_off[s] + i - p] = v[i];
-  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int i = t; i < f; i += 256) {
+      if (i < p) x[r * ldx + b + i] = v[r * f + i];
+      else upd[r * ldu + u_off[s] + i - p] = v[r * f + i];
+    }
 }
 
 // Forward solve, part 2: item = (front s, chunk of 64 update rows):
 // upd_s[a] -= L21[a, :] y_s.  Each wave sums a quarter of the pivot columns
 // for the chunk's 64 rows (one row per lane); the quarters are added in order.
+// Dynamic LDS: NR nc doubles.
+template <int NR>
 __global__ void __launch_bounds__(256) k_g_fwd_gemv(const int *items, const int *c0, const int *nc, const int *fsz,
                                                     const int64_t *f_off, const int *u_off, const double *F,
-                                                    const double *x, double *upd) {
+                                                    const double *x, int64_t ldx, double *upd, int64_t ldu) {
   extern __shared__ double ys[];
-  __shared__ double red[4][64];
+  __shared__ double red[NR][4][64];
   const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
-  const int f = fsz[s], p = nc[s], r = f - p;
+  const int f = fsz[s], p = nc[s], r_ = f - p;
   const double *A = F + f_off[s];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int j = t; j < p; j += 256) ys[j] = x[c0[s] + j];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int j = t; j < p; j += 256) ys[r * p + j] = x[r * ldx + c0[s] + j];
   __syncthreads();
   const int a = chunk * 64 + lane;
-  const int ra = p + min(a, r - 1);
+  const int ra = p + min(a, r_ - 1);
   const int q = (p + 3) / 4, j0 = w * q, j1 = min(p, j0 + q);
-  double acc = 0.0;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
 #pragma unroll 16
-  for (int j = j0; j < j1; ++j) acc += A[ra + (int64_t)j * f] * ys[j];
-  red[w][lane] = acc;
+  for (int j = j0; j < j1; ++j) {
+    const double l = A[ra + (int64_t)j * f];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] += l * ys[r * p + j];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r][w][lane] = acc[r];
   __syncthreads();
-  if (w == 0 && a < r) upd[u_off[s] + a] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (w == 0 && a < r_) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      upd[r * ldu + u_off[s] + a] -= (red[r][0][lane] + red[r][1][lane]) + (red[r][2][lane] + red[r][3][lane]);
+  }
 }
 
 // Forward solve of the small fronts of a height (f <= 64), one wave per
@@ -460,101 +501,149 @@ __global__ void __launch_bounds__(256) k_g_fwd_gemv(const int *items, const int 
 // holds v[l]; the children's update vectors are added through the wave's own
 // LDS slice; then for each pivot column j the lanes below j subtract
 // L[l, j] y_j (pivot rows and update rows alike).
+template <int NR>
 __global__ void __launch_bounds__(256) k_g_fwd_small(const int *fronts, int count, const int *c0, const int *nc,
                                                      const int *fsz, const int64_t *f_off, const int *ch_ptr,
                                                      const int *ch, const int *r_ptr, const int *rel,
-                                                     const int *u_off, const double *F, double *x, double *upd) {
-  __shared__ double sv[4][64];
+                                                     const int *u_off, const double *F, double *x, int64_t ldx,
+                                                     double *upd, int64_t ldu) {
+  __shared__ double sv[NR][4][64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int idx = blockIdx.x * 4 + w;
   if (idx >= count) return;  // the whole wave
   const int s = fronts[idx];
   const int f = fsz[s], p = nc[s], b = c0[s];
   const double *A = F + f_off[s];
-  double *vs = sv[w];
-  vs[l] = l < p ? x[b + l] : 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) sv[r][w][l] = l < p ? x[r * ldx + b + l] : 0.0;
   wfence();
   for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
     const int c = ch[q], rc = fsz[c] - nc[c];  // rc <= f <= 64
-    if (l < rc) vs[rel[r_ptr[c] + l]] += upd[u_off[c] + l];
+    if (l < rc) {
+      const int dst = rel[r_ptr[c] + l];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sv[r][w][dst] += upd[r * ldu + u_off[c] + l];
+    }
     wfence();
   }
-  double v = vs[l];
+  double v[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) v[r] = sv[r][w][l];
   const int lr = min(l, f - 1);
   double a_next = A[lr];
   for (int j = 0; j < p; ++j) {
     const double a = a_next;
     a_next = A[lr + (int64_t)min(j + 1, p - 1) * f];
-    const double z = readlane_d(v, j);
-    if (l > j && l < f) v -= a * z;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double z = readlane_d(v[r], j);
+      if (l > j && l < f) v[r] -= a * z;
+    }
   }
-  if (l < p) x[b + l] = v;
-  else if (l < f) upd[u_off[s] + l - p] = v;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (l < p) x[r * ldx + b + l] = v[r];
+    else if (l < f) upd[r * ldu + u_off[s] + l - p] = v[r];
+  }
 }
 
 // Backward solve of the small fronts (f <= 64), one wave per front: lane l
 // holds y[l] (pivot rows) or x(R_s) (update rows); U12 x(R_s) is subtracted
 // column by column, then the upper pivot block is solved from the last row.
+template <int NR>
 __global__ void __launch_bounds__(256) k_g_bwd_small(const int *fronts, int count, const int *c0, const int *nc,
                                                      const int *fsz, const int64_t *f_off, const int *r_ptr,
-                                                     const int *r_idx, const double *F, double *x) {
+                                                     const int *r_idx, const double *F, double *x, int64_t ldx) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int idx = blockIdx.x * 4 + w;
   if (idx >= count) return;
   const int s = fronts[idx];
-  const int f = fsz[s], p = nc[s], b = c0[s], r = f - p;
+  const int f = fsz[s], p = nc[s], b = c0[s], r_ = f - p;
   const double *A = F + f_off[s];
-  double v = l < p ? x[b + l] : (l < f ? x[r_idx[r_ptr[s] + l - p]] : 0.0);
+  double v[NR];
+  const int src = l < p ? b + l : (l < f ? r_idx[r_ptr[s] + l - p] : -1);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) v[r] = src >= 0 ? x[r * ldx + src] : 0.0;
   const int lr = min(l, p - 1);
-  for (int a = 0; a < r; ++a) {
+  for (int a = 0; a < r_; ++a) {
     const double u = A[lr + (int64_t)(p + a) * f];
-    const double z = readlane_d(v, p + a);
-    if (l < p) v -= u * z;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double z = readlane_d(v[r], p + a);
+      if (l < p) v[r] -= u * z;
+    }
   }
   for (int j = p - 1; j >= 0; --j) {
     const double u = A[lr + (int64_t)j * f];
-    if (l == j) v = v / u;
-    const double z = readlane_d(v, j);
-    if (l < j) v -= u * z;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (l == j) v[r] = v[r] / u;
+      const double z = readlane_d(v[r], j);
+      if (l < j) v[r] -= u * z;
+    }
   }
-  if (l < p) x[b + l] = v;
+  if (l < p) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x[r * ldx + b + l] = v[r];
+  }
 }
 
 // Backward solve (U x = y), part 1: item = (front s, chunk of 64 pivot rows):
 // x(cols s)[i] = y[i] - U12[i, :] x(R_s), x(R_s) being final (the ancestors
-// are done).  Waves split R_s in quarters, added in order.
+// are done).  Waves split R_s in quarters, added in order.  Dynamic LDS:
+// NR (f - nc) doubles.
+template <int NR>
 __global__ void __launch_bounds__(256) k_g_bwd_gemv(const int *items, const int *c0, const int *nc, const int *fsz,
                                                     const int64_t *f_off, const int *r_ptr, const int *r_idx,
-                                                    const double *F, double *x) {
+                                                    const double *F, double *x, int64_t ldx) {
   extern __shared__ double xr[];
-  __shared__ double red[4][64];
+  __shared__ double red[NR][4][64];
   const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
-  const int f = fsz[s], p = nc[s], r = f - p;
+  const int f = fsz[s], p = nc[s], r_ = f - p;
   const double *A = F + f_off[s];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int k = t; k < r; k += 256) xr[k] = x[r_idx[r_ptr[s] + k]];
+  for (int k = t; k < r_; k += 256) {
+    const int g = r_idx[r_ptr[s] + k];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) xr[r * r_ + k] = x[r * ldx + g];
+  }
   __syncthreads();
   const int i = chunk * 64 + lane;
   const int ri = min(i, p - 1);
-  const int q = (r + 3) / 4, k0 = w * q, k1 = min(r, k0 + q);
-  double acc = 0.0;
+  const int q = (r_ + 3) / 4, k0 = w * q, k1 = min(r_, k0 + q);
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
 #pragma unroll 16
-  for (int k = k0; k < k1; ++k) acc += A[ri + (int64_t)(p + k) * f] * xr[k];
-  red[w][lane] = acc;
+  for (int k = k0; k < k1; ++k) {
+    const double u = A[ri + (int64_t)(p + k) * f];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] += u * xr[r * r_ + k];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r][w][lane] = acc[r];
   __syncthreads();
-  if (w == 0 && i < p) x[c0[s] + i] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (w == 0 && i < p) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      x[r * ldx + c0[s] + i] -= (red[r][0][lane] + red[r][1][lane]) + (red[r][2][lane] + red[r][3][lane]);
+  }
 }
 
 // Backward solve, part 2, one workgroup per front: the upper pivot block U11
 // in 32-wide blocks from the last, each block updating the pivot rows above.
+// Dynamic LDS: NR nc doubles.
+template <int NR>
 __global__ void __launch_bounds__(256) k_g_bwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
-                                                   const int64_t *f_off, const double *F, double *x) {
+                                                   const int64_t *f_off, const double *F, double *x, int64_t ldx) {
   extern __shared__ double v[];
   const int s = fronts[blockIdx.x];
   const int f = fsz[s], p = nc[s], b = c0[s];
   const double *A = F + f_off[s];
   const int t = threadIdx.x;
-  for (int i = t; i < p; i += 256) v[i] = x[b + i];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int i = t; i < p; i += 256) v[r * p + i] = x[r * ldx + b + i];
   __syncthreads();
   for (int b0 = ((p - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
     const int bw = min(kNB, p - b0);
@@ -563,30 +652,44 @@ __global__ void __launch_bounds__(256) k_g_bwd_tri(const int *fronts, const int 
       const int rt = b0 + min(t, bw - 1);
 #pragma unroll
       for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
-      double vl = t < bw ? v[b0 + t] : 0.0;
+      double vl[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) vl[r] = t < bw ? v[r * p + b0 + t] : 0.0;
 #pragma unroll
       for (int j = kNB - 1; j >= 0; --j) {
         if (j < bw) {
-          if (t == j) vl = vl / col[j];
-          const double z = readlane_d(vl, j);
-          if (t < j) vl -= col[j] * z;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            if (t == j) vl[r] = vl[r] / col[j];
+            const double z = readlane_d(vl[r], j);
+            if (t < j) vl[r] -= col[j] * z;
+          }
         }
       }
-      if (t < bw) v[b0 + t] = vl;
+      if (t < bw) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r * p + b0 + t] = vl[r];
+      }
     }
     __syncthreads();
     for (int i = t; i < b0; i += 256) {
-      double acc = v[i];
+      double acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = v[r * p + i];
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         const double a = A[i + (int64_t)(b0 + min(j, bw - 1)) * f];
-        acc -= a * (j < bw ? v[b0 + j] : 0.0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] -= a * (j < bw ? v[r * p + b0 + j] : 0.0);
       }
-      v[i] = acc;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[r * p + i] = acc[r];
     }
     __syncthreads();
   }
-  for (int i = t; i < p; i += 256) x[b + i] = v[i];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int i = t; i < p; i += 256) x[r * ldx + b + i] = v[r * p + i];
 }
 
 // PWL sources: u(t) and the slope on the piece holding tm
@@ -862,30 +965,44 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
-                 double *x, double *upd, hipStream_t s) {
-  if (n_small > 0)
-    hipLaunchKernelGGL(k_g_fwd_small, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz, f_off,
-                       ch_ptr, ch, r_ptr, rel, u_off, F, x, upd);
-  if (n_big > 0)
-    hipLaunchKernelGGL(k_g_fwd_tri, dim3(n_big), dim3(256), sizeof(double) * (size_t)max_f, s, big, c0, nc, fsz,
-                       f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, upd);
-  if (n_items > 0)
-    hipLaunchKernelGGL(k_g_fwd_gemv, dim3(n_items), dim3(256), sizeof(double) * (size_t)max_nc, s, items, c0, nc,
-                       fsz, f_off, u_off, F, x, upd);
+                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, hipStream_t s) {
+#define G_FWD(NR)                                                                                                   \
+  if (n_small > 0)                                                                                                  \
+    hipLaunchKernelGGL(k_g_fwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
+                       f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);                                  \
+  if (n_big > 0)                                                                                                    \
+    hipLaunchKernelGGL(k_g_fwd_tri<NR>, dim3(n_big), dim3(256), sizeof(double) * NR * (size_t)max_f, s, big, c0,    \
+                       nc, fsz, f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);                         \
+  if (n_items > 0)                                                                                                  \
+    hipLaunchKernelGGL(k_g_fwd_gemv<NR>, dim3(n_items), dim3(256), sizeof(double) * NR * (size_t)max_nc, s, items,  \
+                       c0, nc, fsz, f_off, u_off, F, x, ldx, upd, ldu);
+  if (nr == 2) {
+    G_FWD(2)
+  } else {
+    G_FWD(1)
+  }
+#undef G_FWD
   return hipGetLastError();
 }
 hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
-                 const int *r_ptr, const int *r_idx, const double *F, double *x, hipStream_t s) {
-  if (n_small > 0)
-    hipLaunchKernelGGL(k_g_bwd_small, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz, f_off,
-                       r_ptr, r_idx, F, x);
-  if (n_items > 0)
-    hipLaunchKernelGGL(k_g_bwd_gemv, dim3(n_items), dim3(256), sizeof(double) * (size_t)max_f, s, items, c0, nc, fsz,
-                       f_off, r_ptr, r_idx, F, x);
-  if (n_big > 0)
-    hipLaunchKernelGGL(k_g_bwd_tri, dim3(n_big), dim3(256), sizeof(double) * (size_t)max_nc, s, big, c0, nc, fsz,
-                       f_off, F, x);
+                 const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, hipStream_t s) {
+#define G_BWD(NR)                                                                                                   \
+  if (n_small > 0)                                                                                                  \
+    hipLaunchKernelGGL(k_g_bwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
+                       f_off, r_ptr, r_idx, F, x, ldx);                                                             \
+  if (n_items > 0)                                                                                                  \
+    hipLaunchKernelGGL(k_g_bwd_gemv<NR>, dim3(n_items), dim3(256), sizeof(double) * NR * (size_t)max_f, s, items,   \
+                       c0, nc, fsz, f_off, r_ptr, r_idx, F, x, ldx);                                                \
+  if (n_big > 0)                                                                                                    \
+    hipLaunchKernelGGL(k_g_bwd_tri<NR>, dim3(n_big), dim3(256), sizeof(double) * NR * (size_t)max_nc, s, big, c0,   \
+                       nc, fsz, f_off, F, x, ldx);
+  if (nr == 2) {
+    G_BWD(2)
+  } else {
+    G_BWD(1)
+  }
+#undef G_BWD
   return hipGetLastError();
 }
 hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,

@@ -31,10 +31,10 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
-                 double *x, double *upd, hipStream_t s);
+                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, hipStream_t s);
 hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
-                 const int *r_ptr, const int *r_idx, const double *F, double *x, hipStream_t s);
+                 const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, hipStream_t s);
 hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,
                      double *u, double *slope, hipStream_t s);
 hipError_t g_rhs(int n, const int *g_rowptr, const int *g_col, const double *g_val, const int *b_rowptr,
@@ -373,10 +373,11 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
   ldv = ((int64_t)n + 31) / 32 * 32;
   const int cols = o.m_max + 1;
   d_F = dalloc<double>(fs.front_doubles);
-  d_upd = dalloc<double>(fs.upd_doubles);
+  d_upd = dalloc<double>(2 * fs.upd_doubles);  // update vectors of up to two right-hand sides
   d_rowmax = dalloc<unsigned long long>(n);
   d_bad = dalloc<int32_t>(1);
-  d_xk = dalloc<double>(n); d_x1 = dalloc<double>(n); d_w = dalloc<double>(n); d_p = dalloc<double>(n);
+  // w and p side by side: they are solved together
+  d_xk = dalloc<double>(n); d_x1 = dalloc<double>(n); d_w = dalloc<double>(2 * (size_t)n); d_p = d_w + n;
   d_z = dalloc<double>(n); d_r = dalloc<double>(n); d_bs = dalloc<double>(n); d_e = dalloc<double>(n);
   d_y = dalloc<double>(n);
   d_u = dalloc<double>(std::max(val.n_src, 1)); d_sl = dalloc<double>(std::max(val.n_src, 1));
@@ -437,14 +438,20 @@ int GridEngine::factor_internal(const double *x) {
   return kSOK;
 }
 
-int GridEngine::solve_internal(double *b) {
+int GridEngine::solve_internal(double *b, int nr) {
+  // two right-hand sides (b and b + n) share the factor loads; their vectors
+  // need 2 max(f) doubles of LDS in one workgroup
+  if (nr == 2 && 2 * sizeof(double) * (size_t)std::max(fs.max_front, fs.max_nc) > 65536) {
+    GRET(solve_internal(b, 1));
+    return solve_internal(b + fs.n, 1);
+  }
   for (const Level &L : levels)
     GCHK(g_fwd(L.n_small, L.small, L.n_big, L.big, L.n_fwd, L.fwd, fs.max_front, fs.max_nc, d_c0, d_nc, d_fsz,
-               d_f_off, d_ch_ptr, d_ch, d_r_ptr, d_rel, d_u_off, d_F, b, d_upd, stream));
+               d_f_off, d_ch_ptr, d_ch, d_r_ptr, d_rel, d_u_off, d_F, b, nr, fs.n, d_upd, fs.upd_doubles, stream));
   for (int h = (int)levels.size() - 1; h >= 0; --h) {
     const Level &L = levels[h];
     GCHK(g_bwd(L.n_small, L.small, L.n_big, L.big, L.n_bwd, L.bwd, fs.max_front, fs.max_nc, d_c0, d_nc, d_fsz,
-               d_f_off, d_r_ptr, d_r_idx, d_F, b, stream));
+               d_f_off, d_r_ptr, d_r_idx, d_F, b, nr, fs.n, stream));
   }
   return kSOK;
 }
@@ -625,8 +632,7 @@ int GridEngine::run(double *x_caller, double t0, const double *grid, int32_t n_g
     GCHK(g_sources(fs.n_src, d_src_ptr, d_src_t, d_src_v, t, t + 0.5 * h_try, d_u, d_sl, stream));
     GCHK(g_rhs(n, d_g_rowptr, d_g_col, d_g_val, d_b_rowptr, d_b_col, d_b_val, d_node_ptr, d_node_code, d_devI0, d_xk,
                d_u, d_sl, d_w, d_p, stream));
-    GRET(solve_internal(d_w));
-    GRET(solve_internal(d_p));
+    GRET(solve_internal(d_w, 2));  // w and p (d_p = d_w + n)
     GCHK(g_spmv(n, d_c_rowptr, d_c_col, d_c_val, d_p, 1.0, d_z, stream));
     GRET(solve_internal(d_z));
     GCHK(g_sub(n, d_w, d_z, d_r, stream));

@@ -126,7 +126,7 @@ struct GridEngine {
   int fail(int code, const std::string &msg);
   int hip(hipError_t e, const char *what);
   int factor_internal(const double *x);
-  int solve_internal(double *b);  // in place, new order
+  int solve_internal(double *b, int nr = 1);  // in place, new order; nr = 2: b and b + n
   struct Basis {
     double *V, *H, *sc, *out;
     int m;
