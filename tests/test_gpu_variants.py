@@ -55,6 +55,13 @@ def test_every_kernel_variant_matches_oracle_replay(bs, E, L, forced):
     xs = s.to_device([g["x0"]])
     info = s.run_schedule(xs, [g["t"]])
     assert info[0]["status"] == 0 and info[0]["steps"] == len(g["t"])
+    # the kernel's work counters: one LU per accepted step, at most two MEVPs
+    # of m_max = 60 Arnoldi steps per trial, MGS terms between one and m_max
+    # per Arnoldi step
+    r = info[0]
+    assert r["lu_count"] == r["steps"] and r["trials"] >= r["steps"]
+    assert 0 < r["arnoldi"] <= 2 * 60 * r["trials"], r
+    assert r["arnoldi"] <= r["mgs_terms"] <= 60 * r["arnoldi"], r
     tr = s.trace(0)
     assert np.array_equal(tr["t"], g["t"])
     err = rel_wave_err(tr["x"], g["replay_probe_x"])

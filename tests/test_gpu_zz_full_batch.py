@@ -61,6 +61,10 @@ def test_full_batch_in_the_benchmark_launch_configuration():
     for i, (net, r) in enumerate(zip(nets, info)):
         assert r["status"] == 0 and r["t"] == net.T, i
         assert r["lu_count"] == r["steps"] > 0, i
+        # work counters within what the trials allow (two MEVPs of at most
+        # m_max = 60 Arnoldi steps per trial)
+        assert 0 < r["arnoldi"] <= 120 * r["trials"], (i, r)
+        assert r["arnoldi"] <= r["mgs_terms"] <= 60 * r["arnoldi"], (i, r)
         assert np.all(np.isfinite(xs[i].cpu().numpy())), i
 
     for i in picks:
