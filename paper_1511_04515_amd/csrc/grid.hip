@@ -183,6 +183,61 @@ __device__ __forceinline__ void lu_block_wave(double (*Dm)[kNB + 1], int kb, dou
   if (weak != 0ull && t == __ffsll((long long)weak) - 1) atomicCAS(bad, 0, 1 + row0 + t);
 }
 
+// Whole partial factorisation of the small fronts of a height (f <= FW,
+// FW = 32 or 64), one wave per front and four fronts per workgroup, with no
+// workgroup barrier: lane l keeps row l of the front in registers (zeros past
+// f); for each pivot p < nc lane p publishes its (final) row through the
+// wave's LDS slice and every lane below eliminates with it, pivot rows and
+// update rows alike (l_lp = a_lp / u_pp, a_lj -= l_lp u_pj for j > p).  The
+// rows go back in place: L and U in the pivot rows and columns, the Schur
+// complement in the trailing block.  Pivot test as in lu_block_wave.
+template <int FW>
+__global__ void __launch_bounds__(256) k_g_small_lu(const int *fronts, int count, const int *c0, const int *nc,
+                                                    const int *fsz, const int64_t *f_off,
+                                                    const unsigned long long *rowmax, double piv_tol, double *F,
+                                                    int *bad) {
+  __shared__ double prow[4][FW];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + w;
+  if (idx >= count) return;  // the whole wave
+  const int s = fronts[idx];
+  const int f = fsz[s], np = nc[s];
+  double *A = F + f_off[s];
+  const double rm = l < np ? __longlong_as_double((long long)rowmax[c0[s] + l]) : 0.0;
+  const int lr = min(l, f - 1);
+  double row[FW];
+#pragma unroll
+  for (int j = 0; j < FW; ++j) row[j] = (l < f && j < f) ? A[lr + (int64_t)j * f] : 0.0;
+  double *pr = prow[w];
+  double diag = 1.0;
+#pragma unroll
+  for (int p = 0; p < FW; ++p) {
+    if (p < np) {
+      if (l == p) {
+        diag = row[p];
+#pragma unroll
+        for (int j = 0; j < FW; ++j) pr[j] = row[j];
+      }
+      wfence();
+      const double piv = pr[p];
+      if (l > p) {
+        const double m = row[p] / piv;
+        row[p] = m;
+#pragma unroll
+        for (int j = p + 1; j < FW; ++j) row[j] -= m * pr[j];
+      }
+      wfence();
+    }
+  }
+  const unsigned long long weak = __ballot(l < np && !(fabs(diag) > piv_tol * rm));
+  if (weak != 0ull && l == __ffsll((long long)weak) - 1) atomicCAS(bad, 0, 1 + c0[s] + l);
+  if (l < f) {
+#pragma unroll
+    for (int j = 0; j < FW; ++j)
+      if (j < f) A[l + (int64_t)j * f] = row[j];
+  }
+}
+
 // Step k0 of the partial factorisation, part 1, one wave per front: LU of the
 // 32 x 32 diagonal block at (k0, k0).  Only a level's first step and the
 // fronts whose previous step's trailing update ran inside the panel kernel
@@ -948,6 +1003,17 @@ hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *item
   if (n_items > 0)
     hipLaunchKernelGGL(k_g_panel, dim3(n_items), dim3(256), sizeof(double) * 2 * (size_t)C * (kNB + 1), s, items,
                        k0, C, fuse, nc, fsz, f_off, F);
+  return hipGetLastError();
+}
+hipError_t g_small_lu(int n32, const int *f32, int n64, const int *f64, const int *c0, const int *nc, const int *fsz,
+                      const int64_t *f_off, const unsigned long long *rowmax, double piv_tol, double *F, int *bad,
+                      hipStream_t s) {
+  if (n32 > 0)
+    hipLaunchKernelGGL(k_g_small_lu<32>, dim3((n32 + 3) / 4), dim3(256), 0, s, f32, n32, c0, nc, fsz, f_off, rowmax,
+                       piv_tol, F, bad);
+  if (n64 > 0)
+    hipLaunchKernelGGL(k_g_small_lu<64>, dim3((n64 + 3) / 4), dim3(256), 0, s, f64, n64, c0, nc, fsz, f_off, rowmax,
+                       piv_tol, F, bad);
   return hipGetLastError();
 }
 hipError_t g_set_limits() {

@@ -21,6 +21,9 @@ hipError_t g_extend(int n_items, const int *items, const int *nc, const int *fsz
                     const int64_t *f_off, const int *r_ptr, const int *rel, double *F, hipStream_t s);
 hipError_t g_extend_small(int n_parents, const int *parents, const int *nc, const int *fsz, const int64_t *f_off,
                           const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, double *F, hipStream_t s);
+hipError_t g_small_lu(int n32, const int *f32, int n64, const int *f64, const int *c0, const int *nc, const int *fsz,
+                      const int64_t *f_off, const unsigned long long *rowmax, double piv_tol, double *F, int *bad,
+                      hipStream_t s);
 hipError_t g_panel(int n_fronts, const int *fronts, int n_items, const int *items, int k0, int C, int fuse,
                    const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                    const unsigned long long *rowmax, double piv_tol, double *F, int *bad, hipStream_t s);
@@ -210,11 +213,14 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
     Level &L = levels[h];
     L.first = fs.lev_ptr[h];
     L.count = fs.lev_ptr[h + 1] - fs.lev_ptr[h];
+    // fronts with f <= 64 are factored whole by one wave each (k_g_small_lu);
+    // the pivot steps below are for the larger ones
+    auto small_front = [&](int s_) { return fs.fsz[s_] <= 64; };
     int maxch = 0, maxnc = 0;
     for (int q = L.first; q < L.first + L.count; ++q) {
       const int s_ = fs.lev_front[q];
       maxch = std::max(maxch, fs.ch_ptr[s_ + 1] - fs.ch_ptr[s_]);
-      maxnc = std::max(maxnc, fs.nc[s_]);
+      if (!small_front(s_)) maxnc = std::max(maxnc, fs.nc[s_]);
     }
     // children with update matrices of at most 32 x 32 are added by one
     // workgroup per parent; the larger ones in passes of 32 x 32 tiles, the
@@ -299,6 +305,22 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       L.n_bwd = (int32_t)((pool.size() - at_b) / 2);
       fix.push_back({at_b, nullptr});
     }
+    {
+      const size_t at32 = pool.size();
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int s_ = fs.lev_front[q];
+        if (fs.nc[s_] > 0 && fs.fsz[s_] <= 32) pool.push_back(s_);
+      }
+      L.n_lu32 = (int32_t)(pool.size() - at32);
+      fix.push_back({at32, nullptr});
+      const size_t at64 = pool.size();
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int s_ = fs.lev_front[q];
+        if (fs.nc[s_] > 0 && fs.fsz[s_] > 32 && fs.fsz[s_] <= 64) pool.push_back(s_);
+      }
+      L.n_lu64 = (int32_t)(pool.size() - at64);
+      fix.push_back({at64, nullptr});
+    }
     // fronts whose trailing update of the previous step ran as tiles: tile
     // (0, 0) of that update has factored this step's diagonal block
     std::vector<char> tiled(fs.nc.size(), 0);
@@ -310,18 +332,20 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       int maxrem = 0;
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int s_ = fs.lev_front[q];
-        if (fs.nc[s_] > k0) maxrem = std::max(maxrem, fs.fsz[s_] - k0 - std::min(32, fs.nc[s_] - k0));
+        if (fs.nc[s_] > k0 && !small_front(s_))
+          maxrem = std::max(maxrem, fs.fsz[s_] - k0 - std::min(32, fs.nc[s_] - k0));
       }
       S.chunk = std::min(128, std::max(8, (maxrem + 7) / 8 * 8));
       const size_t at_d = pool.size();
       for (int q = L.first; q < L.first + L.count; ++q)
-        if (fs.nc[fs.lev_front[q]] > k0 && !tiled[fs.lev_front[q]]) pool.push_back(fs.lev_front[q]);
+        if (fs.nc[fs.lev_front[q]] > k0 && !tiled[fs.lev_front[q]] && !small_front(fs.lev_front[q]))
+          pool.push_back(fs.lev_front[q]);
       S.n_diag = (int32_t)(pool.size() - at_d);
       fix.push_back({at_d, nullptr});
       const size_t at_p = pool.size();
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int s_ = fs.lev_front[q];
-        if (fs.nc[s_] <= k0) continue;
+        if (fs.nc[s_] <= k0 || small_front(s_)) continue;
         const int rem = fs.fsz[s_] - k0 - std::min(32, fs.nc[s_] - k0);
         const int nch = std::max(1, (rem + S.chunk - 1) / S.chunk);
         for (int c = 0; c < nch; ++c) {
@@ -333,7 +357,7 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       const size_t at_t = pool.size();
       for (int q = L.first; q < L.first + L.count; ++q) {
         const int s_ = fs.lev_front[q];
-        if (fs.nc[s_] <= k0) continue;
+        if (fs.nc[s_] <= k0 || small_front(s_)) continue;
         const int kb = std::min(32, fs.nc[s_] - k0), rem = fs.fsz[s_] - k0 - kb;
         tiled[s_] = 0;
         if (rem <= S.chunk && rem <= kFuse) continue;  // updated inside the panel kernel
@@ -362,6 +386,8 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       levels[h].big = d_pool + fix[f++].first;
       levels[h].fwd = d_pool + fix[f++].first;
       levels[h].bwd = d_pool + fix[f++].first;
+      levels[h].lu32 = d_pool + fix[f++].first;
+      levels[h].lu64 = d_pool + fix[f++].first;
       for (auto &S : levels[h].steps) {
         S.diag = d_pool + fix[f++].first;
         S.panel = d_pool + fix[f++].first;
@@ -423,6 +449,8 @@ int GridEngine::factor_internal(const double *x) {
                         stream));
     for (const auto &e : L.extend)
       GCHK(g_extend(e.first, e.second, d_nc, d_fsz, d_parent, d_f_off, d_r_ptr, d_rel, d_F, stream));
+    GCHK(g_small_lu(L.n_lu32, L.lu32, L.n_lu64, L.lu64, d_c0, d_nc, d_fsz, d_f_off, d_rowmax, o.piv_tol, d_F, d_bad,
+                    stream));
     for (const Step &S : L.steps) {
       GCHK(g_panel(S.n_diag, S.diag, S.n_panel, S.panel, S.k0, S.chunk, kFuse, d_c0, d_nc, d_fsz, d_f_off, d_rowmax,
                    o.piv_tol, d_F, d_bad, stream));

@@ -74,6 +74,8 @@ struct GridEngine {
     int32_t *small = nullptr, *big = nullptr;
     int32_t n_fwd = 0, n_bwd = 0;  // solve GEMV items (front, 64-row chunk)
     int32_t *fwd = nullptr, *bwd = nullptr;
+    int32_t n_lu32 = 0, n_lu64 = 0;  // fronts factored whole by one wave (f <= 32, f <= 64)
+    int32_t *lu32 = nullptr, *lu64 = nullptr;
     std::vector<Step> steps;
   };
   std::vector<Level> levels;
