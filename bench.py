@@ -296,7 +296,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is not sharded "
-              f"across GPUs in this build", file=sys.stderr)
+              f"across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -430,7 +430,7 @@ void expri_destroy(expri_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
  * Learned step controller (not part of the paper; an addition to Algorithm
- * 2's step control, whose error test stays the judge).  A multilayer
+ * 2's step control, whose error test still decides acceptance).  A multilayer
  * perceptron 8 -> 64 -> 64 -> 2 with ReLU hidden layers maps eight features
  * of the step to (m, log10 h).  Parameters are EXPRI_MLP_PARAMS floats in the
  * order W1 (64 x 8, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64),
