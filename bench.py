@@ -233,6 +233,41 @@ def grid_measurement(k_steps, log):
                                   "unit": "TFLOP/s", "frac": fa["flops"] / refac_s / 1e12 / 78.6}}
 
 
+def grid_to_T(ctrl, log, t_end=0.1e-9):
+    """The power grid (config 3, from its DC point) up to t_end under the
+    paper's step control and under the learned controller (the network
+    trained on chain traces): time to solution by HIP events, accepted steps,
+    rejections, Arnoldi iterations, and the largest difference of the two
+    final states."""
+    import numpy as np
+    import netgen
+    import paper_1511_04515_amd as E
+    net = netgen.config(3, T=t_end)
+    out, finals = {}, {}
+    for mode in ("plain", "learned"):
+        log(f"grid to {1e9 * t_end:.2f} ns ({mode}) ...")
+        s = E.Solver(net, probes=[np.zeros(0, np.int32)])
+        x = s.zeros()
+        s.dc(x)
+        if mode == "learned":
+            s.load_controller(*ctrl)
+        try:
+            info = s.run(x)[0]
+        except E.ExpriError:
+            info = s.run_info(0)
+        sec, _ = s.kernel_time()
+        finals[mode] = x[0].cpu().numpy()
+        s.close()
+        out[mode] = {"seconds": sec, "accepted_steps": info["steps"], "rejected_trials": info["rejects"],
+                     "arnoldi_iterations": info["arnoldi"], "status": info["status"]}
+        log(f"grid to T ({mode}): {sec:.2f} s, {info['steps']} steps, {info['rejects']} rejections, "
+            f"{info['arnoldi']} Arnoldi")
+    out["t_end"] = t_end
+    out["learned_vs_plain_time_to_solution"] = out["plain"]["seconds"] / out["learned"]["seconds"]
+    out["final_state_max_abs_diff_V"] = float(np.max(np.abs(finals["learned"] - finals["plain"])))
+    return out
+
+
 def controller_training_set():
     """Circuits for the learned controller's training traces, disjoint from
     every benchmarked circuit (seeds 7000+): 16 variants of a 100-stage chain
@@ -290,6 +325,9 @@ def main():
     ap.add_argument("--grid-steps", type=int, default=20,
                     help="adaptive steps of the single 528,288-node power grid (config 3) to time; 0 = skip")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-control run of the same batch")
+    ap.add_argument("--grid-to-T", action="store_true",
+                    help="also run the power grid's first 0.1 ns under the paper's control and under the "
+                         "learned controller (with the grid workload, or after the batch)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only copy one device buffer of this many bytes to another (twice) and exit: the "
                          "calibration of the HBM byte counters")
@@ -321,6 +359,9 @@ def main():
     if args.workload == "grid":
         # the single 528,288-node power grid alone (its own JSON line)
         g = grid_measurement(args.grid_steps or 20, log)
+        if args.grid_to_T:
+            params, norm, _ = train_controller(log)
+            g["to_T"] = grid_to_T((params, norm), log)
         print(json.dumps({"metric": "Rosenbrock-Euler steps/s (single power grid, multifrontal engine)",
                           "value": g["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
                           "steps": g["steps_timed"], "warmup": 0, "ms_per_step": g["ms_per_step_median"],
@@ -500,6 +541,8 @@ def main():
         s2.close()
     if args.workload == "batch" and args.grid_steps > 0:
         out["grid"] = grid_measurement(args.grid_steps, log)
+        if args.grid_to_T and ctrl is not None:
+            out["grid"]["to_T"] = grid_to_T(ctrl, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -130,7 +130,7 @@ typedef struct {
   /* engine: 0 = automatic (a single circuit with n > 9216 goes to the
    * multifrontal engine, everything else to the one-workgroup engine),
    * 1 = one-workgroup engine only, 2 = the multifrontal engine (one circuit;
-   * no ER-C, no learned controller, no expri_set_values / bind_workspace /
+   * no ER-C, no expri_set_values / bind_workspace /
    * run_noalloc / lu_pattern) */
   int32_t engine;
   double gamma;
@@ -488,7 +488,9 @@ void expri_mlp_destroy(expri_mlp *m);
  * learned trial's MEVP does not converge within m_max, the step restarts
  * once from the paper's own proposal (keeping the basis).  Replays
  * (expri_run_schedule, expri_step_fixed) and expri_step ignore the
- * controller.  EINVAL for a
+ * controller.  The multifrontal engine takes the same network and rules in
+ * expri_run (features reduced on the device, the network evaluated by one
+ * wave).  EINVAL for a
  * non-finite parameter, a std <= 0 or safety outside (0, 1]. */
 expri_status expri_controller_load(expri_ctx *ctx, const float *params, const float *norm, double safety);
 

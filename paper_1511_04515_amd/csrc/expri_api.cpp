@@ -832,8 +832,36 @@ expri_status expri_default_opts(expri_opts *o) {
   return EXPRI_OK;
 }
 
+namespace {
+expri_status setup_impl(expri_ctx **out, const expri_circuit *ckt, int32_t n_inst, const expri_opts *o,
+                        void *hip_stream);
+}
+
 expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_inst, const expri_opts *o,
                          void *hip_stream) {
+  expri_status s = setup_impl(out, ckt, n_inst, o, hip_stream);
+  // automatic engine choice: a single circuit that the one-workgroup engine
+  // cannot hold (rows of L or U too long for its solve passes, or too large
+  // for its LDS) goes to the multifrontal engine
+  const int engine = o ? o->engine : 0;
+  if (s == EXPRI_EINVAL && engine == 0 && n_inst == 1 && out && *out && !(*out)->grid) {
+    const std::string &msg = (*out)->err;
+    if (msg.find("longer than the triangular solve handles") != std::string::npos ||
+        msg.find("too large for the one-workgroup engine") != std::string::npos) {
+      expri_opts o2;
+      if (o) o2 = *o; else expri_default_opts(&o2);
+      o2.engine = 2;
+      expri_destroy(*out);
+      *out = nullptr;
+      s = setup_impl(out, ckt, n_inst, &o2, hip_stream);
+    }
+  }
+  return s;
+}
+
+namespace {
+expri_status setup_impl(expri_ctx **out, const expri_circuit *ckt, int32_t n_inst, const expri_opts *o,
+                        void *hip_stream) {
   if (!out) return EXPRI_EINVAL;
   *out = nullptr;
   std::unique_ptr<expri_ctx> c(new (std::nothrow) expri_ctx());
@@ -1137,6 +1165,7 @@ expri_status expri_setup(expri_ctx **out, const expri_circuit *ckt, int32_t n_in
   *out = c.release();
   return EXPRI_OK;
 }
+}  // namespace
 
 expri_status expri_set_values(expri_ctx *c, int32_t inst, const expri_circuit *ckt) {
   if (!c) return EXPRI_EINVAL;
@@ -1628,9 +1657,9 @@ int64_t expri_autotune_runs(void) {
 
 expri_status expri_controller_load(expri_ctx *c, const float *params, const float *norm, double safety) {
   if (!c) return EXPRI_EINVAL;
-  if (c->grid) return fail(c, EXPRI_EINVAL, "the learned controller is not available in the multifrontal engine");
   if (!params) {
     c->ctrl_on = false;
+    if (c->grid) c->grid->ctrl_w = nullptr;
     return EXPRI_OK;
   }
   if (!norm || !(safety > 0.0 && safety <= 1.0)) return fail(c, EXPRI_EINVAL, "controller: norm missing or safety not in (0, 1]");
@@ -1651,6 +1680,11 @@ expri_status expri_controller_load(expri_ctx *c, const float *params, const floa
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->ctrl_on = true;
   c->ctrl_safety = safety;
+  if (c->grid) {
+    c->grid->ctrl_w = c->d_ctrl_w;
+    c->grid->ctrl_norm = c->d_ctrl_norm;
+    c->grid->ctrl_safety = safety;
+  }
   return EXPRI_OK;
 }
 

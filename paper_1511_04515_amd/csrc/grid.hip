@@ -27,6 +27,7 @@
 
 #include "devcommon.hpp"
 #include "layout.hpp"
+#include "mlp.hpp"
 #include "mosfet.hpp"
 
 namespace expri {
@@ -947,6 +948,40 @@ __global__ void k_g_dF(int n, const int *node_ptr, const int *node_code, const i
   }
 }
 
+// F_k(x_k) at every node: J_dev(x_k) x_k - I_dev(x_k), the part of the
+// device currents that the linearisation at x_k leaves (a step feature of the
+// learned controller)
+__global__ void k_g_fk(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,
+                       const double *devI, const double *x, double *out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int c = node_ptr[i]; c < node_ptr[i + 1]; ++c) {
+      const int code = node_code[c], k = code >> 1;
+      double lin = 0.0;
+      for (int v = 0; v < 3; ++v) {
+        const int nd = dev_node[3 * k + v];
+        if (nd >= 0) lin += devD[3 * k + v] * x[nd];
+      }
+      const double term = lin - devI[k];
+      acc += (code & 1) ? -term : term;
+    }
+    out[i] = acc;
+  }
+}
+
+// The learned step controller on one feature vector (one wave): the
+// bfloat16 network of the transient kernel, out = (m, log10 h)
+__global__ void __launch_bounds__(64) k_g_ctrl(const uint16_t *w, const float *norm, const float *feat, float *out) {
+  float f[kMlpIn], o[kMlpOut];
+#pragma unroll
+  for (int i = 0; i < kMlpIn; ++i) f[i] = feat[i];
+  mlp_infer_wave(w, norm, f, o);
+  if (threadIdx.x == 0) {
+    out[0] = o[0];
+    out[1] = o[1];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1129,6 +1164,16 @@ hipError_t g_axpy(int n, double a, const double *x, double *y, hipStream_t s) {
 }
 hipError_t g_sub(int n, const double *a, const double *b, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_g_sub, dim3(blocks_for(n)), dim3(kTB), 0, s, n, a, b, out);
+  return hipGetLastError();
+}
+hipError_t g_fk(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,
+                const double *devI, const double *x, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_fk, dim3(blocks_for(n)), dim3(kTB), 0, s, n, node_ptr, node_code, dev_node, devD, devI, x,
+                     out);
+  return hipGetLastError();
+}
+hipError_t g_ctrl(const uint16_t *w, const float *norm, const float *feat, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_g_ctrl, dim3(1), dim3(64), 0, s, w, norm, feat, out);
   return hipGetLastError();
 }
 hipError_t g_dF(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,

@@ -59,6 +59,9 @@ hipError_t g_sub(int n, const double *a, const double *b, double *out, hipStream
 hipError_t g_dF(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,
                 const double *devI0, const double *devI1, const double *xk, const double *x1, double *out,
                 hipStream_t s);
+hipError_t g_fk(int n, const int *node_ptr, const int *node_code, const int *dev_node, const double *devD,
+                const double *devI, const double *x, double *out, hipStream_t s);
+hipError_t g_ctrl(const uint16_t *w, const float *norm, const float *feat, float *out, hipStream_t s);
 hipError_t launch_hess_phi1(const double *H, int m, double h, const double *beta, int want2, double *mat,
                             double *out, hipStream_t s);
 
@@ -418,7 +421,9 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
   d_scm = d_out + kSc;
   d_sce = d_oute + kSc;
   d_red = dalloc<double>(8);
-  if (!d_F || !d_upd || !d_rowmax || !d_bad || !d_xk || !d_x1 || !d_w || !d_p || !d_z || !d_r || !d_bs || !d_e ||
+  d_feat = dalloc<float>(kFeat);
+  d_cout = dalloc<float>(2);
+  if (!d_feat || !d_cout || !d_F || !d_upd || !d_rowmax || !d_bad || !d_xk || !d_x1 || !d_w || !d_p || !d_z || !d_r || !d_bs || !d_e ||
       !d_y || !d_u || !d_sl || !d_devI0 || !d_devI1 || !d_devD || !d_devD1 || !d_V || !d_Ve || !d_H || !d_He || !d_mat ||
       !d_part || !d_h1 || !d_h2 || !d_out || !d_oute || !d_red)
     return fail(kSENOMEM, "device allocation failed (workspace)");
@@ -626,6 +631,11 @@ int GridEngine::run(double *x_caller, double t0, const double *grid, int32_t n_g
   GCHK(hipEventRecord(e0, stream));
   GCHK(g_gather(n, d_perm, x_caller, d_xk, stream));
   double t = t0, h_prop = std::min(h0, h_max);
+  // the learned controller proposes (m, h) from features of the step; the
+  // error test still judges every trial (as in the transient kernel)
+  const bool learned = ctrl_w != nullptr && !replay;
+  double h_prev = h_prop, rho_prev = 0.0, err_prev = 0.0;
+  int m_prev = 0, rej_prev = 0, m_err_prev = 0;
   size_t bp_idx = 0;
   while (bp_idx + 1 < bps.size() && bps[bp_idx] <= t0) ++bp_idx;
   bool lu_valid = false;
@@ -656,6 +666,57 @@ int GridEngine::run(double *x_caller, double t0, const double *grid, int32_t n_g
     } else {
       GCHK(g_stamp(fs.n_dev, d_dev_node, d_par, d_xk, vdd, d_devI0, d_devD, stream));
     }
+    // step features (recorded in every mode, the learned controller's input):
+    // log ||r_k||, m_{k-1} / 60, log h_{k-1}, log rho_{k-1}, log(1 + max |du/dt|
+    // 1 ns) at the middle of the segment, log ||F_k(x_k)||, log(e_{k-1} / E_rr),
+    // rejections of step k - 1
+    double feat[kFeat] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int m_first = 1;
+    if (!replay) {
+      const double ts = t + 0.5 * (learned ? bps[bp_idx] - t : h_try);
+      GCHK(g_sources(fs.n_src, d_src_ptr, d_src_t, d_src_v, t, ts, d_u, d_sl, stream));
+      GCHK(g_rhs(n, d_g_rowptr, d_g_col, d_g_val, d_b_rowptr, d_b_col, d_b_val, d_node_ptr, d_node_code, d_devI0,
+                 d_xk, d_u, d_sl, d_w, d_p, stream));
+      GCHK(g_absmax(n, d_w, d_part, d_red, stream));
+      GCHK(g_fk(n, d_node_ptr, d_node_code, d_dev_node, d_devD, d_devI0, d_xk, d_e, stream));
+      GCHK(g_absmax(n, d_e, d_part, d_red + 1, stream));
+      if (fs.n_src > 0) GCHK(g_absmax(fs.n_src, d_sl, d_part, d_red + 2, stream));
+      else GCHK(g_fill(d_red + 2, 1, 0.0, stream));
+      double nr[3];
+      GRET(read_scalars(d_red, nr, 3));
+      feat[0] = std::log10(std::max(nr[0], 1e-30));
+      feat[1] = m_prev / 60.0;
+      feat[2] = std::log10(h_prev);
+      feat[3] = std::log10(std::max(rho_prev, 1e-30));
+      feat[4] = std::log10(1.0 + nr[2] * 1e-9);
+      feat[5] = std::log10(std::max(nr[1], 1e-30));
+      feat[6] = std::log10(std::max(err_prev / E_rr, 1e-30));
+      feat[7] = rej_prev;
+      if (learned) {
+        float ff[kFeat], out[2];
+        for (int i = 0; i < kFeat; ++i) ff[i] = (float)feat[i];
+        GCHK(hipMemcpyAsync(d_feat, ff, sizeof(ff), hipMemcpyHostToDevice, stream));
+        GCHK(g_ctrl(ctrl_w, ctrl_norm, d_feat, d_cout, stream));
+        GCHK(hipMemcpyAsync(out, d_cout, sizeof(out), hipMemcpyDeviceToHost, stream));
+        GCHK(hipStreamSynchronize(stream));
+        // the first residual test at m - 1; the step within alpha .. beta of
+        // the previous accepted one, stretched by up to 25 % to land on a
+        // source corner or split into halves before one
+        m_first = (int)std::min(std::max(std::rint((double)out[0]) - 1.0, 1.0), (double)o.m_max);
+        double hl = ctrl_safety * std::pow(10.0, (double)out[1]);
+        if (!(hl == hl)) hl = h_prev;
+        hl = std::min(std::max(hl, o.alpha * h_prev), o.beta * h_prev);
+        t_land = bps[bp_idx];
+        h_try = h_unc = std::min(hl, h_max);
+        land = false;
+        if (t + h_try * 1.25 >= t_land) {
+          h_try = t_land - t;
+          land = true;
+        } else if (t + 2.0 * h_try > t_land) {
+          h_try = 0.5 * (t_land - t);
+        }
+      }
+    }
     // w = G^{-1} r, p = G^{-1} B s, z = G^{-1} C p, v = w - z
     GCHK(g_sources(fs.n_src, d_src_ptr, d_src_t, d_src_v, t, t + 0.5 * h_try, d_u, d_sl, stream));
     GCHK(g_rhs(n, d_g_rowptr, d_g_col, d_g_val, d_b_rowptr, d_b_col, d_b_val, d_node_ptr, d_node_code, d_devI0, d_xk,
@@ -668,9 +729,31 @@ int GridEngine::run(double *x_caller, double t0, const double *grid, int32_t n_g
     if ((status = basis_start(Bm, d_r)) != kSOK) break;
     double h = h_try, rho = 0.0, errv = 0.0;
     int rej = 0, m_err = 0;
+    bool fell_back = false;
+    // a learned proposal whose MEVP misses eps_K at m_max restarts once from
+    // the paper's proposal (the basis is kept)
+    auto fall_back = [&]() {
+      fell_back = true;
+      double hp = std::min(h_prop, h_max);
+      h_unc = hp;
+      t_land = bps[bp_idx];
+      land = false;
+      if (t + hp * (1.0 + 1e-3) >= t_land) {
+        hp = t_land - t;
+        land = true;
+      }
+      h = h_try = hp;
+      rej = 0;
+      status = kSOK;
+    };
     for (;;) {
       ++trials;
-      if ((status = converge(Bm, h, eps_K, &rho, 0, 1)) != kSOK) break;
+      status = converge(Bm, h, eps_K, &rho, 0, rej == 0 ? m_first : 1);
+      if (status == kSEKRYLOV && learned && !fell_back) {
+        fall_back();
+        continue;
+      }
+      if (status != kSOK) break;
       GCHK(g_combine(n, d_xk, d_p, h, Bm.V, ldv, Bm.m, Bm.sc, Bm.out, d_x1, stream));
       comb_terms += Bm.m;
       errv = 0.0;
@@ -683,7 +766,12 @@ int GridEngine::run(double *x_caller, double t0, const double *grid, int32_t n_g
         Basis Be{d_Ve, d_He, d_sce, d_oute, 0, false};
         double rho_e = 0.0;
         if ((status = basis_start(Be, d_e)) != kSOK) break;
-        if ((status = converge(Be, h, eps_K, &rho_e, 0, 1)) != kSOK) break;
+        status = converge(Be, h, eps_K, &rho_e, 0, learned ? std::max(1, m_err_prev - 2) : 1);
+        if (status == kSEKRYLOV && learned && !fell_back) {
+          fall_back();
+          continue;
+        }
+        if (status != kSOK) break;
         m_err = Be.m;
         GCHK(g_combine(n, nullptr, nullptr, 0.0, Be.V, ldv, Be.m, Be.sc, Be.out, d_e, stream));
         comb_terms += Be.m;
@@ -714,7 +802,14 @@ int GridEngine::run(double *x_caller, double t0, const double *grid, int32_t n_g
     trace.resize(base + rec, 0.0);
     double *r = trace.data() + base;
     r[0] = t_new; r[1] = h; r[2] = h_unc; r[3] = Bm.m; r[4] = m_err; r[5] = rej; r[6] = errv; r[7] = rho;
+    for (int i = 0; i < kFeat; ++i) r[8 + i] = feat[i];
     for (int q = 0; q < n_probe; ++q) r[kRecFixed + q] = probes[q];
+    h_prev = (land && rej == 0) ? h_unc : h;
+    rho_prev = rho;
+    err_prev = errv;
+    m_prev = Bm.m;
+    rej_prev = rej;
+    m_err_prev = m_err;
     if (last) *last = GridStepRec{t_new, h, h_unc, errv, rho, Bm.m, m_err, rej};
     const double grow = rej < o.grow_if_rejects_lt ? o.beta : 1.0;
     h_prop = std::min(h_max, grow * (rej == 0 ? h_prop : h));

@@ -95,6 +95,12 @@ struct GridEngine {
   double *d_out = nullptr;                    // hess_phi1 output: d, d2, rho
   double *d_oute = nullptr;
   double *d_red = nullptr;                    // reduction results
+  // the learned step controller (bfloat16 network and standardisation owned
+  // by the context; null: the paper's alpha / beta control)
+  const uint16_t *ctrl_w = nullptr;
+  const float *ctrl_norm = nullptr;
+  double ctrl_safety = 1.0;
+  float *d_feat = nullptr, *d_cout = nullptr;  // one feature vector, (m, log10 h)
   int64_t ldv = 0;
   bool factored = false;
 

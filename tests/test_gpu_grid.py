@@ -183,3 +183,74 @@ def test_full_power_grid_factor_solve_and_replay():
     assert info[0]["status"] == 0 and np.array_equal(tr["t"], g["t"])
     assert berr <= 1e-12 and err <= 1e-6 and fin <= 1e-6
     s.close()
+
+
+def test_learned_controller_in_the_multifrontal_engine_on_grid96():
+    # the learned controller (trained on chain traces, as the benchmark's) in
+    # the multifrontal engine over the first 0.3 ns of the 2 x 96 x 96 grid
+    # (about 60 steps of the paper's control reach 0.14 ns, after which its
+    # steps settle near 0.3 ps): the run reaches T, every accepted step meets
+    # E_rr (the error test still judges every trial), the trace holds finite
+    # features, and the final state stays within 100 E_rr of the paper's
+    # control
+    import paper_1511_04515_amd as E
+    from paper_1511_04515_amd import control
+    base = netgen.inverter_chain(seed=7000, n_stages=80).meta["values"]
+    nets = [netgen.inverter_chain(seed=7000, n_stages=80, base=base, variation=dict(seed=7100 + i))
+            for i in range(8)]
+    nets += [netgen.inverter_chain(seed=7300 + j, n_stages=L) for j, L in enumerate((60, 110, 150, 190))]
+    s = E.Solver(nets, probes=[np.zeros(0, np.int32)] * len(nets), trace_cap=8192)
+    x = s.zeros()
+    s.dc(x)
+    s.run(x, max_steps_per_launch=8192)
+    X, T = control.samples_from_traces([s.trace(i) for i in range(len(nets))])
+    s.close()
+    params, norm, _ = control.train(X, T, epochs=40, batch=4096, lr=1e-3)
+    print(f"controller trained on {len(X)} samples", flush=True)
+
+    net = netgen.power_grid(side=96, n_drivers=60, T=0.3e-9)
+
+    def run(ctrl):
+        g = E.Solver(net)
+        assert g.classes()[0][0]["workgroups"] == 0  # the multifrontal engine
+        xg = g.zeros()
+        g.dc(xg)
+        if ctrl is not None:
+            g.load_controller(*ctrl)
+        info = g.run(xg)[0]
+        tr = g.trace(0)
+        sec, _ = g.kernel_time()
+        out = xg[0].cpu().numpy()
+        g.close()
+        print(f"  {'learned' if ctrl is not None else 'paper'}: {sec:.2f} s, {info['steps']} steps", flush=True)
+        return info, tr, out, sec
+
+    pi, ptr, px, psec = run(None)
+    li, ltr, lx, lsec = run((params, norm))
+    gap = np.max(np.abs(lx - px))
+    print(f"grid96 to 0.3 ns: paper's control {psec:.2f} s, {pi['steps']} steps, {pi['rejects']} rejections, "
+          f"{pi['arnoldi']} Arnoldi; learned {lsec:.2f} s, {li['steps']} steps, {li['rejects']} rejections, "
+          f"{li['arnoldi']} Arnoldi; final state gap {gap:.2e} V", flush=True)
+    assert pi["status"] == 0 and li["status"] == 0
+    assert ptr["t"][-1] == net.T and ltr["t"][-1] == net.T
+    assert np.all(ltr["err"] <= 1e-6) and np.all(ptr["err"] <= 1e-6)
+    assert np.isfinite(ltr["feat"]).all() and np.isfinite(ptr["feat"]).all()
+    assert gap <= 100 * 1e-6
+
+
+def test_automatic_engine_choice_falls_back_to_the_multifrontal_engine():
+    # a 2 x 64 x 64 grid (8,252 unknowns) is under the one-workgroup engine's
+    # size bound, but rows of its L and U are longer than that engine's solve
+    # passes hold: the automatic choice sets it up on the multifrontal engine
+    import paper_1511_04515_amd as E
+    net = netgen.power_grid(seed=9003, side=64, T=0.05e-9, stim_seed=9004, n_drivers=30)
+    assert net.n <= 9216
+    s = E.Solver(net)
+    assert s.classes()[0][0]["workgroups"] == 0
+    x = s.zeros()
+    s.dc(x)
+    info = s.run(x)[0]
+    assert info["status"] == 0 and s.trace(0)["t"][-1] == net.T
+    s.close()
+    with pytest.raises(E.ExpriError):
+        E.Solver(net, engine=1)
