@@ -42,20 +42,20 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {"sources": ("paper_1511_04515_amd/csrc/engine.hip", "paper_1511_04515_amd/csrc/layout.hpp",
                            "paper_1511_04515_amd/csrc/mlp.hpp", "paper_1511_04515_amd/csrc/devcommon.hpp",
                            "paper_1511_04515_amd/csrc/mosfet.hpp"),
-               "sha256_16": "783f2eb571a083d8", "workload": "batch", "controller": "learned",
+               "sha256_16": "783f2eb571a083d8", "workload": "batch", "controller": "learned", "safety": 0.85,
                "kernel": "k_run<512, 9>",
-               "fetch_kib": 12462941406.8, "fetch_factor": 2.0,
-               "write_kib": 2402835445.7, "write_factor": 1.0}
+               "fetch_kib": 12498834521.3, "fetch_factor": 2.0,
+               "write_kib": 2322903977.8, "write_factor": 1.0}
 
 
-def pmc_traffic_bytes(workload, learned, nlaunch, kernel):
+def pmc_traffic_bytes(workload, learned, safety, nlaunch, kernel):
     import hashlib
     h = hashlib.sha256()
     for f in PMC_TRAFFIC["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if (h.hexdigest()[:16] != PMC_TRAFFIC["sha256_16"] or workload != PMC_TRAFFIC["workload"]
-            or not learned or nlaunch != 1 or kernel != PMC_TRAFFIC["kernel"]):
+            or not learned or safety != PMC_TRAFFIC["safety"] or nlaunch != 1 or kernel != PMC_TRAFFIC["kernel"]):
         return None
     return 1024.0 * (PMC_TRAFFIC["fetch_kib"] * PMC_TRAFFIC["fetch_factor"]
                      + PMC_TRAFFIC["write_kib"] * PMC_TRAFFIC["write_factor"])
@@ -314,7 +314,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--controller", default="learned", choices=("learned", "plain"))
-    ap.add_argument("--safety", type=float, default=1.0)
+    ap.add_argument("--safety", type=float, default=0.85,
+                    help="factor on the learned controller's step (0.85: fastest on its training circuits)")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="measure each pattern's launch configuration at set-up (untimed) instead of the rule")
@@ -449,7 +450,7 @@ def main():
     per_launch_s = class_s[q] / max(nlaunch, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9
     kname = f"k_run<{classes[q]['block_size']}, {classes[q]['max_rows']}>"
-    traffic = pmc_traffic_bytes(args.workload, ctrl is not None, nlaunch, kname)
+    traffic = pmc_traffic_bytes(args.workload, ctrl is not None, args.safety, nlaunch, kname)
     # the SpTRSV/SpMV phase (Arnoldi C SpMV + L/U solves) from the in-kernel
     # phase timers: its time summed over instances, spread over the resident
     # workgroups

@@ -480,9 +480,10 @@ class Solver:
         self._check(self.lib.expri_lu_values(self.ctx, inst, _ptr(out, C.c_double)))
         return out
 
-    def load_controller(self, params=None, norm=None, safety: float = 1.0):
+    def load_controller(self, params=None, norm=None, safety: float = 0.85):
         """Use a trained network as the step controller of run() (None: the
-        paper's alpha/beta rule)."""
+        paper's alpha/beta rule).  The default safety factor was chosen on
+        the controller's own training circuits (fastest of 0.8 to 1.0)."""
         if params is None:
             self._check(self.lib.expri_controller_load(self.ctx, None, None, 1.0))
             return

@@ -74,7 +74,7 @@ def test_learned_controller_beats_plain_control_on_a_fresh_circuit():
     assert g["t_final"] == fresh.T
     ref = g["x_final"]
     plain, t_plain, x_plain, _ = _run(E, fresh)
-    learned, t_learned, x_learned, tr = _run(E, fresh, (params, norm), safety=1.0)
+    learned, t_learned, x_learned, tr = _run(E, fresh, (params, norm), safety=0.85)
     e_plain = np.abs(x_plain - ref).max()
     e_learned = np.abs(x_learned - ref).max()
     print(f"plain: {t_plain:.2f} s, {plain['steps']} steps, {plain['rejects']} rejections, "

@@ -100,7 +100,7 @@ def test_full_batch_in_the_benchmark_launch_configuration():
     X, T = control.samples_from_traces([st.trace(i) for i in range(len(tnets))])
     st.close()
     params, norm, _ = control.train(X, T, epochs=40, batch=4096, lr=1e-3)
-    s.load_controller(params, norm, safety=1.0)
+    s.load_controller(params, norm, safety=0.85)
     xl = [x.clone() for x in x0]
     info_l = s.run(xl, max_steps_per_launch=8192)
     E_rr = s.opts.E_rr
@@ -113,7 +113,7 @@ def test_full_batch_in_the_benchmark_launch_configuration():
           f"{sum(r['steps'] for r in info)}, {sum(r['rejects'] for r in info)})", flush=True)
     for i in picks:
         s1 = E.Solver(nets[i], trace_cap=8192)
-        s1.load_controller(params, norm, safety=1.0)
+        s1.load_controller(params, norm, safety=0.85)
         x1 = [x0[i].clone()]
         s1.run(x1, max_steps_per_launch=8192)
         a, b = s.trace(i), s1.trace(0)
