@@ -429,27 +429,39 @@ __global__ void __launch_bounds__(256) k_g_update(const int *items, int k0, cons
 // once (NR = 1 or 2): vector r of x starts at x + r ldx and its update
 // vectors at upd + r ldu.  The factor entries are loaded once for all NR.
 
+// Row t of the kNB-wide diagonal block of a pivot block that starts at b0
+// (bw rows), in registers; indices are clamped into the block so every load
+// is in bounds.  The triangular solves below load the next block this way
+// right after solving the current one, so its latency overlaps the update.
+__device__ __forceinline__ void tri_block_row(double (&col)[kNB], const double *A, int f, int b0, int bw, int t) {
+  const int rt = b0 + min(t, bw - 1);
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
+}
+
 // Forward solve of one tree height (L y = b, unit lower), part 1, one
-// workgroup per front: v = [x(cols s); 0] + the children's update vectors at
-// their relative indices; the unit-lower pivot block L11 is solved in 32-wide
-// blocks (a wave solves the block triangle, the workgroup updates the pivot
-// rows below it); y goes to x, the rest of v (the children's contributions to
-// the update vector) to upd.  Part 2 (k_g_fwd_gemv) subtracts L21 y.
-// Dynamic LDS: NR f doubles.
-template <int NR>
-__global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
-                                                   const int64_t *f_off, const int *ch_ptr, const int *ch,
-                                                   const int *r_ptr, const int *rel, const int *u_off,
-                                                   const double *F, double *x, int64_t ldx, double *upd,
-                                                   int64_t ldu) {
+// workgroup of BS threads per front: v = [x(cols s); 0] + the children's
+// update vectors at their relative indices; the unit-lower pivot block L11 is
+// solved in 32-wide blocks (a wave solves the block triangle, the workgroup
+// updates the pivot rows below it); y goes to x, the rest of v (the
+// children's contributions to the update vector) to upd.  Part 2
+// (k_g_fwd_gemv) subtracts L21 y.  Dynamic LDS: NR f doubles.
+template <int NR, int BS>
+__global__ void __launch_bounds__(BS) k_g_fwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
+                                                  const int64_t *f_off, const int *ch_ptr, const int *ch,
+                                                  const int *r_ptr, const int *rel, const int *u_off,
+                                                  const double *F, double *x, int64_t ldx, double *upd,
+                                                  int64_t ldu) {
   extern __shared__ double v[];
   const int s = fronts[blockIdx.x];
   const int f = fsz[s], p = nc[s], b = c0[s];
   const double *A = F + f_off[s];
   const int t = threadIdx.x;
+  double col[kNB];  // wave 0: row t of the current diagonal block
+  if (t < 64 && p > 0) tri_block_row(col, A, f, 0, min(kNB, p), t);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    for (int i = t; i < f; i += 256) v[r * f + i] = i < p ? x[r * ldx + b + i] : 0.0;
+    for (int i = t; i < f; i += BS) v[r * f + i] = i < p ? x[r * ldx + b + i] : 0.0;
   __syncthreads();
   for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
     const int c = ch[q], rc = fsz[c] - nc[c];
@@ -457,19 +469,22 @@ __global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const double *uc = upd + r * ldu + u_off[c];
-      for (int a = t; a < rc; a += 256) v[r * f + rl[a]] += uc[a];
+      for (int a = t; a < rc; a += BS) v[r * f + rl[a]] += uc[a];
     }
     __syncthreads();
   }
   for (int b0 = 0; b0 < p; b0 += kNB) {
     const int bw = min(kNB, p - b0);
-    if (t < 64) {
-      // lane t holds row t of the block (indices clamped into the block, so
-      // every load is in bounds and issued before the sequential part)
-      double col[kNB];
-      const int rt = b0 + min(t, bw - 1);
+    // this thread's first row below the block: its kNB entries are loaded
+    // before the block triangle is solved (a row past p loads row p - 1)
+    const int i0 = b0 + bw + t;
+    double pa[kNB];
+    {
+      const int ri = min(i0, p - 1);
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
+      for (int j = 0; j < kNB; ++j) pa[j] = A[ri + (int64_t)(b0 + min(j, bw - 1)) * f];
+    }
+    if (t < 64) {
       double vl[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) vl[r] = t < bw ? v[r * f + b0 + t] : 0.0;
@@ -487,9 +502,23 @@ __global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int 
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r * f + b0 + t] = vl[r];
       }
+      const int b1 = b0 + kNB;
+      if (b1 < p) tri_block_row(col, A, f, b1, min(kNB, p - b1), t);
     }
     __syncthreads();
-    for (int i = b0 + bw + t; i < p; i += 256) {
+    if (i0 < p) {
+      double acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = v[r * f + i0];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] -= pa[j] * (j < bw ? v[r * f + b0 + j] : 0.0);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[r * f + i0] = acc[r];
+    }
+    for (int i = i0 + BS; i < p; i += BS) {
       double acc[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = v[r * f + i];
@@ -506,7 +535,7 @@ __global__ void __launch_bounds__(256) k_g_fwd_tri(const int *fronts, const int 
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    for (int i = t; i < f; i += 256) {
+    for (int i = t; i < f; i += BS) {
       if (i < p) x[r * ldx + b + i] = v[r * f + i];
       else upd[r * ldu + u_off[s] + i - p] = v[r * f + i];
     }
@@ -686,28 +715,36 @@ __global__ void __launch_bounds__(256) k_g_bwd_gemv(const int *items, const int 
   }
 }
 
-// Backward solve, part 2, one workgroup per front: the upper pivot block U11
-// in 32-wide blocks from the last, each block updating the pivot rows above.
+// Backward solve, part 2, one workgroup of BS threads per front: the upper
+// pivot block U11 in 32-wide blocks from the last, each block updating the
+// pivot rows above.
 // Dynamic LDS: NR nc doubles.
-template <int NR>
-__global__ void __launch_bounds__(256) k_g_bwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
-                                                   const int64_t *f_off, const double *F, double *x, int64_t ldx) {
+template <int NR, int BS>
+__global__ void __launch_bounds__(BS) k_g_bwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
+                                                  const int64_t *f_off, const double *F, double *x, int64_t ldx) {
   extern __shared__ double v[];
   const int s = fronts[blockIdx.x];
   const int f = fsz[s], p = nc[s], b = c0[s];
   const double *A = F + f_off[s];
   const int t = threadIdx.x;
+  const int last = p > 0 ? ((p - 1) / kNB) * kNB : 0;
+  double col[kNB];  // wave 0: row t of the current diagonal block of U
+  if (t < 64 && p > 0) tri_block_row(col, A, f, last, min(kNB, p - last), t);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    for (int i = t; i < p; i += 256) v[r * p + i] = x[r * ldx + b + i];
+    for (int i = t; i < p; i += BS) v[r * p + i] = x[r * ldx + b + i];
   __syncthreads();
-  for (int b0 = ((p - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
+  for (int b0 = p > 0 ? last : -1; b0 >= 0; b0 -= kNB) {
     const int bw = min(kNB, p - b0);
-    if (t < 64) {
-      double col[kNB];  // row t of the block of U (clamped, as in the forward solve)
-      const int rt = b0 + min(t, bw - 1);
+    // this thread's first row above the block: its kNB entries are loaded
+    // before the block triangle is solved (with no row above, row 0)
+    double pa[kNB];
+    {
+      const int ri = min(t, max(b0 - 1, 0));
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) col[j] = A[rt + (int64_t)(b0 + min(j, bw - 1)) * f];
+      for (int j = 0; j < kNB; ++j) pa[j] = A[ri + (int64_t)(b0 + min(j, bw - 1)) * f];
+    }
+    if (t < 64) {
       double vl[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) vl[r] = t < bw ? v[r * p + b0 + t] : 0.0;
@@ -726,9 +763,22 @@ __global__ void __launch_bounds__(256) k_g_bwd_tri(const int *fronts, const int 
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r * p + b0 + t] = vl[r];
       }
+      if (b0 > 0) tri_block_row(col, A, f, b0 - kNB, kNB, t);
     }
     __syncthreads();
-    for (int i = t; i < b0; i += 256) {
+    if (t < b0) {
+      double acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = v[r * p + t];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] -= pa[j] * (j < bw ? v[r * p + b0 + j] : 0.0);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[r * p + t] = acc[r];
+    }
+    for (int i = t + BS; i < b0; i += BS) {
       double acc[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = v[r * p + i];
@@ -745,7 +795,7 @@ __global__ void __launch_bounds__(256) k_g_bwd_tri(const int *fronts, const int 
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    for (int i = t; i < p; i += 256) x[r * ldx + b + i] = v[r * p + i];
+    for (int i = t; i < p; i += BS) x[r * ldx + b + i] = v[r * p + i];
 }
 
 // PWL sources: u(t) and the slope on the piece holding tm
@@ -1066,14 +1116,21 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
-                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, hipStream_t s) {
+                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, int tri_bs, hipStream_t s) {
+#define G_FWD_TRI(NR, BS)                                                                                           \
+  hipLaunchKernelGGL((k_g_fwd_tri<NR, BS>), dim3(n_big), dim3(BS), sizeof(double) * NR * (size_t)max_f, s, big, c0,  \
+                     nc, fsz, f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);
 #define G_FWD(NR)                                                                                                   \
   if (n_small > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_fwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
                        f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);                                  \
-  if (n_big > 0)                                                                                                    \
-    hipLaunchKernelGGL(k_g_fwd_tri<NR>, dim3(n_big), dim3(256), sizeof(double) * NR * (size_t)max_f, s, big, c0,    \
-                       nc, fsz, f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);                         \
+  if (n_big > 0) {                                                                                                  \
+    if (tri_bs == 512) {                                                                                            \
+      G_FWD_TRI(NR, 512)                                                                                            \
+    } else {                                                                                                        \
+      G_FWD_TRI(NR, 256)                                                                                            \
+    }                                                                                                               \
+  }                                                                                                                 \
   if (n_items > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_fwd_gemv<NR>, dim3(n_items), dim3(256), sizeof(double) * NR * (size_t)max_nc, s, items,  \
                        c0, nc, fsz, f_off, u_off, F, x, ldx, upd, ldu);
@@ -1083,11 +1140,16 @@ hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n
     G_FWD(1)
   }
 #undef G_FWD
+#undef G_FWD_TRI
   return hipGetLastError();
 }
 hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
-                 const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, hipStream_t s) {
+                 const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, int tri_bs,
+                 hipStream_t s) {
+#define G_BWD_TRI(NR, BS)                                                                                           \
+  hipLaunchKernelGGL((k_g_bwd_tri<NR, BS>), dim3(n_big), dim3(BS), sizeof(double) * NR * (size_t)max_nc, s, big, c0, \
+                     nc, fsz, f_off, F, x, ldx);
 #define G_BWD(NR)                                                                                                   \
   if (n_small > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_bwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
@@ -1095,15 +1157,20 @@ hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n
   if (n_items > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_bwd_gemv<NR>, dim3(n_items), dim3(256), sizeof(double) * NR * (size_t)max_f, s, items,   \
                        c0, nc, fsz, f_off, r_ptr, r_idx, F, x, ldx);                                                \
-  if (n_big > 0)                                                                                                    \
-    hipLaunchKernelGGL(k_g_bwd_tri<NR>, dim3(n_big), dim3(256), sizeof(double) * NR * (size_t)max_nc, s, big, c0,   \
-                       nc, fsz, f_off, F, x, ldx);
+  if (n_big > 0) {                                                                                                  \
+    if (tri_bs == 512) {                                                                                            \
+      G_BWD_TRI(NR, 512)                                                                                            \
+    } else {                                                                                                        \
+      G_BWD_TRI(NR, 256)                                                                                            \
+    }                                                                                                               \
+  }
   if (nr == 2) {
     G_BWD(2)
   } else {
     G_BWD(1)
   }
 #undef G_BWD
+#undef G_BWD_TRI
   return hipGetLastError();
 }
 hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,

@@ -34,10 +34,11 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
-                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, hipStream_t s);
+                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, int tri_bs, hipStream_t s);
 hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
-                 const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, hipStream_t s);
+                 const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, int tri_bs,
+                 hipStream_t s);
 hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,
                      double *u, double *slope, hipStream_t s);
 hipError_t g_rhs(int n, const int *g_rowptr, const int *g_col, const double *g_val, const int *b_rowptr,
@@ -277,7 +278,10 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       fix.push_back({at_s, nullptr});
       const size_t at_g = pool.size();
       for (int q = L.first; q < L.first + L.count; ++q)
-        if (fs.fsz[fs.lev_front[q]] > 64) pool.push_back(fs.lev_front[q]);
+        if (fs.fsz[fs.lev_front[q]] > 64) {
+          pool.push_back(fs.lev_front[q]);
+          L.big_maxp = std::max(L.big_maxp, fs.nc[fs.lev_front[q]]);
+        }
       L.n_big = (int32_t)(pool.size() - at_g);
       fix.push_back({at_g, nullptr});
     }
@@ -480,11 +484,12 @@ int GridEngine::solve_internal(double *b, int nr) {
   }
   for (const Level &L : levels)
     GCHK(g_fwd(L.n_small, L.small, L.n_big, L.big, L.n_fwd, L.fwd, fs.max_front, fs.max_nc, d_c0, d_nc, d_fsz,
-               d_f_off, d_ch_ptr, d_ch, d_r_ptr, d_rel, d_u_off, d_F, b, nr, fs.n, d_upd, fs.upd_doubles, stream));
+               d_f_off, d_ch_ptr, d_ch, d_r_ptr, d_rel, d_u_off, d_F, b, nr, fs.n, d_upd, fs.upd_doubles,
+               L.tri_bs(), stream));
   for (int h = (int)levels.size() - 1; h >= 0; --h) {
     const Level &L = levels[h];
     GCHK(g_bwd(L.n_small, L.small, L.n_big, L.big, L.n_bwd, L.bwd, fs.max_front, fs.max_nc, d_c0, d_nc, d_fsz,
-               d_f_off, d_r_ptr, d_r_idx, d_F, b, nr, fs.n, stream));
+               d_f_off, d_r_ptr, d_r_idx, d_F, b, nr, fs.n, L.tri_bs(), stream));
   }
   return kSOK;
 }
