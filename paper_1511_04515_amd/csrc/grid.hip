@@ -1113,6 +1113,9 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
                      bad);
   return hipGetLastError();
 }
+// tri_bs: workgroup size of the pivot-block kernels with one right-hand side
+// (256 or 512); two right-hand sides always take 256 threads, whose register
+// budget holds both vectors' accumulators without spilling.
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
@@ -1125,7 +1128,7 @@ hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n
     hipLaunchKernelGGL(k_g_fwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
                        f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);                                  \
   if (n_big > 0) {                                                                                                  \
-    if (tri_bs == 512) {                                                                                            \
+    if (tri_bs == 512 && NR == 1) {                                                                                 \
       G_FWD_TRI(NR, 512)                                                                                            \
     } else {                                                                                                        \
       G_FWD_TRI(NR, 256)                                                                                            \
@@ -1158,7 +1161,7 @@ hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n
     hipLaunchKernelGGL(k_g_bwd_gemv<NR>, dim3(n_items), dim3(256), sizeof(double) * NR * (size_t)max_f, s, items,   \
                        c0, nc, fsz, f_off, r_ptr, r_idx, F, x, ldx);                                                \
   if (n_big > 0) {                                                                                                  \
-    if (tri_bs == 512) {                                                                                            \
+    if (tri_bs == 512 && NR == 1) {                                                                                 \
       G_BWD_TRI(NR, 512)                                                                                            \
     } else {                                                                                                        \
       G_BWD_TRI(NR, 256)                                                                                            \

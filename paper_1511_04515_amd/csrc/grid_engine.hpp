@@ -73,8 +73,9 @@ struct GridEngine {
     int32_t n_small = 0, n_big = 0;  // solve: fronts with f <= 64 (a wave each) and the rest
     int32_t *small = nullptr, *big = nullptr;
     int32_t big_maxp = 0;  // the most pivots of a front in big
-    // workgroup size of the pivot-block solves: 512 threads once a block's
-    // update rows outnumber 256 threads (the few large fronts near the root)
+    // workgroup size of the pivot-block solves with one right-hand side: 512
+    // threads once a block's update rows outnumber 256 threads (the few large
+    // fronts near the root)
     int tri_bs() const { return big_maxp > 256 + 32 ? 512 : 256; }
     int32_t n_fwd = 0, n_bwd = 0;  // solve GEMV items (front, 64-row chunk)
     int32_t *fwd = nullptr, *bwd = nullptr;
