@@ -61,6 +61,35 @@ def test_grid_engine_is_picked_and_factor_solve_meet_the_bar():
     s.close()
 
 
+def test_grid_engine_solve_with_a_root_front_over_288_pivots():
+    # a 2 x 160 x 160 grid: its root front has 319 pivots, so the top height's
+    # pivot-block solves take 512-thread workgroups and the others 256; the
+    # solve meets the backward-error bar near the DC point (at random node
+    # voltages some driver outputs have no conducting device, G_k is nearly
+    # singular and the normwise bar says little)
+    import paper_1511_04515_amd as E
+    from paper_1511_04515_amd import binding as B
+    net = netgen.power_grid(side=160, n_drivers=100)
+    a = B.frontal_analysis(net)
+    root = a["height"] == a["height"].max()
+    assert a["nc"][root].max() > 288 and (a["nc"][~root] <= 288).all()
+    s = E.Solver(net)
+    assert s.classes()[0][0]["workgroups"] == 0
+    x0 = s.zeros()
+    s.dc(x0)
+    x = x0[0].cpu().numpy() + np.random.default_rng(11).normal(0, 0.05, net.n)
+    s.factor(s.to_device([x]))
+    b = np.random.default_rng(12).standard_normal(net.n)
+    ys = s.zeros()
+    s.solve(s.to_device([b]), ys)
+    y = ys[0].cpu().numpy()
+    berr = backward_error(net, x, b, y)
+    print(f"grid160 solve backward error {berr:.2e}, max |y| {np.abs(y).max():.2e}", flush=True)
+    # |y| stays near 1e4 here; a nearly singular G_k would give |y| near 1e12
+    assert np.abs(y).max() < 1e6 and berr <= 1e-12
+    s.close()
+
+
 def test_grid_engine_dc_matches_oracle():
     import paper_1511_04515_amd as E
     net = grid96()
