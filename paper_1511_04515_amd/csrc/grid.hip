@@ -451,17 +451,21 @@ __global__ void __launch_bounds__(BS) k_g_fwd_tri(const int *fronts, const int *
                                                   const int64_t *f_off, const int *ch_ptr, const int *ch,
                                                   const int *r_ptr, const int *rel, const int *u_off,
                                                   const double *F, double *x, int64_t ldx, double *upd,
-                                                  int64_t ldu) {
+                                                  int64_t ldu, const int64_t *inv_off, double *tmp) {
   extern __shared__ double v[];
   const int s = fronts[blockIdx.x];
-  const int f = fsz[s], p = nc[s], b = c0[s];
+  // a front with an inverted pivot block leaves the triangle to k_g_trmv:
+  // its assembled v goes to tmp instead
+  const bool inv = inv_off[s] >= 0;
+  const int f = fsz[s], p = inv ? 0 : nc[s], pv = nc[s], b = c0[s];
+  double *xo = inv ? tmp : x;
   const double *A = F + f_off[s];
   const int t = threadIdx.x;
   double col[kNB];  // wave 0: row t of the current diagonal block
   if (t < 64 && p > 0) tri_block_row(col, A, f, 0, min(kNB, p), t);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    for (int i = t; i < f; i += BS) v[r * f + i] = i < p ? x[r * ldx + b + i] : 0.0;
+    for (int i = t; i < f; i += BS) v[r * f + i] = i < pv ? x[r * ldx + b + i] : 0.0;
   __syncthreads();
   for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
     const int c = ch[q], rc = fsz[c] - nc[c];
@@ -536,8 +540,8 @@ __global__ void __launch_bounds__(BS) k_g_fwd_tri(const int *fronts, const int *
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     for (int i = t; i < f; i += BS) {
-      if (i < p) x[r * ldx + b + i] = v[r * f + i];
-      else upd[r * ldu + u_off[s] + i - p] = v[r * f + i];
+      if (i < pv) xo[r * ldx + b + i] = v[r * f + i];
+      else upd[r * ldu + u_off[s] + i - pv] = v[r * f + i];
     }
 }
 
@@ -721,9 +725,11 @@ __global__ void __launch_bounds__(256) k_g_bwd_gemv(const int *items, const int 
 // Dynamic LDS: NR nc doubles.
 template <int NR, int BS>
 __global__ void __launch_bounds__(BS) k_g_bwd_tri(const int *fronts, const int *c0, const int *nc, const int *fsz,
-                                                  const int64_t *f_off, const double *F, double *x, int64_t ldx) {
+                                                  const int64_t *f_off, const double *F, double *x, int64_t ldx,
+                                                  const int64_t *inv_off) {
   extern __shared__ double v[];
   const int s = fronts[blockIdx.x];
+  if (inv_off[s] >= 0) return;  // the inverted pivot block is applied by k_g_trmv
   const int f = fsz[s], p = nc[s], b = c0[s];
   const double *A = F + f_off[s];
   const int t = threadIdx.x;
@@ -796,6 +802,179 @@ __global__ void __launch_bounds__(BS) k_g_bwd_tri(const int *fronts, const int *
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     for (int i = t; i < p; i += BS) x[r * ldx + b + i] = v[r * p + i];
+}
+
+// Inverses of the pivot blocks of the fronts with many pivots, once per
+// factorisation.  Item (s, 2 cb + u): column block cb (32 columns) of
+// L11^{-1} (u = 0; unit lower, its strictly lower part stored) or of U11^{-1}
+// (u = 1; upper, stored with the diagonal), into Finv + inv_off[s] (p x p,
+// column-major; the two inverses share the array as L and U share the
+// front).  Left-looking over 32-row blocks r in the order the recurrence
+// needs them: X_r = A_rr^{-1} (delta_r,cb I - sum_k A_rk X_k), k running over
+// the finished blocks between cb and r, two blocks per step on FP64 MFMA;
+// the next pair of tiles is loaded while the current one is multiplied.
+__global__ void __launch_bounds__(256) k_g_inv(const int *items, const int *nc, const int *fsz,
+                                               const int64_t *f_off, const int64_t *inv_off, const double *F,
+                                               double *Finv) {
+  __shared__ double As[32][65], Xs[64][33];
+  const int s = items[2 * blockIdx.x], code = items[2 * blockIdx.x + 1];
+  const int cb = code >> 1;
+  const bool upper = (code & 1) != 0;
+  const int f = fsz[s], p = nc[s], R = (p + 31) / 32, j0 = cb * 32;
+  const double *A = F + f_off[s];
+  double *X = Finv + inv_off[s];
+  const int t = threadIdx.x;
+  // the 32 x 32 block T is four 16 x 16 FP64 MFMA quadrants, one per wave
+  // (lane layout as in k_g_update)
+  const int lane = t & 63, wave = t >> 6, lr = lane & 15, lq = lane >> 4;
+  const int wi = (wave >> 1) * 16, wj = (wave & 1) * 16;
+  // tiles A(r-block, columns k*32 .. k*32 + 63) and X(rows k*32 .. k*32 + 63,
+  // cb-block), columns / rows past block kmax zero
+  auto load = [&](int r, int k, int kmax, double (&an)[8], double (&xn)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      {
+        const int a = e & 31, c = e >> 5;
+        const int ra = r * 32 + a, ca = k * 32 + c;
+        const double av = A[min(ra, p - 1) + (int64_t)min(ca, p - 1) * f];
+        an[q] = (ra < p && ca < p && ca < (kmax + 1) * 32) ? av : 0.0;
+      }
+      {
+        const int a = e & 63, c = e >> 6;
+        const int rx = k * 32 + a, cx = j0 + c;
+        const double xv = X[min(rx, p - 1) + (int64_t)min(cx, p - 1) * p];
+        // entries outside this inverse's triangle are its known zeros (and
+        // the unit diagonal of L^{-1}); the array holds the other inverse there
+        const bool mine = upper ? rx <= cx : rx > cx;
+        xn[q] = (rx < p && cx < p && rx < (kmax + 1) * 32) ? (mine ? xv : (!upper && rx == cx ? 1.0 : 0.0)) : 0.0;
+      }
+    }
+  };
+  for (int st = 0; st < R; ++st) {
+    const int r = upper ? cb - st : cb + st;
+    if (r < 0 || r >= R) break;
+    dbl4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = (r == cb && wi + lq + 4 * v == wj + lr) ? 1.0 : 0.0;
+    const int k_lo = upper ? r + 1 : cb, k_hi = upper ? cb : r - 1;
+    double an[8], xn[8];
+    if (k_lo <= k_hi) load(r, k_lo, k_hi, an, xn);
+    for (int k = k_lo; k <= k_hi; k += 2) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = t + 256 * q;
+        As[e & 31][e >> 5] = an[q];
+        Xs[e & 63][e >> 6] = xn[q];
+      }
+      __syncthreads();
+      if (k + 2 <= k_hi) load(r, k + 2, k_hi, an, xn);
+#pragma unroll
+      for (int l = 0; l < 64; l += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-As[wi + lr][l + lq], Xs[l + lq][wj + lr], acc, 0, 0, 0);
+      __syncthreads();
+    }
+    // X_r = A_rr^{-1} T: T through Xs, A_rr (identity past p) through As;
+    // thread j < 32 substitutes column j
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xs[wi + lq + 4 * v][wj + lr] = acc[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, a = e & 31, c = e >> 5;
+      const int ra = r * 32 + a, ca = r * 32 + c;
+      const double av = A[min(ra, p - 1) + (int64_t)min(ca, p - 1) * f];
+      As[a][c] = (ra < p && ca < p) ? av : (a == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (t < 32) {
+      const int j = t;
+      double xc[32];
+#pragma unroll
+      for (int a = 0; a < 32; ++a) xc[a] = Xs[a][j];
+      if (!upper) {
+#pragma unroll
+        for (int a = 1; a < 32; ++a) {
+          double v = xc[a];
+#pragma unroll
+          for (int l = 0; l < a; ++l) v -= As[a][l] * xc[l];
+          xc[a] = v;
+        }
+      } else {
+#pragma unroll
+        for (int a = 31; a >= 0; --a) {
+          double v = xc[a];
+#pragma unroll
+          for (int l = a + 1; l < 32; ++l) v -= As[a][l] * xc[l];
+          xc[a] = v / As[a][a];
+        }
+      }
+      const int col = j0 + j;
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+        const int row = r * 32 + a;
+        if (row < p && col < p && (upper ? row <= col : row > col)) X[row + (int64_t)col * p] = xc[a];
+      }
+    }
+    __syncthreads();  // this block's X is read by the later row blocks
+  }
+}
+
+// y = X v on the pivot rows of a front with an inverted pivot block: item
+// (s, chunk of 64 rows); X = L11^{-1} (UPPER false: unit lower, y = v + the
+// strictly lower part times v) or U11^{-1} (UPPER true).  v is read from `in`
+// (vector r at + r ldx), the chunk's rows written to `out`.  Each of the eight
+// waves sums an eighth of the columns that reach the chunk (many loads in
+// flight per compute unit); the eighths are added in order.  Dynamic LDS:
+// NR p doubles.
+template <int NR, bool UPPER>
+__global__ void __launch_bounds__(512) k_g_trmv(const int *items, const int *c0, const int *nc,
+                                                const int64_t *inv_off, const double *Finv, const double *in,
+                                                double *out, int64_t ldx) {
+  extern __shared__ double vs[];
+  __shared__ double red[NR][8][64];
+  const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
+  const int p = nc[s], b = c0[s];
+  const double *X = Finv + inv_off[s];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    for (int j = t; j < p; j += 512) vs[r * p + j] = in[r * ldx + b + j];
+  __syncthreads();
+  const int i = chunk * 64 + lane, ri = min(i, p - 1);
+  const int jlo = UPPER ? chunk * 64 : 0, jhi = UPPER ? p : min(p, chunk * 64 + 64);
+  const int q = (jhi - jlo + 7) / 8, j0 = jlo + w * q, j1 = min(jhi, j0 + q);
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+#pragma unroll 16
+  for (int j = j0; j < j1; ++j) {
+    const double xv = X[ri + (int64_t)j * p];
+    const bool nz = UPPER ? j >= ri : j < ri;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] += nz ? xv * vs[r * p + j] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r][w][lane] = acc[r];
+  __syncthreads();
+  if (w == 0 && i < p) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double y = ((red[r][0][lane] + red[r][1][lane]) + (red[r][2][lane] + red[r][3][lane])) +
+                 ((red[r][4][lane] + red[r][5][lane]) + (red[r][6][lane] + red[r][7][lane]));
+      if (!UPPER) y += vs[r * p + i];
+      out[r * ldx + b + i] = y;
+    }
+  }
+}
+
+// the pivot rows of the fronts with inverted pivot blocks, src -> dst (the
+// k_g_trmv items; vector r at + r ldx)
+template <int NR>
+__global__ void __launch_bounds__(256) k_g_copy_rows(const int *items, const int *c0, const int *nc,
+                                                     const double *src, double *dst, int64_t ldx) {
+  const int s = items[2 * blockIdx.x], chunk = items[2 * blockIdx.x + 1];
+  const int i = chunk * 64 + (threadIdx.x & 63), r = threadIdx.x >> 6;
+  if (r < NR && i < nc[s]) dst[r * ldx + c0[s] + i] = src[r * ldx + c0[s] + i];
 }
 
 // PWL sources: u(t) and the slope on the piece holding tm
@@ -1119,10 +1298,12 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
-                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, int tri_bs, hipStream_t s) {
+                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, int tri_bs, int n_trmv,
+                 const int *trmv, int max_p_inv, const int64_t *inv_off, const double *Finv, double *tmp,
+                 hipStream_t s) {
 #define G_FWD_TRI(NR, BS)                                                                                           \
   hipLaunchKernelGGL((k_g_fwd_tri<NR, BS>), dim3(n_big), dim3(BS), sizeof(double) * NR * (size_t)max_f, s, big, c0,  \
-                     nc, fsz, f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu);
+                     nc, fsz, f_off, ch_ptr, ch, r_ptr, rel, u_off, F, x, ldx, upd, ldu, inv_off, tmp);
 #define G_FWD(NR)                                                                                                   \
   if (n_small > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_fwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
@@ -1134,6 +1315,9 @@ hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n
       G_FWD_TRI(NR, 256)                                                                                            \
     }                                                                                                               \
   }                                                                                                                 \
+  if (n_trmv > 0)                                                                                                   \
+    hipLaunchKernelGGL((k_g_trmv<NR, false>), dim3(n_trmv), dim3(512), sizeof(double) * NR * (size_t)max_p_inv, s,  \
+                       trmv, c0, nc, inv_off, Finv, tmp, x, ldx);                                                   \
   if (n_items > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_fwd_gemv<NR>, dim3(n_items), dim3(256), sizeof(double) * NR * (size_t)max_nc, s, items,  \
                        c0, nc, fsz, f_off, u_off, F, x, ldx, upd, ldu);
@@ -1149,10 +1333,11 @@ hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n
 hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, int tri_bs,
-                 hipStream_t s) {
+                 int n_trmv, const int *trmv, int max_p_inv, const int64_t *inv_off, const double *Finv,
+                 double *tmp, hipStream_t s) {
 #define G_BWD_TRI(NR, BS)                                                                                           \
   hipLaunchKernelGGL((k_g_bwd_tri<NR, BS>), dim3(n_big), dim3(BS), sizeof(double) * NR * (size_t)max_nc, s, big, c0, \
-                     nc, fsz, f_off, F, x, ldx);
+                     nc, fsz, f_off, F, x, ldx, inv_off);
 #define G_BWD(NR)                                                                                                   \
   if (n_small > 0)                                                                                                  \
     hipLaunchKernelGGL(k_g_bwd_small<NR>, dim3((n_small + 3) / 4), dim3(256), 0, s, small, n_small, c0, nc, fsz,    \
@@ -1166,6 +1351,11 @@ hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n
     } else {                                                                                                        \
       G_BWD_TRI(NR, 256)                                                                                            \
     }                                                                                                               \
+  }                                                                                                                 \
+  if (n_trmv > 0) {                                                                                                 \
+    hipLaunchKernelGGL((k_g_trmv<NR, true>), dim3(n_trmv), dim3(512), sizeof(double) * NR * (size_t)max_p_inv, s,   \
+                       trmv, c0, nc, inv_off, Finv, x, tmp, ldx);                                                   \
+    hipLaunchKernelGGL(k_g_copy_rows<NR>, dim3(n_trmv), dim3(256), 0, s, trmv, c0, nc, tmp, x, ldx);               \
   }
   if (nr == 2) {
     G_BWD(2)
@@ -1174,6 +1364,12 @@ hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n
   }
 #undef G_BWD
 #undef G_BWD_TRI
+  return hipGetLastError();
+}
+hipError_t g_inv(int n_items, const int *items, const int *nc, const int *fsz, const int64_t *f_off,
+                 const int64_t *inv_off, const double *F, double *Finv, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_g_inv, dim3(n_items), dim3(256), 0, s, items, nc, fsz, f_off, inv_off, F, Finv);
   return hipGetLastError();
 }
 hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,

@@ -34,11 +34,16 @@ hipError_t g_update(int n_items, const int *items, int k0, const int *c0, const 
 hipError_t g_fwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *ch_ptr, const int *ch, const int *r_ptr, const int *rel, const int *u_off, const double *F,
-                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, int tri_bs, hipStream_t s);
+                 double *x, int nr, int64_t ldx, double *upd, int64_t ldu, int tri_bs, int n_trmv,
+                 const int *trmv, int max_p_inv, const int64_t *inv_off, const double *Finv, double *tmp,
+                 hipStream_t s);
 hipError_t g_bwd(int n_small, const int *small, int n_big, const int *big, int n_items, const int *items,
                  int max_f, int max_nc, const int *c0, const int *nc, const int *fsz, const int64_t *f_off,
                  const int *r_ptr, const int *r_idx, const double *F, double *x, int nr, int64_t ldx, int tri_bs,
-                 hipStream_t s);
+                 int n_trmv, const int *trmv, int max_p_inv, const int64_t *inv_off, const double *Finv,
+                 double *tmp, hipStream_t s);
+hipError_t g_inv(int n_items, const int *items, const int *nc, const int *fsz, const int64_t *f_off,
+                 const int64_t *inv_off, const double *F, double *Finv, hipStream_t s);
 hipError_t g_sources(int n_src, const int *src_ptr, const double *src_t, const double *src_v, double t, double tm,
                      double *u, double *slope, hipStream_t s);
 hipError_t g_rhs(int n, const int *g_rowptr, const int *g_col, const double *g_val, const int *b_rowptr,
@@ -73,6 +78,7 @@ constexpr int kSOK = 0, kSEINVAL = -1, kSENOMEM = -2, kSESINGULAR = -3, kSEKRYLO
 constexpr int kRBlocks = 512;  // blocks of the two-pass reductions (grid.hip)
 constexpr int kSc = 2 * kHLd + 8;  // offset of the basis scalars in the hess_phi1 output area
 constexpr int kFuse = 64;          // trailing blocks up to this size are updated by the panel kernel
+constexpr int kInvPivots = 288;    // pivot blocks with more pivots are inverted after each factorisation
 }  // namespace
 
 #define GCHK(call)                                  \
@@ -211,6 +217,17 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
   // trailing-update tiles of each 32-wide pivot step
   const int H = (int)fs.lev_ptr.size() - 1;
   levels.resize(H);
+  // fronts whose pivot blocks are inverted: the few large ones near the root,
+  // whose one-workgroup triangular solves would otherwise set the solve time
+  auto inverted = [&](int s_) { return fs.fsz[s_] > 64 && fs.nc[s_] > kInvPivots; };
+  std::vector<int64_t> inv_off(fs.nc.size(), -1);
+  int64_t inv_doubles = 0;
+  for (size_t s_ = 0; s_ < fs.nc.size(); ++s_)
+    if (inverted((int)s_)) {
+      inv_off[s_] = inv_doubles;
+      inv_doubles += ((int64_t)fs.nc[s_] * fs.nc[s_] + 31) / 32 * 32;
+      max_p_inv = std::max(max_p_inv, fs.nc[s_]);
+    }
   std::vector<int32_t> pool;
   std::vector<std::pair<size_t, int32_t **>> fix;
   for (int h = 0; h < H; ++h) {
@@ -328,6 +345,19 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       L.n_lu64 = (int32_t)(pool.size() - at64);
       fix.push_back({at64, nullptr});
     }
+    {
+      const size_t at_i = pool.size();
+      for (int q = L.first; q < L.first + L.count; ++q) {
+        const int s_ = fs.lev_front[q];
+        if (!inverted(s_)) continue;
+        for (int c = 0; c < (fs.nc[s_] + 63) / 64; ++c) {
+          pool.push_back(s_);
+          pool.push_back(c);
+        }
+      }
+      L.n_trmv = (int32_t)((pool.size() - at_i) / 2);
+      fix.push_back({at_i, nullptr});
+    }
     // fronts whose trailing update of the previous step ran as tiles: tile
     // (0, 0) of that update has factored this step's diagonal block
     std::vector<char> tiled(fs.nc.size(), 0);
@@ -382,8 +412,28 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       fix.push_back({at_t, nullptr});
     }
   }
+  // inversion items (front, 2 column block + which), the largest fronts first
+  const size_t at_inv = pool.size();
+  {
+    std::vector<int32_t> inv_fronts;
+    for (size_t s_ = 0; s_ < fs.nc.size(); ++s_)
+      if (inv_off[s_] >= 0) inv_fronts.push_back((int32_t)s_);
+    std::stable_sort(inv_fronts.begin(), inv_fronts.end(),
+                     [&](int32_t a_, int32_t b_) { return fs.nc[a_] > fs.nc[b_]; });
+    for (int32_t s_ : inv_fronts)
+      for (int cb = 0; cb < (fs.nc[s_] + 31) / 32; ++cb)
+        for (int u = 0; u < 2; ++u) {
+          pool.push_back(s_);
+          // the lower inverse's first column blocks and the upper's last ones
+          // carry the longest recurrences: they go first
+          pool.push_back(2 * (u == 0 ? cb : (fs.nc[s_] + 31) / 32 - 1 - cb) + u);
+        }
+    n_inv_items = (int32_t)((pool.size() - at_inv) / 2);
+  }
   int32_t *d_pool = up32(pool);
+  d_inv_off = up64(inv_off);
   if (!ok) return fail(kSENOMEM, "device allocation or upload failed (symbolic data)");
+  d_inv_items = d_pool + at_inv;
   {
     size_t f = 0;
     for (int h = 0; h < H; ++h) {
@@ -395,6 +445,7 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
       levels[h].bwd = d_pool + fix[f++].first;
       levels[h].lu32 = d_pool + fix[f++].first;
       levels[h].lu64 = d_pool + fix[f++].first;
+      levels[h].trmv = d_pool + fix[f++].first;
       for (auto &S : levels[h].steps) {
         S.diag = d_pool + fix[f++].first;
         S.panel = d_pool + fix[f++].first;
@@ -407,6 +458,8 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
   const int cols = o.m_max + 1;
   d_F = dalloc<double>(fs.front_doubles);
   d_upd = dalloc<double>(2 * fs.upd_doubles);  // update vectors of up to two right-hand sides
+  d_Finv = dalloc<double>(std::max<int64_t>(inv_doubles, 1));
+  d_tmp = dalloc<double>(2 * (size_t)n);        // pivot rows of inverted fronts, two right-hand sides
   d_rowmax = dalloc<unsigned long long>(n);
   d_bad = dalloc<int32_t>(1);
   // w and p side by side: they are solved together
@@ -427,7 +480,7 @@ int GridEngine::setup(const PatternInput &pin, const GridValues &val, const int3
   d_red = dalloc<double>(8);
   d_feat = dalloc<float>(kFeat);
   d_cout = dalloc<float>(2);
-  if (!d_feat || !d_cout || !d_F || !d_upd || !d_rowmax || !d_bad || !d_xk || !d_x1 || !d_w || !d_p || !d_z || !d_r || !d_bs || !d_e ||
+  if (!d_feat || !d_cout || !d_F || !d_upd || !d_Finv || !d_tmp || !d_rowmax || !d_bad || !d_xk || !d_x1 || !d_w || !d_p || !d_z || !d_r || !d_bs || !d_e ||
       !d_y || !d_u || !d_sl || !d_devI0 || !d_devI1 || !d_devD || !d_devD1 || !d_V || !d_Ve || !d_H || !d_He || !d_mat ||
       !d_part || !d_h1 || !d_h2 || !d_out || !d_oute || !d_red)
     return fail(kSENOMEM, "device allocation failed (workspace)");
@@ -466,6 +519,7 @@ int GridEngine::factor_internal(const double *x) {
       GCHK(g_update(S.n_tiles, S.tiles, S.k0, d_c0, d_nc, d_fsz, d_f_off, d_rowmax, o.piv_tol, d_F, d_bad, stream));
     }
   }
+  GCHK(g_inv(n_inv_items, d_inv_items, d_nc, d_fsz, d_f_off, d_inv_off, d_F, d_Finv, stream));
   int32_t bad = 0;
   GCHK(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   GCHK(hipStreamSynchronize(stream));
@@ -485,11 +539,12 @@ int GridEngine::solve_internal(double *b, int nr) {
   for (const Level &L : levels)
     GCHK(g_fwd(L.n_small, L.small, L.n_big, L.big, L.n_fwd, L.fwd, fs.max_front, fs.max_nc, d_c0, d_nc, d_fsz,
                d_f_off, d_ch_ptr, d_ch, d_r_ptr, d_rel, d_u_off, d_F, b, nr, fs.n, d_upd, fs.upd_doubles,
-               L.tri_bs(), stream));
+               L.tri_bs(), L.n_trmv, L.trmv, max_p_inv, d_inv_off, d_Finv, d_tmp, stream));
   for (int h = (int)levels.size() - 1; h >= 0; --h) {
     const Level &L = levels[h];
     GCHK(g_bwd(L.n_small, L.small, L.n_big, L.big, L.n_bwd, L.bwd, fs.max_front, fs.max_nc, d_c0, d_nc, d_fsz,
-               d_f_off, d_r_ptr, d_r_idx, d_F, b, nr, fs.n, L.tri_bs(), stream));
+               d_f_off, d_r_ptr, d_r_idx, d_F, b, nr, fs.n, L.tri_bs(), L.n_trmv, L.trmv, max_p_inv, d_inv_off,
+               d_Finv, d_tmp, stream));
   }
   return kSOK;
 }

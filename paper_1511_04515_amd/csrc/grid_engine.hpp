@@ -81,6 +81,8 @@ struct GridEngine {
     int32_t *fwd = nullptr, *bwd = nullptr;
     int32_t n_lu32 = 0, n_lu64 = 0;  // fronts factored whole by one wave (f <= 32, f <= 64)
     int32_t *lu32 = nullptr, *lu64 = nullptr;
+    int32_t n_trmv = 0;        // (front, 64-row chunk) of the fronts with inverted pivot blocks
+    int32_t *trmv = nullptr;
     std::vector<Step> steps;
   };
   std::vector<Level> levels;
@@ -89,6 +91,13 @@ struct GridEngine {
   double *d_src_t = nullptr, *d_src_v = nullptr;
   // numeric
   double *d_F = nullptr, *d_upd = nullptr;
+  // pivot blocks with more than kInvPivots pivots are inverted after each
+  // factorisation (L11^{-1} and U11^{-1} in one p x p array per front), and
+  // their triangular solves become grid-wide products
+  int64_t *d_inv_off = nullptr;  // per front: offset into d_Finv, -1 if not inverted
+  double *d_Finv = nullptr, *d_tmp = nullptr;
+  int32_t n_inv_items = 0, max_p_inv = 0;
+  int32_t *d_inv_items = nullptr;
   unsigned long long *d_rowmax = nullptr;
   int32_t *d_bad = nullptr;
   double *d_xk = nullptr, *d_x1 = nullptr, *d_w = nullptr, *d_p = nullptr, *d_z = nullptr, *d_r = nullptr;
