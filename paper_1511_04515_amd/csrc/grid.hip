@@ -886,33 +886,34 @@ __global__ void __launch_bounds__(256) k_g_inv(const int *items, const int *nc, 
       As[a][c] = (ra < p && ca < p) ? av : (a == c ? 1.0 : 0.0);
     }
     __syncthreads();
-    if (t < 32) {
-      const int j = t;
-      double xc[32];
+    {
+      // eight groups of 32 lanes, each substituting columns cg, cg + 8, ...:
+      // lane a of a group holds row a of A_rr and x_a; x_l reaches the other
+      // lanes of its half-wave by readlane
+      const int a = lane & 31, cg = t >> 5, hb = lane & 32;
+      double arow[32];
 #pragma unroll
-      for (int a = 0; a < 32; ++a) xc[a] = Xs[a][j];
-      if (!upper) {
+      for (int l = 0; l < 32; ++l) arow[l] = As[a][l];
+#pragma unroll 1
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = cg + 8 * jj;
+        double xv = Xs[a][j];
+        if (!upper) {
 #pragma unroll
-        for (int a = 1; a < 32; ++a) {
-          double v = xc[a];
+          for (int l = 0; l < 32; ++l) {
+            const double z0 = readlane_d(xv, l), z1 = readlane_d(xv, 32 + l);
+            if (a > l) xv -= arow[l] * (hb ? z1 : z0);
+          }
+        } else {
 #pragma unroll
-          for (int l = 0; l < a; ++l) v -= As[a][l] * xc[l];
-          xc[a] = v;
+          for (int l = 31; l >= 0; --l) {
+            if (a == l) xv = xv / arow[l];
+            const double z0 = readlane_d(xv, l), z1 = readlane_d(xv, 32 + l);
+            if (a < l) xv -= arow[l] * (hb ? z1 : z0);
+          }
         }
-      } else {
-#pragma unroll
-        for (int a = 31; a >= 0; --a) {
-          double v = xc[a];
-#pragma unroll
-          for (int l = a + 1; l < 32; ++l) v -= As[a][l] * xc[l];
-          xc[a] = v / As[a][a];
-        }
-      }
-      const int col = j0 + j;
-#pragma unroll
-      for (int a = 0; a < 32; ++a) {
-        const int row = r * 32 + a;
-        if (row < p && col < p && (upper ? row <= col : row > col)) X[row + (int64_t)col * p] = xc[a];
+        const int row = r * 32 + a, col = j0 + j;
+        if (row < p && col < p && (upper ? row <= col : row > col)) X[row + (int64_t)col * p] = xv;
       }
     }
     __syncthreads();  // this block's X is read by the later row blocks
